@@ -1,0 +1,235 @@
+"""FP64 CPU oracle of the multi-frame EM iteration -- TEST INFRASTRUCTURE ONLY.
+
+This package is the independent reference that the GPU path is checked against.
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import it.  It shares no code with ``paper_2302_05804_amd``.
+
+The arithmetic lives in ``em_oracle.c`` (plain C, double precision, one
+thread, ``-O2`` without fast-math); this module compiles it with gcc and wraps
+it with ctypes.  What it computes (Sukurdeep, Navarro & Budavari,
+arXiv:2302.05804, Sec. 2):
+
+* ``forward``  -- F_t x = D(f_t * x), Eq. (1) (sr=1) and Eq. (3) (sr=2);
+* ``adjoint``  -- F_t^T r = f_t (correlate) D^T r, the transpose used in Eq. (2);
+* ``numerator`` / ``denominator`` -- the two frame sums of Eq. (2);
+* ``loglik``   -- the Gaussian log-likelihood implied by Eq. (1);
+* ``run``      -- k iterations of the multiplicative update of Eq. (2);
+* ``step_at``  -- one iteration evaluated only at chosen latent pixels;
+* ``flat_x0``  -- the flat strictly-positive starting guess.
+
+The readings taken where the paper is silent (weight placement, clamp of a
+negative numerator, 0/0 guards, boundary, downsampling kernel) are listed in
+the header comment of ``em_oracle.c``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "em_oracle.c")
+_LIB = os.path.join(_HERE, "libem_oracle.so")
+_lib = None
+
+W_ADJOINT = 0
+W_LITERAL = 1
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (single-threaded, -O2, no fast-math)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(
+            ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fno-fast-math", "-Wall",
+             "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build(force=True)
+    lib = ctypes.CDLL(_LIB)
+    P = ctypes.c_void_p
+    I = ctypes.c_int
+    lib.em_oracle_forward_at.restype = ctypes.c_double
+    lib.em_oracle_forward_at.argtypes = [I, I, I, I, P, P, I, I]
+    lib.em_oracle_adjoint_at.restype = ctypes.c_double
+    lib.em_oracle_adjoint_at.argtypes = [I, I, I, I, P, P, I, I]
+    lib.em_oracle_forward.restype = None
+    lib.em_oracle_forward.argtypes = [I, I, I, I, P, P, P]
+    lib.em_oracle_adjoint.restype = None
+    lib.em_oracle_adjoint.argtypes = [I, I, I, I, P, P, P]
+    lib.em_oracle_weights.restype = ctypes.c_long
+    lib.em_oracle_weights.argtypes = [ctypes.c_long, P, P, P, P]
+    lib.em_oracle_flat_x0.restype = ctypes.c_double
+    lib.em_oracle_flat_x0.argtypes = [I, I, I, I, P, P]
+    lib.em_oracle_numerator.restype = I
+    lib.em_oracle_numerator.argtypes = [I, I, I, I, I, I, P, P, P, P]
+    lib.em_oracle_denominator.restype = I
+    lib.em_oracle_denominator.argtypes = [I, I, I, I, I, I, P, P, P, P, P]
+    lib.em_oracle_loglik.restype = I
+    lib.em_oracle_loglik.argtypes = [I, I, I, I, I, P, P, P, P, P]
+    lib.em_oracle_run.restype = I
+    lib.em_oracle_run.argtypes = [I, I, I, I, I, I, P, P, P, P, I, P, P]
+    lib.em_oracle_step_at.restype = I
+    lib.em_oracle_step_at.argtypes = [I, I, I, I, I, P, P, P, P, I, P, P, P, P, P]
+    _lib = lib
+    return lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f32(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def _shape(y, psf, sr):
+    y = np.asarray(y)
+    if y.ndim != 3:
+        raise ValueError("y must be n x Hf x Wf")
+    n, hf, wf = y.shape
+    psf = np.asarray(psf)
+    if psf.ndim != 3 or psf.shape[0] != n or psf.shape[1] != psf.shape[2] or psf.shape[1] % 2 == 0:
+        raise ValueError("psf must be n x K x K with odd K")
+    if sr not in (1, 2):
+        raise ValueError("sr must be 1 or 2")
+    return n, hf, wf, psf.shape[1]
+
+
+def forward(f, x, sr: int = 1) -> np.ndarray:
+    """F x = D(f * x) for one PSF f (K x K, odd) and latent image x (Hl x Wl)."""
+    lib = _load()
+    f = _f64(f)
+    x = _f64(x)
+    K = f.shape[0]
+    hl, wl = x.shape
+    if hl % sr or wl % sr:
+        raise ValueError("latent size must be a multiple of sr")
+    m = np.empty((hl // sr, wl // sr), np.float64)
+    lib.em_oracle_forward(K, sr, hl, wl, _p(f), _p(x), _p(m))
+    return m
+
+
+def adjoint(f, r, sr: int = 1) -> np.ndarray:
+    """F^T r = f (correlate) D^T r for frame-grid r (Hf x Wf); output Hl x Wl."""
+    lib = _load()
+    f = _f64(f)
+    r = _f64(r)
+    K = f.shape[0]
+    hf, wf = r.shape
+    s = np.empty((hf * sr, wf * sr), np.float64)
+    lib.em_oracle_adjoint(K, sr, hf * sr, wf * sr, _p(f), _p(r), _p(s))
+    return s
+
+
+def weights(y, v):
+    """(u, yhat, n_invalid): u = 1/v, 0 where v=+inf; yhat = y, 0 where masked."""
+    lib = _load()
+    y = _f32(y)
+    v = _f32(v)
+    u = np.empty(y.shape, np.float64)
+    yh = np.empty(y.shape, np.float64)
+    bad = lib.em_oracle_weights(y.size, _p(y), _p(v), _p(u), _p(yh))
+    return u, yh, int(bad)
+
+
+def flat_x0(y, v, sr: int = 1) -> float:
+    lib = _load()
+    y = _f32(y)
+    v = _f32(v)
+    n, hf, wf = y.shape
+    val = lib.em_oracle_flat_x0(n, hf, wf, sr, _p(y), _p(v))
+    if val < 0:
+        raise ValueError("invalid inputs")
+    return float(val)
+
+
+def numerator(y, v, psf, sr: int = 1, mode: int = W_ADJOINT) -> np.ndarray:
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf = _f32(y), _f32(v), _f32(psf)
+    B = np.empty((hf * sr, wf * sr), np.float64)
+    rc = lib.em_oracle_numerator(n, hf, wf, K, sr, mode, _p(y), _p(v), _p(psf), _p(B))
+    if rc:
+        raise ValueError(f"oracle numerator failed ({rc})")
+    return B
+
+
+def denominator(y, v, psf, x, sr: int = 1, mode: int = W_ADJOINT) -> np.ndarray:
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf, x = _f32(y), _f32(v), _f32(psf), _f64(x)
+    Dn = np.empty((hf * sr, wf * sr), np.float64)
+    rc = lib.em_oracle_denominator(n, hf, wf, K, sr, mode, _p(y), _p(v), _p(psf), _p(x), _p(Dn))
+    if rc:
+        raise ValueError(f"oracle denominator failed ({rc})")
+    return Dn
+
+
+def loglik(y, v, psf, x, sr: int = 1) -> float:
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf, x = _f32(y), _f32(v), _f32(psf), _f64(x)
+    out = np.zeros(1, np.float64)
+    rc = lib.em_oracle_loglik(n, hf, wf, K, sr, _p(y), _p(v), _p(psf), _p(x), _p(out))
+    if rc:
+        raise ValueError(f"oracle loglik failed ({rc})")
+    return float(out[0])
+
+
+def run(y, v, psf, x0, n_iter: int, sr: int = 1, mode: int = W_ADJOINT,
+        trace: bool = False, relchange: bool = False):
+    """n_iter EM iterations of Eq. (2) from x0.
+
+    Returns x (float64) or (x, trace, relchange) when either is requested;
+    trace[k-1] = l(x^(k-1)), relchange[k-1] = ||x^k - x^(k-1)|| / ||x^(k-1)||.
+    """
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf = _f32(y), _f32(v), _f32(psf)
+    x = np.array(x0, dtype=np.float64, copy=True, order="C")
+    if x.shape != (hf * sr, wf * sr):
+        raise ValueError("x0 must be the latent grid")
+    tr = np.zeros(max(n_iter, 1), np.float64)
+    rc_ = np.zeros(max(n_iter, 1), np.float64)
+    rc = lib.em_oracle_run(n, hf, wf, K, sr, mode, _p(y), _p(v), _p(psf), _p(x), int(n_iter),
+                           _p(tr), _p(rc_))
+    if rc:
+        raise ValueError(f"oracle run failed ({rc})")
+    if trace or relchange:
+        return x, tr[:n_iter], rc_[:n_iter]
+    return x
+
+
+def step_at(y, v, psf, x0, rows, cols, sr: int = 1):
+    """One iteration evaluated only at latent pixels (rows[i], cols[i]).
+
+    Returns (B, Dn, x1) at those pixels, computed from x0 (float32 latent grid).
+    """
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf, x0 = _f32(y), _f32(v), _f32(psf), _f32(x0)
+    rows = np.ascontiguousarray(rows, dtype=np.int32)
+    cols = np.ascontiguousarray(cols, dtype=np.int32)
+    npts = rows.size
+    B = np.empty(npts, np.float64)
+    Dn = np.empty(npts, np.float64)
+    x1 = np.empty(npts, np.float64)
+    rc = lib.em_oracle_step_at(n, hf, wf, K, sr, _p(y), _p(v), _p(psf), _p(x0), npts,
+                               _p(rows), _p(cols), _p(B), _p(Dn), _p(x1))
+    if rc:
+        raise ValueError(f"oracle step_at failed ({rc})")
+    return B, Dn, x1

@@ -1,0 +1,424 @@
+/*
+ * em_oracle.c -- TEST INFRASTRUCTURE, not part of the product path.
+ *
+ * A plain, slow, single-threaded FP64 CPU reference of the multi-frame EM
+ * deconvolution / super-resolution iteration of Sukurdeep, Navarro & Budavari,
+ * "A Flexible Expectation Maximization Framework for Fast, Scalable and
+ * High-fidelity Multi-frame Astronomical Image Deconvolution" (arXiv:2302.05804),
+ * Sec. 2, Eqs. (1)-(3).  Only the test-suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no code,
+ * header, table or helper with the GPU path.
+ *
+ * Every operator is written as its textbook definition (a sum over taps, with
+ * loop bounds clipped to the image), evaluated pixel by pixel, in double.
+ * Inputs that arrive as FP32 data (exposures, variances, PSFs, an initial
+ * guess) are read as float and widened exactly to double.
+ *
+ * Readings of the paper that this file fixes (the paper is silent on them):
+ *  - F_t x = D(f_t * x): true 2-D convolution, odd K, centre c=(K-1)/2,
+ *    zero-filled outside the latent grid, output the size of the latent grid
+ *    ("same"); D = identity for sr=1, a 2x2 box SUM for sr=2 where frame pixel
+ *    I covers latent rows 2I and 2I+1 (Eq. (3)).
+ *  - u = 1/v; v = +inf marks a masked pixel, u = 0 there, and y is replaced by
+ *    0 there (it may hold NaN).
+ *  - The weights act on the frame grid before the adjoint (the
+ *    majorise-minimise step of the Gaussian likelihood of Eq. (1)):
+ *        x <- x * max(B, 0) / Dn,  B = sum_t F_t^T (u_t y_t),
+ *                                  Dn = sum_t F_t^T (u_t F_t x).
+ *    The as-typeset form of Eq. (2), u_t (F_t^T y_t) / u_t (F_t^T F_t x) with
+ *    u applied on the latent grid, is kept as weight mode 1 (sr=1 only).
+ *  - Guards: x_j = 0 stays 0; x_j > 0 with Dn_j = 0 keeps x_j; otherwise
+ *    q_j = max(B_j,0)/Dn_j is formed first and then x_j*q_j.
+ *  - Log-likelihood of Eq. (1):
+ *        l(x) = -1/2 sum_t sum_{u>0} [ u (y - F_t x)^2 + ln(2 pi v) ].
+ *  - Flat initial guess: mu = sum u y / sum u over all frames and pixels,
+ *    x0 = max(mu, 1e-3) / sr^2.
+ *  - Frames are summed in the order t = 0 .. n-1.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define EMO_PI 3.14159265358979323846
+
+static int imax(int a, int b) { return a > b ? a : b; }
+static int imin(int a, int b) { return a < b ? a : b; }
+
+/* floor division for possibly negative numerators, positive d */
+static int fdiv(int a, int d) { return (a >= 0) ? a / d : -((-a + d - 1) / d); }
+
+/* ---------------------------------------------------------------------------
+ * Weights (text following Eq. (2): u = 1/v).  Returns the number of invalid
+ * pixels: an unmasked v that is <= 0, NaN or -inf, or an unmasked y that is
+ * not finite.
+ * ------------------------------------------------------------------------- */
+long em_oracle_weights(long npix, const float* y, const float* v, double* u, double* yhat)
+{
+    long bad = 0;
+    for (long p = 0; p < npix; ++p) {
+        double vv = (double)v[p];
+        if (isinf(vv) && vv > 0) {           /* masked */
+            u[p] = 0.0;
+            yhat[p] = 0.0;
+            continue;
+        }
+        if (!(vv > 0.0) || !isfinite(vv) || !isfinite((double)y[p])) {
+            ++bad;
+            u[p] = 0.0;
+            yhat[p] = 0.0;
+            continue;
+        }
+        u[p] = 1.0 / vv;
+        yhat[p] = (double)y[p];
+    }
+    return bad;
+}
+
+/* ---------------------------------------------------------------------------
+ * Forward operator at one frame pixel (Eq. (1) for sr=1, Eq. (3) for sr=2):
+ *   (F x)[I,J] = sum_{p,q<sr} sum_{a,b} f[a,b] x[sr I + p + c - a, sr J + q + c - b]
+ * with x = 0 outside the Hl x Wl latent grid.
+ * ------------------------------------------------------------------------- */
+double em_oracle_forward_at(int K, int sr, int Hl, int Wl, const double* f, const double* x,
+                            int I, int J)
+{
+    const int c = (K - 1) / 2;
+    double acc = 0.0;
+    for (int p = 0; p < sr; ++p) {
+        for (int q = 0; q < sr; ++q) {
+            const int i = sr * I + p, j = sr * J + q;
+            /* need 0 <= i + c - a < Hl  and  0 <= a < K */
+            const int a_lo = imax(0, i + c - Hl + 1), a_hi = imin(K - 1, i + c);
+            const int b_lo = imax(0, j + c - Wl + 1), b_hi = imin(K - 1, j + c);
+            for (int a = a_lo; a <= a_hi; ++a)
+                for (int b = b_lo; b <= b_hi; ++b)
+                    acc += f[a * K + b] * x[(long)(i + c - a) * Wl + (j + c - b)];
+        }
+    }
+    return acc;
+}
+
+/* ---------------------------------------------------------------------------
+ * Adjoint at one latent pixel:  (F^T r)[k,l] = (H^T D^T r)[k,l]
+ *   (D^T r)[i,j] = r[floor(i/sr), floor(j/sr)]     (replicate)
+ *   (H^T s)[k,l] = sum_{a,b} f[a,b] s[k - c + a, l - c + b]   (correlation)
+ * with s = 0 outside the latent grid.
+ * ------------------------------------------------------------------------- */
+double em_oracle_adjoint_at(int K, int sr, int Hl, int Wl, const double* f, const double* r,
+                            int k, int l)
+{
+    const int c = (K - 1) / 2;
+    const int Wf = Wl / sr;
+    double acc = 0.0;
+    const int a_lo = imax(0, c - k), a_hi = imin(K - 1, Hl - 1 - k + c);
+    const int b_lo = imax(0, c - l), b_hi = imin(K - 1, Wl - 1 - l + c);
+    for (int a = a_lo; a <= a_hi; ++a) {
+        const int i = k - c + a;
+        for (int b = b_lo; b <= b_hi; ++b) {
+            const int j = l - c + b;
+            acc += f[a * K + b] * r[(long)fdiv(i, sr) * Wf + fdiv(j, sr)];
+        }
+    }
+    return acc;
+}
+
+void em_oracle_forward(int K, int sr, int Hl, int Wl, const double* f, const double* x, double* m)
+{
+    const int Hf = Hl / sr, Wf = Wl / sr;
+    for (int I = 0; I < Hf; ++I)
+        for (int J = 0; J < Wf; ++J)
+            m[(long)I * Wf + J] = em_oracle_forward_at(K, sr, Hl, Wl, f, x, I, J);
+}
+
+void em_oracle_adjoint(int K, int sr, int Hl, int Wl, const double* f, const double* r, double* s)
+{
+    for (int k = 0; k < Hl; ++k)
+        for (int l = 0; l < Wl; ++l)
+            s[(long)k * Wl + l] = em_oracle_adjoint_at(K, sr, Hl, Wl, f, r, k, l);
+}
+
+/* ---------------------------------------------------------------------------
+ * Whole-problem helpers.  Shapes: y, v: n x Hf x Wf; f: n x K x K (float);
+ * latent grid Hl = sr*Hf, Wl = sr*Wf.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int n, Hf, Wf, K, sr;
+    long nf, nl;           /* pixels per frame, latent pixels */
+    double* u;             /* n * nf */
+    double* yh;            /* n * nf */
+    double* f;             /* n * K * K */
+    double* m;             /* nf scratch */
+    double* r;             /* nf scratch */
+    double* s;             /* nl scratch */
+    double lconst;         /* sum_{u>0} ln(2 pi v) */
+    long bad;
+} emo_state;
+
+static void emo_free(emo_state* st)
+{
+    free(st->u); free(st->yh); free(st->f); free(st->m); free(st->r); free(st->s);
+}
+
+static int emo_setup(emo_state* st, int n, int Hf, int Wf, int K, int sr,
+                     const float* y, const float* v, const float* psf)
+{
+    memset(st, 0, sizeof(*st));
+    st->n = n; st->Hf = Hf; st->Wf = Wf; st->K = K; st->sr = sr;
+    st->nf = (long)Hf * Wf;
+    st->nl = st->nf * sr * sr;
+    st->u = (double*)malloc(sizeof(double) * n * st->nf);
+    st->yh = (double*)malloc(sizeof(double) * n * st->nf);
+    st->f = (double*)malloc(sizeof(double) * n * K * K);
+    st->m = (double*)malloc(sizeof(double) * st->nf);
+    st->r = (double*)malloc(sizeof(double) * st->nf);
+    st->s = (double*)malloc(sizeof(double) * st->nl);
+    if (!st->u || !st->yh || !st->f || !st->m || !st->r || !st->s) { emo_free(st); return -2; }
+    st->bad = em_oracle_weights((long)n * st->nf, y, v, st->u, st->yh);
+    for (long p = 0; p < (long)n * K * K; ++p) st->f[p] = (double)psf[p];
+    double lc = 0.0;
+    for (long p = 0; p < (long)n * st->nf; ++p)
+        if (st->u[p] > 0.0) lc += log(2.0 * EMO_PI * (double)v[p]);
+    st->lconst = lc;
+    return 0;
+}
+
+/* l(x) of Eq. (1), summed over unmasked pixels, frames in order. */
+static double emo_loglik(emo_state* st, const double* x)
+{
+    const int Hl = st->Hf * st->sr, Wl = st->Wf * st->sr;
+    double quad = 0.0;
+    for (int t = 0; t < st->n; ++t) {
+        const double* ft = st->f + (long)t * st->K * st->K;
+        em_oracle_forward(st->K, st->sr, Hl, Wl, ft, x, st->m);
+        const double* ut = st->u + (long)t * st->nf;
+        const double* yt = st->yh + (long)t * st->nf;
+        for (long p = 0; p < st->nf; ++p)
+            if (ut[p] > 0.0) {
+                const double d = yt[p] - st->m[p];
+                quad += ut[p] * d * d;
+            }
+    }
+    return -0.5 * (quad + st->lconst);
+}
+
+/* Numerator of Eq. (2).  mode 0: B = sum_t F_t^T (u_t y_t);
+ * mode 1 (sr=1): B = sum_t u_t (F_t^T y_t). */
+static void emo_numerator(emo_state* st, int mode, double* B)
+{
+    const int Hl = st->Hf * st->sr, Wl = st->Wf * st->sr;
+    for (long j = 0; j < st->nl; ++j) B[j] = 0.0;
+    for (int t = 0; t < st->n; ++t) {
+        const double* ft = st->f + (long)t * st->K * st->K;
+        const double* ut = st->u + (long)t * st->nf;
+        const double* yt = st->yh + (long)t * st->nf;
+        if (mode == 0) {
+            for (long p = 0; p < st->nf; ++p) st->r[p] = ut[p] * yt[p];
+            em_oracle_adjoint(st->K, st->sr, Hl, Wl, ft, st->r, st->s);
+            for (long j = 0; j < st->nl; ++j) B[j] += st->s[j];
+        } else {
+            em_oracle_adjoint(st->K, st->sr, Hl, Wl, ft, yt, st->s);
+            for (long j = 0; j < st->nl; ++j) B[j] += ut[j] * st->s[j];
+        }
+    }
+}
+
+/* Denominator of Eq. (2) at x, plus (optionally) l(x) from the same F_t x. */
+static void emo_denominator(emo_state* st, int mode, const double* x, double* Dn, double* loglik)
+{
+    const int Hl = st->Hf * st->sr, Wl = st->Wf * st->sr;
+    double quad = 0.0;
+    for (long j = 0; j < st->nl; ++j) Dn[j] = 0.0;
+    for (int t = 0; t < st->n; ++t) {
+        const double* ft = st->f + (long)t * st->K * st->K;
+        const double* ut = st->u + (long)t * st->nf;
+        const double* yt = st->yh + (long)t * st->nf;
+        em_oracle_forward(st->K, st->sr, Hl, Wl, ft, x, st->m);
+        for (long p = 0; p < st->nf; ++p)
+            if (ut[p] > 0.0) {
+                const double d = yt[p] - st->m[p];
+                quad += ut[p] * d * d;
+            }
+        if (mode == 0) {
+            for (long p = 0; p < st->nf; ++p) st->r[p] = ut[p] * st->m[p];
+            em_oracle_adjoint(st->K, st->sr, Hl, Wl, ft, st->r, st->s);
+            for (long j = 0; j < st->nl; ++j) Dn[j] += st->s[j];
+        } else {
+            em_oracle_adjoint(st->K, st->sr, Hl, Wl, ft, st->m, st->s);
+            for (long j = 0; j < st->nl; ++j) Dn[j] += ut[j] * st->s[j];
+        }
+    }
+    if (loglik) *loglik = -0.5 * (quad + st->lconst);
+}
+
+/* Multiplicative update of Eq. (2) with the non-negativity clamp and guards. */
+static void emo_update(long nl, const double* B, const double* Dn, double* x,
+                       double* dsq, double* xsq)
+{
+    double a = 0.0, b = 0.0;
+    for (long j = 0; j < nl; ++j) {
+        const double xo = x[j];
+        double xn;
+        if (xo == 0.0) {
+            xn = 0.0;
+        } else if (Dn[j] == 0.0) {
+            xn = xo;
+        } else {
+            const double q = (B[j] > 0.0 ? B[j] : 0.0) / Dn[j];
+            xn = xo * q;
+        }
+        a += (xn - xo) * (xn - xo);
+        b += xo * xo;
+        x[j] = xn;
+    }
+    if (dsq) *dsq = a;
+    if (xsq) *xsq = b;
+}
+
+/* ---------------------------------------------------------------------------
+ * Public entry points (called through ctypes from the test-suite).
+ * ------------------------------------------------------------------------- */
+
+/* Flat initial guess (see header comment).  Returns -1 on invalid input. */
+double em_oracle_flat_x0(int n, int Hf, int Wf, int sr, const float* y, const float* v)
+{
+    const long np = (long)n * Hf * Wf;
+    double num = 0.0, den = 0.0;
+    for (long p = 0; p < np; ++p) {
+        const double vv = (double)v[p];
+        if (isinf(vv) && vv > 0) continue;
+        if (!(vv > 0.0) || !isfinite(vv) || !isfinite((double)y[p])) return -1.0;
+        num += (double)y[p] / vv;
+        den += 1.0 / vv;
+    }
+    double mu = den > 0.0 ? num / den : 0.0;
+    if (!(mu > 1e-3)) mu = 1e-3;
+    return mu / (double)(sr * sr);
+}
+
+/* B of Eq. (2) (numerator), latent grid. */
+int em_oracle_numerator(int n, int Hf, int Wf, int K, int sr, int mode,
+                        const float* y, const float* v, const float* psf, double* B)
+{
+    emo_state st;
+    if (emo_setup(&st, n, Hf, Wf, K, sr, y, v, psf)) return -2;
+    if (st.bad) { emo_free(&st); return -1; }
+    emo_numerator(&st, mode, B);
+    emo_free(&st);
+    return 0;
+}
+
+/* Dn of Eq. (2) (denominator) at x, latent grid. */
+int em_oracle_denominator(int n, int Hf, int Wf, int K, int sr, int mode,
+                          const float* y, const float* v, const float* psf,
+                          const double* x, double* Dn)
+{
+    emo_state st;
+    if (emo_setup(&st, n, Hf, Wf, K, sr, y, v, psf)) return -2;
+    if (st.bad) { emo_free(&st); return -1; }
+    emo_denominator(&st, mode, x, Dn, NULL);
+    emo_free(&st);
+    return 0;
+}
+
+/* l(x) of Eq. (1). */
+int em_oracle_loglik(int n, int Hf, int Wf, int K, int sr,
+                     const float* y, const float* v, const float* psf,
+                     const double* x, double* out)
+{
+    emo_state st;
+    if (emo_setup(&st, n, Hf, Wf, K, sr, y, v, psf)) return -2;
+    if (st.bad) { emo_free(&st); return -1; }
+    *out = emo_loglik(&st, x);
+    emo_free(&st);
+    return 0;
+}
+
+/*
+ * Run k_max EM iterations of Eq. (2) from x (in: x^(0), out: x^(k_max)).
+ * trace[k-1]     = l(x^(k-1))                 for k = 1..k_max (may be NULL)
+ * relchange[k-1] = ||x^(k) - x^(k-1)|| / ||x^(k-1)||         (may be NULL)
+ * Returns 0, -1 for invalid inputs, -2 for allocation failure.
+ */
+int em_oracle_run(int n, int Hf, int Wf, int K, int sr, int mode,
+                  const float* y, const float* v, const float* psf,
+                  double* x, int k_max, double* trace, double* relchange)
+{
+    if (n < 1 || Hf < 1 || Wf < 1 || K < 1 || (K % 2) == 0 || (sr != 1 && sr != 2)) return -1;
+    if (mode == 1 && sr != 1) return -1;
+    emo_state st;
+    if (emo_setup(&st, n, Hf, Wf, K, sr, y, v, psf)) return -2;
+    if (st.bad) { emo_free(&st); return -1; }
+    double* B = (double*)malloc(sizeof(double) * st.nl);
+    double* Dn = (double*)malloc(sizeof(double) * st.nl);
+    if (!B || !Dn) { free(B); free(Dn); emo_free(&st); return -2; }
+    emo_numerator(&st, mode, B);
+    for (int k = 1; k <= k_max; ++k) {
+        double ll = 0.0, a = 0.0, b = 0.0;
+        emo_denominator(&st, mode, x, Dn, &ll);
+        if (trace) trace[k - 1] = ll;
+        emo_update(st.nl, B, Dn, x, &a, &b);
+        if (relchange) relchange[k - 1] = b > 0.0 ? sqrt(a) / sqrt(b) : 0.0;
+    }
+    free(B); free(Dn);
+    emo_free(&st);
+    return 0;
+}
+
+/*
+ * One iteration evaluated only at selected latent pixels (for checks at sizes
+ * where a whole run is out of reach).  x0 (float, latent grid) is x^(0); for each
+ * point (rows[i], cols[i]) writes B, Dn and x^(1) there (adjoint weighting).
+ * Each F_t x value needed is evaluated on demand from its definition.
+ */
+int em_oracle_step_at(int n, int Hf, int Wf, int K, int sr,
+                      const float* y, const float* v, const float* psf, const float* x0,
+                      int npts, const int* rows, const int* cols,
+                      double* B_out, double* Dn_out, double* x1_out)
+{
+    const int Hl = Hf * sr, Wl = Wf * sr, c = (K - 1) / 2;
+    const long nl = (long)Hl * Wl;
+    double* xd = (double*)malloc(sizeof(double) * nl);
+    double* fd = (double*)malloc(sizeof(double) * K * K);
+    if (!xd || !fd) { free(xd); free(fd); return -2; }
+    for (long j = 0; j < nl; ++j) xd[j] = (double)x0[j];
+    for (int pt = 0; pt < npts; ++pt) {
+        const int k = rows[pt], l = cols[pt];
+        double Bv = 0.0, Dv = 0.0;
+        for (int t = 0; t < n; ++t) {
+            for (int e = 0; e < K * K; ++e) fd[e] = (double)psf[(long)t * K * K + e];
+            const float* yt = y + (long)t * Hf * Wf;
+            const float* vt = v + (long)t * Hf * Wf;
+            /* adjoint at (k,l): sum_{a,b} f[a,b] w[floor((k-c+a)/sr), floor((l-c+b)/sr)] */
+            double bt = 0.0, dt = 0.0;
+            for (int a = 0; a < K; ++a) {
+                const int i = k - c + a;
+                if (i < 0 || i >= Hl) continue;
+                for (int b = 0; b < K; ++b) {
+                    const int jj = l - c + b;
+                    if (jj < 0 || jj >= Wl) continue;
+                    const int I = i / sr, J = jj / sr;
+                    const double vv = (double)vt[(long)I * Wf + J];
+                    if (isinf(vv) && vv > 0) continue;            /* u = 0 */
+                    if (!(vv > 0.0) || !isfinite((double)yt[(long)I * Wf + J])) {
+                        free(xd); free(fd); return -1;
+                    }
+                    const double u = 1.0 / vv;
+                    const double mval = em_oracle_forward_at(K, sr, Hl, Wl, fd, xd, I, J);
+                    bt += fd[a * K + b] * (u * (double)yt[(long)I * Wf + J]);
+                    dt += fd[a * K + b] * (u * mval);
+                }
+            }
+            Bv += bt;
+            Dv += dt;
+        }
+        const double xo = xd[(long)k * Wl + l];
+        double xn;
+        if (xo == 0.0) xn = 0.0;
+        else if (Dv == 0.0) xn = xo;
+        else xn = xo * ((Bv > 0.0 ? Bv : 0.0) / Dv);
+        B_out[pt] = Bv; Dn_out[pt] = Dv; x1_out[pt] = xn;
+    }
+    free(xd); free(fd);
+    return 0;
+}
