@@ -1,0 +1,180 @@
+/*
+ * em.h -- C ABI of libem.so: the MI355X (gfx950) hot path of the multi-frame
+ * expectation-maximisation deconvolution and super-resolution method of
+ * Sukurdeep, Navarro & Budavari, arXiv:2302.05804, Sec. 2.
+ *
+ * What the library computes (paper notation):
+ *   exposures y^(t), PSFs f^(t) (or super-resolved h^(t)), variance maps v^(t),
+ *   t = 1..n; inverse-variance weights u^(t) = 1/v^(t) (text after Eq. (2)).
+ *   Image model, Eq. (1):  y^(t) = f^(t) * x + noise, noise ~ N(0, v^(t)).
+ *   Super-resolution model, Eq. (3):  y^(t) = D(h^(t) * x) + noise, with D a
+ *   2x2 box sum from the latent grid (x) to the frame grid (y).
+ *   One EM iteration, the multiplicative update of Eq. (2):
+ *       x <- x (.) max(B, 0) / Dn,
+ *       B  = sum_t F_t^T (u_t (.) y_t)          (constant, formed once),
+ *       Dn = sum_t F_t^T (u_t (.) F_t x),
+ *   where F_t x = D(f_t * x) (D = identity when sr = 1).  The weights act on
+ *   the frame grid before the adjoint; this is the majorise-minimise step of the
+ *   Gaussian likelihood of Eq. (1) (the paper's Eq. (2) typesets u outside
+ *   F^T, which coincides when each v^(t) is constant; weight mode
+ *   EM_W_LITERAL reproduces the typeset form, sr = 1 only).
+ *   Guards: x_j = 0 stays 0 (zeros are absorbing); x_j > 0 with Dn_j = 0 (a
+ *   pixel no unmasked frame pixel sees) keeps its value.
+ *   Log-likelihood, from Eq. (1):
+ *       l(x) = -1/2 sum_t sum_{u>0} [ u (y - F_t x)^2 + ln(2 pi v) ].
+ *
+ * Conventions:
+ *   - Convolution is a true 2-D convolution with an odd K x K kernel whose
+ *     centre is c = (K-1)/2, zero-filled outside the latent grid, output the
+ *     size of the grid ("same").  PSFs live on the latent grid.
+ *   - The latent grid is (sr*frame_h) x (sr*frame_w); frame pixel (I,J)
+ *     covers latent pixels (sr*I + p, sr*J + q), p,q < sr.
+ *   - All images are contiguous row-major float32.  Exposures and variances are
+ *     n x frame_h x frame_w, PSFs n x K x K, latent images H_lat x W_lat.
+ *   - v = +inf marks a masked pixel (u = 0); y there is never read as a
+ *     number (it may be NaN).  Any other v must be finite and > 0, and an
+ *     unmasked y must be finite; PSF taps must be finite and >= 0.
+ *
+ * Streams: a `stream` argument is a hipStream_t passed as void* (NULL is the
+ * default stream).  Device pointers are plain HIP device addresses.
+ *
+ * Errors: every entry point returns EM_OK (0) or a negative EM_E* code and
+ * never throws.  em_last_error() returns a thread-local text for the last
+ * failure on the calling thread.  Device errors from asynchronous work surface
+ * at the next synchronising call (em_init, em_iterate with a trace,
+ * em_loglik, em_sync).
+ *
+ * Threading: an em_ctx must be used by one thread at a time.
+ */
+#ifndef EM_H
+#define EM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define EM_OK         0
+#define EM_EINVAL    (-1)   /* bad argument or invalid input data            */
+#define EM_ENOMEM    (-2)   /* workspace / budget too small                   */
+#define EM_EDEVICE   (-3)   /* HIP runtime error (text in em_last_error)      */
+#define EM_EAGAIN    (-4)   /* serving: job not finished yet                  */
+#define EM_ECANCELED (-5)   /* serving: job cancelled                         */
+#define EM_ENOTSUP   (-6)   /* combination not provided by this build         */
+
+/* arithmetic of the two convolutions (the update is always FP32, the
+ * log-likelihood and convergence sums always FP64) */
+#define EM_FP32        0    /* FP32 products, FP32 accumulation               */
+#define EM_BF16_SPLIT  1    /* BF16 MFMA, hi+lo split operands, FP32 accum.   */
+#define EM_FP16_SPLIT  2    /* reserved                                       */
+#define EM_BF16        3    /* plain BF16 MFMA (ablation; below 1e-3 accuracy) */
+
+/* placement of the inverse-variance weights */
+#define EM_W_ADJOINT   0    /* sum_t F_t^T (u_t (.) .)  (default)              */
+#define EM_W_LITERAL   1    /* sum_t u_t (.) F_t^T (.)  (Eq. (2) as typeset, sr=1) */
+
+typedef struct em_ctx em_ctx;
+typedef struct em_server em_server;
+typedef int64_t em_job_id;
+
+typedef struct {
+    int32_t n_frames;     /* n >= 1                                          */
+    int32_t frame_h;      /* exposure rows    >= 1                           */
+    int32_t frame_w;      /* exposure columns >= 1                           */
+    int32_t psf_k;        /* odd, 1 <= K <= 43                               */
+    int32_t sr;           /* super-resolution factor: 1 or 2 (Eq. (3))       */
+    int32_t precision;    /* EM_FP32 or EM_BF16_SPLIT                        */
+    int32_t weight_mode;  /* EM_W_ADJOINT (EM_W_LITERAL: sr = 1 only)        */
+} em_problem;
+
+/* Library build / device description (NUL-terminated, static storage). */
+const char* em_version(void);
+
+/* Thread-local text of the last error on this thread ("" if none). */
+const char* em_last_error(void);
+
+/*
+ * Device bytes the library needs beyond the caller's buffers for problem p
+ * (weights, weighted model images, numerator B, coefficient tables, FP64
+ * partial sums).  Returns 0 for an invalid problem.
+ */
+size_t em_workspace_bytes(const em_problem* p);
+
+/*
+ * Set up one deconvolution job (Sec. 2: data y, f, v; initial guess x^(0)).
+ *   y, v      device, n x frame_h x frame_w float32 (caller-owned, borrowed
+ *             until em_destroy; not modified)
+ *   psf       device, n x K x K float32 on the latent grid (borrowed)
+ *   x0        device latent image, or NULL for the flat guess
+ *             x0 = max(mu, 1e-3) / sr^2, mu = sum u y / sum u
+ *             (x0 must be finite and >= 0; zeros stay zero)
+ *   x         device latent image (the iterate; written here, updated in
+ *             place by em_iterate; borrowed)
+ *   workspace device buffer of ws_bytes >= em_workspace_bytes(p), 256-byte
+ *             aligned (borrowed)
+ *   stream    hipStream_t (as void*) on which all of the job's work runs
+ * Computes u, B and x^(0) on the stream and synchronises it to validate the
+ * data.  Returns EM_EINVAL for a bad problem, NULL pointers or invalid data,
+ * EM_ENOMEM if ws_bytes is too small, EM_ENOTSUP for an unsupported
+ * precision / weight mode combination, EM_EDEVICE on a HIP error.
+ */
+int em_init(em_ctx** out, const em_problem* p,
+            const float* y, const float* v, const float* psf,
+            const float* x0, float* x,
+            void* workspace, size_t ws_bytes, void* stream);
+
+/*
+ * Run n_iter >= 0 iterations of the multiplicative update of Eq. (2)
+ * asynchronously on the job's stream.  If loglik_trace (host, n_iter doubles)
+ * is non-NULL, loglik_trace[k-1] = l(x^(k-1)) for k = 1..n_iter, and the
+ * call synchronises the stream before returning.
+ */
+int em_iterate(em_ctx* ctx, int32_t n_iter, double* loglik_trace);
+
+/*
+ * Like em_iterate, but stops after the first iteration k whose relative change
+ * ||x^(k) - x^(k-1)||_2 / ||x^(k-1)||_2 is below tol (FP64 sums on the GPU;
+ * the paper leaves the convergence criterion open, Sec. 2).  Checks every
+ * `check_every` iterations (>= 1).  Writes the iterations run to *iters_done and,
+ * if relchange_trace (host, max_iter doubles) is non-NULL, the relative
+ * change of every iteration run.  Synchronous.
+ */
+int em_iterate_tol(em_ctx* ctx, int32_t max_iter, double tol, int32_t check_every,
+                   int32_t* iters_done, double* loglik_trace, double* relchange_trace);
+
+/* l(x) at the current iterate, FP64 (synchronous). */
+int em_loglik(em_ctx* ctx, double* out);
+
+/*
+ * Diagnostics of the two frame sums of Eq. (2) at the current iterate: writes
+ * B (if B_out != NULL) and Dn (if Dn_out != NULL) as device float32 latent
+ * images.  Asynchronous on the job's stream; does not change the iterate.
+ */
+int em_terms(em_ctx* ctx, float* B_out, float* Dn_out);
+
+/* Wait for the job's stream; reports asynchronous device errors. */
+int em_sync(em_ctx* ctx);
+
+/* Release library state of the job (caller buffers are not freed). */
+int em_destroy(em_ctx* ctx);
+
+/*
+ * Stand-alone operators, for checking: F_t x and F_t^T r for every frame.
+ *   psf: device n x K x K; x, s: device latent images n x H_lat x W_lat for
+ *   em_adjoint_op output and one latent image for em_forward_op input;
+ *   m, r: device n x frame_h x frame_w.  `workspace` must hold
+ *   em_workspace_bytes(p) bytes.  Asynchronous on `stream`.
+ */
+int em_forward_op(const em_problem* p, const float* psf, const float* x, float* m,
+                  void* workspace, size_t ws_bytes, void* stream);
+int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* s,
+                  void* workspace, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* EM_H */

@@ -1,0 +1,556 @@
+// em_api.cpp -- C ABI of libem.so (declared in include/em.h): problem
+// validation, workspace layout, launch planning and the iteration driver of
+// the multiplicative EM update (arXiv:2302.05804, Sec. 2, Eq. (2)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/em.h"
+#include "em_internal.h"
+
+namespace em {
+
+int fwd_tile_h(const Geometry& g);
+int fwd_tile_w(const Geometry& g);
+int adj_tile_h(const Geometry& g);
+int adj_tile_w(const Geometry& g);
+
+static thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return code;
+}
+
+#define EM_HIP(call)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (call);                                                           \
+    if (e_ != hipSuccess)                                                             \
+      return em::fail(EM_EDEVICE, "%s: %s (%s:%d)", #call, hipGetErrorString(e_),     \
+                      __FILE__, __LINE__);                                            \
+  } while (0)
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+bool make_geometry(const void* problem, Geometry* g, const char** why) {
+  const em_problem* p = static_cast<const em_problem*>(problem);
+  if (!p) { *why = "problem is NULL"; return false; }
+  if (p->n_frames < 1) { *why = "n_frames must be >= 1"; return false; }
+  if (p->frame_h < 1 || p->frame_w < 1) { *why = "frame size must be >= 1"; return false; }
+  if (p->frame_h > 65536 || p->frame_w > 65536) { *why = "frame side above 65536"; return false; }
+  if (p->psf_k < 1 || p->psf_k % 2 == 0 || p->psf_k > K_MAX) {
+    *why = "psf_k must be odd and in [1, 43]";
+    return false;
+  }
+  if (p->sr != 1 && p->sr != 2) { *why = "sr must be 1 or 2"; return false; }
+  if (p->weight_mode != EM_W_ADJOINT && p->weight_mode != EM_W_LITERAL) {
+    *why = "unknown weight_mode";
+    return false;
+  }
+  if (p->precision < EM_FP32 || p->precision > EM_BF16) { *why = "unknown precision"; return false; }
+  g->n = p->n_frames;
+  g->Hf = p->frame_h;
+  g->Wf = p->frame_w;
+  g->sr = p->sr;
+  g->Hl = p->frame_h * p->sr;
+  g->Wl = p->frame_w * p->sr;
+  g->K = p->psf_k;
+  g->KT = p->psf_k <= KT_SMALL ? KT_SMALL : KT_LARGE;
+  g->KC = g->sr == 1 ? g->KT : g->KT + 1;
+  g->Nf = (int64_t)g->Hf * g->Wf;
+  g->Nl = (int64_t)g->Hl * g->Wl;
+  g->precision = p->precision;
+  g->weight_mode = p->weight_mode;
+  if ((int64_t)g->n * g->Nf > ((int64_t)1 << 40)) { *why = "problem too large"; return false; }
+  return true;
+}
+
+Plan make_plan(const Geometry& g) {
+  Plan pl{};
+  const int target = 1024;  // ~4 workgroups per compute unit on 256 CUs
+  pl.fwd_variant = 0;
+  pl.fwd_tiles = (int)(cdiv(g.Wf, fwd_tile_w(g)) * cdiv(g.Hf, fwd_tile_h(g)));
+  int fg = (int)std::min<int64_t>(g.n, cdiv(target, pl.fwd_tiles));
+  fg = std::max(fg, 1);
+  pl.fwd_fpg = (int)cdiv(g.n, fg);
+  pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
+  pl.adj_variant = 0;
+  pl.adj_tiles = (int)(cdiv(g.Wl, adj_tile_w(g)) * cdiv(g.Hl, adj_tile_h(g)));
+  if (pl.adj_tiles >= target / 2) {
+    pl.adj_groups = 1;
+    pl.adj_fpg = g.n;
+  } else {
+    int ag = (int)std::min<int64_t>(g.n, cdiv(target, pl.adj_tiles));
+    ag = std::max(ag, 1);
+    pl.adj_fpg = (int)cdiv(g.n, ag);
+    pl.adj_groups = (int)cdiv(g.n, pl.adj_fpg);
+  }
+  pl.prep_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv((int64_t)g.n * g.Nf, 256)));
+  pl.upd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv(g.Nl, 256)));
+  pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
+  return pl;
+}
+
+static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+Layout make_layout(const Geometry& g, const Plan& pl) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = off;
+    off += al256(bytes);
+    return o;
+  };
+  const size_t nf = (size_t)g.n * g.Nf;
+  // frame groups for per-frame adjoint output of em_adjoint_op use the caller's buffer
+  const int G = pl.adj_groups;
+  L.u = take(nf * sizeof(float));
+  L.r = take(nf * sizeof(float));
+  L.B = take((size_t)g.Nl * sizeof(float));
+  L.planes = take(G > 1 ? (size_t)G * g.Nl * sizeof(float) : 0);
+  L.tab = take((size_t)g.n * g.KC * TAB_LD * sizeof(float));
+  L.part_ll = take((size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double));
+  L.part_rc = take((size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double));
+  L.part_prep = take((size_t)3 * pl.prep_blocks * sizeof(double));
+  L.scalars = take(S_COUNT * sizeof(double));
+  L.trace_ll = take(TRACE_CAP * sizeof(double));
+  L.trace_rc = take(TRACE_CAP * sizeof(double));
+  L.counters = take(16 * sizeof(int));
+  L.total = off;
+  return L;
+}
+
+// Checks that [ptr, ptr + bytes) lies inside one device allocation.
+static int check_device_range(const void* ptr, size_t bytes, const char* name) {
+  if (ptr == nullptr) return fail(EM_EINVAL, "%s is NULL", name);
+  hipPointerAttribute_t attr;
+  hipError_t e = hipPointerGetAttributes(&attr, ptr);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(EM_EINVAL, "%s is not a HIP device pointer", name);
+  }
+  if (attr.type != hipMemoryTypeDevice && attr.type != hipMemoryTypeManaged)
+    return fail(EM_EINVAL, "%s is not device memory", name);
+  void* base = nullptr;
+  size_t size = 0;
+  e = hipMemGetAddressRange(reinterpret_cast<hipDeviceptr_t*>(&base), &size,
+                            reinterpret_cast<hipDeviceptr_t>(const_cast<void*>(ptr)));
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(EM_EINVAL, "%s: cannot query the allocation", name);
+  }
+  const char* b = static_cast<const char*>(base);
+  const char* p = static_cast<const char*>(ptr);
+  if (p < b || p + bytes > b + size)
+    return fail(EM_EINVAL, "%s: buffer smaller than the %zu bytes needed", name, bytes);
+  return EM_OK;
+}
+
+}  // namespace em
+
+using namespace em;
+
+struct em_ctx {
+  Geometry g;
+  Plan pl;
+  Layout lay;
+  hipStream_t stream;
+  const float* y;
+  const float* v;
+  const float* psf;
+  float* x;
+  char* ws;
+  // device views into the workspace
+  float* u;
+  float* r;
+  float* B;
+  float* planes;
+  float* tab;
+  double* part_ll;
+  double* part_rc;
+  double* part_prep;
+  double* scalars;
+  double* trace_ll;
+  double* trace_rc;
+  int* counters;  // [0] iteration counter, [4..7] validation flags
+};
+
+static void bind_views(em_ctx* c) {
+  char* w = c->ws;
+  const Layout& L = c->lay;
+  c->u = reinterpret_cast<float*>(w + L.u);
+  c->r = reinterpret_cast<float*>(w + L.r);
+  c->B = reinterpret_cast<float*>(w + L.B);
+  c->planes = reinterpret_cast<float*>(w + L.planes);
+  c->tab = reinterpret_cast<float*>(w + L.tab);
+  c->part_ll = reinterpret_cast<double*>(w + L.part_ll);
+  c->part_rc = reinterpret_cast<double*>(w + L.part_rc);
+  c->part_prep = reinterpret_cast<double*>(w + L.part_prep);
+  c->scalars = reinterpret_cast<double*>(w + L.scalars);
+  c->trace_ll = reinterpret_cast<double*>(w + L.trace_ll);
+  c->trace_rc = reinterpret_cast<double*>(w + L.trace_rc);
+  c->counters = reinterpret_cast<int*>(w + L.counters);
+}
+
+extern "C" {
+
+const char* em_version(void) {
+  return "libem 0.1 (gfx950; FP32 direct convolution; FP64 reductions)";
+}
+
+const char* em_last_error(void) { return em::g_last_error.c_str(); }
+
+size_t em_workspace_bytes(const em_problem* p) {
+  Geometry g;
+  const char* why = nullptr;
+  if (!make_geometry(p, &g, &why)) return 0;
+  const Plan pl = make_plan(g);
+  return make_layout(g, pl).total;
+}
+
+}  // extern "C"
+
+// Adjoint over frames of `in` (n x Nf) into B-like output `out` (Nl floats),
+// never applying the update.
+static int adjoint_sum(em_ctx* c, const float* in, float* out) {
+  AdjLaunch a{};
+  a.in = in;
+  a.tab = c->tab;
+  a.n = c->g.n;
+  a.Hf = c->g.Hf;
+  a.Wf = c->g.Wf;
+  a.Hl = c->g.Hl;
+  a.Wl = c->g.Wl;
+  a.fpg = c->pl.adj_fpg;
+  a.fused = 0;
+  a.plane = c->pl.adj_groups > 1 ? c->planes : out;
+  EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+  if (c->pl.adj_groups > 1)
+    EM_HIP(launch_sum_planes(c->planes, c->pl.adj_groups, c->g.Nl, out, c->stream));
+  return EM_OK;
+}
+
+// Forward pass at the current iterate: r = u F x (if write_r) and loglik partials.
+static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
+  FwdLaunch f{};
+  f.x = c->x;
+  f.tab = c->tab;
+  f.u = c->u;
+  f.y = c->y;
+  f.out = write_r ? c->r : nullptr;
+  f.part = loglik ? c->part_ll : nullptr;
+  f.n = c->g.n;
+  f.Hf = c->g.Hf;
+  f.Wf = c->g.Wf;
+  f.Hl = c->g.Hl;
+  f.Wl = c->g.Wl;
+  f.fpg = c->pl.fwd_fpg;
+  EM_HIP(launch_forward(c->g, c->pl, f, c->stream));
+  return EM_OK;
+}
+
+// One EM iteration (Eq. (2)); optional FP64 loglik / relative-change bookkeeping.
+static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
+  int rc = forward_pass(c, true, loglik);
+  if (rc) return rc;
+  AdjLaunch a{};
+  a.in = c->r;
+  a.tab = c->tab;
+  a.n = c->g.n;
+  a.Hf = c->g.Hf;
+  a.Wf = c->g.Wf;
+  a.Hl = c->g.Hl;
+  a.Wl = c->g.Wl;
+  a.fpg = c->pl.adj_fpg;
+  int n_rc;
+  if (c->pl.adj_groups == 1) {
+    a.fused = 1;
+    a.x = c->x;
+    a.B = c->B;
+    a.part = relchange ? c->part_rc : nullptr;
+    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+    n_rc = c->pl.adj_tiles;
+  } else {
+    a.fused = 0;
+    a.plane = c->planes;
+    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+    EM_HIP(launch_update(c->planes, c->pl.adj_groups, c->g.Nl, c->B, c->x,
+                         relchange ? c->part_rc : nullptr, c->pl.upd_blocks, c->stream));
+    n_rc = c->pl.upd_blocks;
+  }
+  if (loglik || relchange) {
+    EM_HIP(launch_finalize_iter(loglik ? c->part_ll : nullptr, c->pl.fwd_tiles * c->pl.fwd_groups,
+                                relchange ? c->part_rc : nullptr, n_rc, c->scalars, c->trace_ll,
+                                c->trace_rc, c->counters, c->stream));
+  }
+  return EM_OK;
+}
+
+extern "C" {
+
+int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, const float* psf,
+            const float* x0, float* x, void* workspace, size_t ws_bytes, void* stream) {
+  if (!out) return fail(EM_EINVAL, "out is NULL");
+  *out = nullptr;
+  Geometry g;
+  const char* why = nullptr;
+  if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
+  if (g.precision != EM_FP32) return fail(EM_ENOTSUP, "precision %d not provided", g.precision);
+  if (g.weight_mode != EM_W_ADJOINT)
+    return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
+  const Plan pl = make_plan(g);
+  const Layout L = make_layout(g, pl);
+  if (ws_bytes < L.total)
+    return fail(EM_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(EM_EINVAL, "workspace must be 256-byte aligned");
+  const size_t fbytes = (size_t)g.n * g.Nf * sizeof(float);
+  const size_t lbytes = (size_t)g.Nl * sizeof(float);
+  int rc;
+  if ((rc = check_device_range(y, fbytes, "y"))) return rc;
+  if ((rc = check_device_range(v, fbytes, "v"))) return rc;
+  if ((rc = check_device_range(psf, (size_t)g.n * g.K * g.K * sizeof(float), "psf"))) return rc;
+  if (x0 && (rc = check_device_range(x0, lbytes, "x0"))) return rc;
+  if ((rc = check_device_range(x, lbytes, "x"))) return rc;
+  if ((rc = check_device_range(workspace, L.total, "workspace"))) return rc;
+
+  em_ctx* c = new (std::nothrow) em_ctx();
+  if (!c) return fail(EM_ENOMEM, "host allocation failed");
+  c->g = g;
+  c->pl = pl;
+  c->lay = L;
+  c->stream = static_cast<hipStream_t>(stream);
+  c->y = y;
+  c->v = v;
+  c->psf = psf;
+  c->x = x;
+  c->ws = static_cast<char*>(workspace);
+  bind_views(c);
+
+  auto bail = [&](int code) {
+    delete c;
+    return code;
+  };
+  hipError_t e;
+  if ((e = launch_reset_counters(c->counters, c->stream)) != hipSuccess ||
+      (e = launch_reset_counters(c->counters + 4, c->stream)) != hipSuccess)
+    return bail(fail(EM_EDEVICE, "reset: %s", hipGetErrorString(e)));
+  PrepLaunch pr{};
+  pr.y = y;
+  pr.v = v;
+  pr.u = c->u;
+  pr.w = c->r;
+  pr.part = c->part_prep;
+  pr.flags = c->counters + 4;
+  pr.count = (int64_t)g.n * g.Nf;
+  pr.blocks = pl.prep_blocks;
+  if ((e = launch_prep(pr, c->stream)) != hipSuccess)
+    return bail(fail(EM_EDEVICE, "prep: %s", hipGetErrorString(e)));
+  if ((e = launch_psf_tables(g, psf, c->tab, c->counters + 4, c->stream)) != hipSuccess)
+    return bail(fail(EM_EDEVICE, "psf tables: %s", hipGetErrorString(e)));
+  if ((rc = adjoint_sum(c, c->r, c->B))) return bail(rc);
+  if ((e = launch_finalize_prep(c->part_prep, pl.prep_blocks, c->scalars, g.sr, c->stream)) !=
+      hipSuccess)
+    return bail(fail(EM_EDEVICE, "finalize: %s", hipGetErrorString(e)));
+  if ((e = launch_init_x(x0, x, c->scalars, g.Nl, c->counters + 4, c->stream)) != hipSuccess)
+    return bail(fail(EM_EDEVICE, "init x: %s", hipGetErrorString(e)));
+  int flags[4] = {0, 0, 0, 0};
+  if ((e = hipMemcpyAsync(flags, c->counters + 4, sizeof(flags), hipMemcpyDeviceToHost,
+                          c->stream)) != hipSuccess ||
+      (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+    return bail(fail(EM_EDEVICE, "init sync: %s", hipGetErrorString(e)));
+  if (flags[0]) return bail(fail(EM_EINVAL, "%d invalid exposure/variance pixels", flags[0]));
+  if (flags[1]) return bail(fail(EM_EINVAL, "%d invalid PSF taps (must be finite, >= 0)", flags[1]));
+  if (flags[2]) return bail(fail(EM_EINVAL, "%d invalid x0 pixels (must be finite, >= 0)", flags[2]));
+  *out = c;
+  return EM_OK;
+}
+
+int em_iterate(em_ctx* c, int32_t n_iter, double* loglik_trace) {
+  if (!c) return fail(EM_EINVAL, "ctx is NULL");
+  if (n_iter < 0) return fail(EM_EINVAL, "n_iter < 0");
+  const bool tr = loglik_trace != nullptr;
+  int done = 0;
+  while (done < n_iter) {
+    const int chunk = std::min(n_iter - done, TRACE_CAP);
+    if (tr) EM_HIP(launch_reset_counters(c->counters, c->stream));
+    for (int k = 0; k < chunk; ++k) {
+      int rc = one_iteration(c, tr, false);
+      if (rc) return rc;
+    }
+    if (tr) {
+      EM_HIP(hipMemcpyAsync(loglik_trace + done, c->trace_ll, sizeof(double) * chunk,
+                            hipMemcpyDeviceToHost, c->stream));
+      EM_HIP(hipStreamSynchronize(c->stream));
+    }
+    done += chunk;
+  }
+  return EM_OK;
+}
+
+int em_iterate_tol(em_ctx* c, int32_t max_iter, double tol, int32_t check_every,
+                   int32_t* iters_done, double* loglik_trace, double* relchange_trace) {
+  if (!c) return fail(EM_EINVAL, "ctx is NULL");
+  if (max_iter < 0 || check_every < 1) return fail(EM_EINVAL, "bad max_iter / check_every");
+  if (!iters_done) return fail(EM_EINVAL, "iters_done is NULL");
+  const bool tr = loglik_trace != nullptr;
+  int done = 0;
+  std::vector<double> rcbuf;
+  while (done < max_iter) {
+    const int chunk = std::min(std::min(max_iter - done, check_every), TRACE_CAP);
+    EM_HIP(launch_reset_counters(c->counters, c->stream));
+    for (int k = 0; k < chunk; ++k) {
+      int rc = one_iteration(c, tr, true);
+      if (rc) return rc;
+    }
+    rcbuf.resize(chunk);
+    EM_HIP(hipMemcpyAsync(rcbuf.data(), c->trace_rc, sizeof(double) * chunk,
+                          hipMemcpyDeviceToHost, c->stream));
+    if (tr)
+      EM_HIP(hipMemcpyAsync(loglik_trace + done, c->trace_ll, sizeof(double) * chunk,
+                            hipMemcpyDeviceToHost, c->stream));
+    EM_HIP(hipStreamSynchronize(c->stream));
+    if (relchange_trace) std::copy(rcbuf.begin(), rcbuf.end(), relchange_trace + done);
+    done += chunk;
+    bool stop = false;
+    for (int k = 0; k < chunk; ++k) stop = stop || rcbuf[k] < tol;
+    if (stop) break;
+  }
+  *iters_done = done;
+  return EM_OK;
+}
+
+int em_loglik(em_ctx* c, double* out) {
+  if (!c || !out) return fail(EM_EINVAL, "NULL argument");
+  int rc = forward_pass(c, false, true);
+  if (rc) return rc;
+  EM_HIP(launch_finalize_loglik(c->part_ll, c->pl.fwd_tiles * c->pl.fwd_groups, c->scalars,
+                                c->stream));
+  EM_HIP(hipMemcpyAsync(out, c->scalars + S_LOGLIK, sizeof(double), hipMemcpyDeviceToHost,
+                        c->stream));
+  EM_HIP(hipStreamSynchronize(c->stream));
+  return EM_OK;
+}
+
+int em_terms(em_ctx* c, float* B_out, float* Dn_out) {
+  if (!c) return fail(EM_EINVAL, "ctx is NULL");
+  const size_t lbytes = (size_t)c->g.Nl * sizeof(float);
+  int rc;
+  if (B_out) {
+    if ((rc = check_device_range(B_out, lbytes, "B_out"))) return rc;
+    EM_HIP(hipMemcpyAsync(B_out, c->B, lbytes, hipMemcpyDeviceToDevice, c->stream));
+  }
+  if (Dn_out) {
+    if ((rc = check_device_range(Dn_out, lbytes, "Dn_out"))) return rc;
+    if ((rc = forward_pass(c, true, false))) return rc;
+    if ((rc = adjoint_sum(c, c->r, Dn_out))) return rc;
+  }
+  return EM_OK;
+}
+
+int em_sync(em_ctx* c) {
+  if (!c) return fail(EM_EINVAL, "ctx is NULL");
+  EM_HIP(hipStreamSynchronize(c->stream));
+  return EM_OK;
+}
+
+int em_destroy(em_ctx* c) {
+  delete c;
+  return EM_OK;
+}
+
+// ---- stand-alone operators -------------------------------------------------
+
+static int op_setup(const em_problem* p, const float* psf, void* workspace, size_t ws_bytes,
+                    Geometry* g, Plan* pl, Layout* L) {
+  const char* why = nullptr;
+  if (!make_geometry(p, g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
+  *pl = make_plan(*g);
+  *L = make_layout(*g, *pl);
+  if (ws_bytes < L->total) return fail(EM_ENOMEM, "workspace too small");
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255) != 0)
+    return fail(EM_EINVAL, "workspace must be 256-byte aligned");
+  int rc;
+  if ((rc = check_device_range(workspace, L->total, "workspace"))) return rc;
+  if ((rc = check_device_range(psf, (size_t)g->n * g->K * g->K * sizeof(float), "psf"))) return rc;
+  return EM_OK;
+}
+
+int em_forward_op(const em_problem* p, const float* psf, const float* x, float* m, void* workspace,
+                  size_t ws_bytes, void* stream) {
+  Geometry g;
+  Plan pl;
+  Layout L;
+  int rc = op_setup(p, psf, workspace, ws_bytes, &g, &pl, &L);
+  if (rc) return rc;
+  if ((rc = check_device_range(x, (size_t)g.Nl * sizeof(float), "x"))) return rc;
+  if ((rc = check_device_range(m, (size_t)g.n * g.Nf * sizeof(float), "m"))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace);
+  float* tab = reinterpret_cast<float*>(w + L.tab);
+  int* flags = reinterpret_cast<int*>(w + L.counters);
+  EM_HIP(launch_reset_counters(flags, s));
+  EM_HIP(launch_psf_tables(g, psf, tab, flags, s));
+  FwdLaunch f{};
+  f.x = x;
+  f.tab = tab;
+  f.u = nullptr;
+  f.y = nullptr;
+  f.out = m;
+  f.part = nullptr;
+  f.n = g.n;
+  f.Hf = g.Hf;
+  f.Wf = g.Wf;
+  f.Hl = g.Hl;
+  f.Wl = g.Wl;
+  f.fpg = pl.fwd_fpg;
+  EM_HIP(launch_forward(g, pl, f, s));
+  return EM_OK;
+}
+
+int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* sout,
+                  void* workspace, size_t ws_bytes, void* stream) {
+  Geometry g;
+  Plan pl;
+  Layout L;
+  int rc = op_setup(p, psf, workspace, ws_bytes, &g, &pl, &L);
+  if (rc) return rc;
+  if ((rc = check_device_range(r, (size_t)g.n * g.Nf * sizeof(float), "r"))) return rc;
+  if ((rc = check_device_range(sout, (size_t)g.n * g.Nl * sizeof(float), "s"))) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  char* w = static_cast<char*>(workspace);
+  float* tab = reinterpret_cast<float*>(w + L.tab);
+  int* flags = reinterpret_cast<int*>(w + L.counters);
+  EM_HIP(launch_reset_counters(flags, s));
+  EM_HIP(launch_psf_tables(g, psf, tab, flags, s));
+  Plan per = pl;  // one frame per group: group t writes plane t = F_t^T r_t
+  per.adj_fpg = 1;
+  per.adj_groups = g.n;
+  AdjLaunch a{};
+  a.in = r;
+  a.tab = tab;
+  a.plane = sout;
+  a.n = g.n;
+  a.Hf = g.Hf;
+  a.Wf = g.Wf;
+  a.Hl = g.Hl;
+  a.Wl = g.Wl;
+  a.fpg = 1;
+  a.fused = 0;
+  EM_HIP(launch_adjoint(g, per, a, s));
+  return EM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,136 @@
+// em_internal.h -- declarations shared inside libem.so (not installed).
+//
+// Plan of one EM iteration (Eq. (2) of arXiv:2302.05804, Sec. 2) on the GPU:
+//   forward  : r_t = u_t (.) F_t x  for every frame t      (+ FP64 l(x) partials)
+//   adjoint  : Dn  = sum_t F_t^T r_t                         (fixed frame order)
+//   update   : x  <- x (.) max(B,0) / Dn                     (+ FP64 change partials)
+// F_t x = D(f_t * x) is a direct K x K convolution (sr = 1) or a stride-2
+// convolution with the 2x2-box-extended kernel k_t = h_t * 1_{2x2} of size
+// (K+1) x (K+1) (sr = 2, Eq. (3)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+namespace em {
+
+// Supported padded kernel sizes.  A smaller odd K is zero-padded symmetrically
+// to the next of these, which leaves every sum unchanged (the extra taps
+// multiply finite values by +0).
+constexpr int KT_SMALL = 15;
+constexpr int KT_LARGE = 43;
+constexpr int K_MAX = KT_LARGE;
+
+// Coefficient tables: per frame, KC columns of TAB_LD floats, column b holds
+// the kernel taps k[0..KC-1][b] (column-major), KC = KT (sr=1) or KT+1 (sr=2).
+constexpr int TAB_LD = 48;
+
+// Device trace capacity (iterations per chunk of em_iterate).
+constexpr int TRACE_CAP = 4096;
+
+// Scalar slots (double) in the workspace.
+enum Scalar {
+  S_SUM_UY = 0,     // sum u*y over unmasked frame pixels
+  S_SUM_U = 1,      // sum u
+  S_LCONST = 2,     // sum_{u>0} ln(2 pi v)
+  S_X0 = 3,         // flat starting value
+  S_LOGLIK = 4,     // last em_loglik result
+  S_RC_NUM = 5,
+  S_RC_DEN = 6,
+  S_COUNT = 16
+};
+
+struct Geometry {
+  int n, Hf, Wf, sr, Hl, Wl, K, KT, KC;
+  int64_t Nf, Nl;
+  int precision, weight_mode;
+};
+
+// Launch shape chosen for a geometry (a pure function of the geometry, so the
+// arithmetic of a job never depends on what else runs).
+struct Plan {
+  // forward
+  int fwd_variant;
+  int fwd_tiles;       // frame-grid tiles
+  int fwd_groups;      // frame groups (grid.y)
+  int fwd_fpg;         // frames per group
+  // adjoint
+  int adj_variant;
+  int adj_tiles;       // latent-grid tiles
+  int adj_groups;      // frame groups; 1 => update fused into the adjoint
+  int adj_fpg;
+  // reductions
+  int prep_blocks;     // blocks of the per-pixel prep kernel
+  int upd_blocks;      // blocks of the separate update kernel
+  int max_partials;    // doubles per partial array
+};
+
+// Workspace layout (byte offsets from the workspace base, 256-aligned).
+struct Layout {
+  size_t u, r, B, planes, tab, part_ll, part_rc, part_prep, scalars, trace_ll, trace_rc,
+      counters, total;
+};
+
+bool make_geometry(const void* problem, Geometry* g, const char** why);
+Plan make_plan(const Geometry& g);
+Layout make_layout(const Geometry& g, const Plan& pl);
+
+// ---- launchers (em_fp32.hip / em_elem.hip) --------------------------------
+struct FwdLaunch {
+  const float* x;      // latent image
+  const float* tab;    // coefficient tables
+  const float* u;      // weights (nullptr => raw F_t x output)
+  const float* y;      // exposures (loglik only)
+  float* out;          // r_t = u_t F_t x  (or F_t x when u == nullptr)
+  double* part;        // loglik partials (nullptr => none)
+  int n, Hf, Wf, Hl, Wl, fpg;
+};
+
+struct AdjLaunch {
+  const float* in;     // frame-grid images, n x Nf
+  const float* tab;
+  float* plane;        // output planes (mode 0), G x Nl
+  float* x;            // iterate (fused update)
+  const float* B;      // numerator (fused update)
+  double* part;        // change partials (fused update, may be nullptr)
+  int n, Hf, Wf, Hl, Wl, fpg;
+  int fused;           // 1 => x update in the epilogue (G == 1)
+};
+
+hipError_t launch_forward(const Geometry& g, const Plan& pl, const FwdLaunch& a, hipStream_t s);
+hipError_t launch_adjoint(const Geometry& g, const Plan& pl, const AdjLaunch& a, hipStream_t s);
+
+struct PrepLaunch {
+  const float* y;
+  const float* v;
+  float* u;
+  float* w;            // u * y (masked y -> 0)
+  double* part;        // 3 x blocks partial sums
+  int* flags;          // [0] invalid data count
+  int64_t count;       // n * Nf
+  int blocks;
+};
+hipError_t launch_prep(const PrepLaunch& a, hipStream_t s);
+
+hipError_t launch_psf_tables(const Geometry& g, const float* psf, float* tab, int* flags,
+                             hipStream_t s);
+
+// sums `count` partials of `nsum` interleaved arrays in fixed order
+hipError_t launch_finalize_prep(const double* part, int blocks, double* scalars, int sr,
+                                hipStream_t s);
+hipError_t launch_init_x(const float* x0, float* x, const double* scalars, int64_t count,
+                         int* flags, hipStream_t s);
+hipError_t launch_sum_planes(const float* planes, int G, int64_t Nl, float* out, hipStream_t s);
+hipError_t launch_update(const float* planes, int G, int64_t Nl, const float* B, float* x,
+                         double* part, int blocks, hipStream_t s);
+// iteration bookkeeping: writes trace entries at counters[0] and advances it
+hipError_t launch_finalize_iter(const double* part_ll, int n_ll, const double* part_rc,
+                                int n_rc, const double* scalars, double* trace_ll,
+                                double* trace_rc, int* counters, hipStream_t s);
+hipError_t launch_finalize_loglik(const double* part_ll, int n_ll, double* scalars,
+                                  hipStream_t s);
+hipError_t launch_reset_counters(int* counters, hipStream_t s);
+hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t s);
+
+}  // namespace em

@@ -1,0 +1,233 @@
+"""ctypes binding of libem.so (C ABI in include/em.h).
+
+Argument marshalling only: every step of the EM iteration runs in the HIP
+kernels of libem.so.  PyTorch tensors provide device memory and the stream;
+their device addresses are passed as plain pointers.  Importing this module
+raises if the library has not been built (``python -m
+paper_2302_05804_amd.build``) -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libem.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2302_05804_amd.build`")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+# status codes (include/em.h)
+OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ECANCELED, ENOTSUP = 0, -1, -2, -3, -4, -5, -6
+# precisions
+FP32, BF16_SPLIT, FP16_SPLIT, BF16 = 0, 1, 2, 3
+# weight placement
+W_ADJOINT, W_LITERAL = 0, 1
+
+_NAMES = {OK: "EM_OK", EINVAL: "EM_EINVAL", ENOMEM: "EM_ENOMEM", EDEVICE: "EM_EDEVICE",
+          EAGAIN: "EM_EAGAIN", ECANCELED: "EM_ECANCELED", ENOTSUP: "EM_ENOTSUP"}
+
+
+class EMError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        msg = _lib.em_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {_NAMES.get(code, code)}: {msg}")
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("n_frames", ctypes.c_int32), ("frame_h", ctypes.c_int32),
+                ("frame_w", ctypes.c_int32), ("psf_k", ctypes.c_int32),
+                ("sr", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("weight_mode", ctypes.c_int32)]
+
+    @classmethod
+    def make(cls, n, frame_h, frame_w, psf_k, sr=1, precision=FP32, weight_mode=W_ADJOINT):
+        return cls(int(n), int(frame_h), int(frame_w), int(psf_k), int(sr), int(precision),
+                   int(weight_mode))
+
+    @property
+    def latent_shape(self):
+        return (self.frame_h * self.sr, self.frame_w * self.sr)
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_sig = {
+    "em_version": (ctypes.c_char_p, []),
+    "em_last_error": (ctypes.c_char_p, []),
+    "em_workspace_bytes": (ctypes.c_size_t, [ctypes.POINTER(Problem)]),
+    "em_init": (ctypes.c_int, [_PP, ctypes.POINTER(Problem), _P, _P, _P, _P, _P, _P,
+                               ctypes.c_size_t, _P]),
+    "em_iterate": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "em_iterate_tol": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.POINTER(ctypes.c_int32), _P, _P]),
+    "em_loglik": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
+    "em_terms": (ctypes.c_int, [_P, _P, _P]),
+    "em_sync": (ctypes.c_int, [_P]),
+    "em_destroy": (ctypes.c_int, [_P]),
+    "em_forward_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "em_adjoint_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
+}
+for _name, (_res, _args) in _sig.items():
+    _fn = getattr(_lib, _name)
+    _fn.restype = _res
+    _fn.argtypes = _args
+
+
+def exported_symbols():
+    """Names of the C ABI entry points this binding resolved."""
+    return sorted(_sig)
+
+
+def version() -> str:
+    return _lib.em_version().decode()
+
+
+def workspace_bytes(p: Problem) -> int:
+    return int(_lib.em_workspace_bytes(ctypes.byref(p)))
+
+
+def _check(code: int, where: str):
+    if code != OK:
+        raise EMError(code, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dev_ptr(t, name, numel=None):
+    torch = _torch()
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype != torch.float32 and t.dtype != torch.uint8:
+        raise TypeError(f"{name} must be float32")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, {numel} expected")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_ptr(stream):
+    torch = _torch()
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream), stream
+
+
+def alloc_workspace(p: Problem, device="cuda"):
+    torch = _torch()
+    nb = workspace_bytes(p)
+    if nb == 0:
+        raise EMError(EINVAL, "em_workspace_bytes")
+    return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+class Context:
+    """One deconvolution job: wraps em_init / em_iterate / em_loglik / em_destroy.
+
+    y, v: (n, Hf, Wf) float32 device tensors; psf: (n, K, K); x: latent-size
+    float32 tensor that receives the iterate; x0 optional (None = flat guess).
+    All tensors are borrowed for the lifetime of the context.
+    """
+
+    def __init__(self, p: Problem, y, v, psf, x, x0=None, workspace=None, stream=None):
+        nf = p.n_frames * p.frame_h * p.frame_w
+        nl = p.latent_shape[0] * p.latent_shape[1]
+        self.p = p
+        self._keep = [y, v, psf, x, x0]
+        self.ws = workspace if workspace is not None else alloc_workspace(p, device=y.device)
+        self._keep.append(self.ws)
+        sp, self.stream = _stream_ptr(stream)
+        h = ctypes.c_void_p()
+        _check(_lib.em_init(ctypes.byref(h), ctypes.byref(p), _dev_ptr(y, "y", nf),
+                            _dev_ptr(v, "v", nf), _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
+                            _dev_ptr(x0, "x0", nl), _dev_ptr(x, "x", nl),
+                            _dev_ptr(self.ws, "workspace"), self.ws.numel(), sp), "em_init")
+        self._h = h
+
+    def iterate(self, n_iter: int, trace: bool = False) -> Optional[np.ndarray]:
+        if trace:
+            tr = np.zeros(max(n_iter, 1), np.float64)
+            _check(_lib.em_iterate(self._h, int(n_iter), tr.ctypes.data_as(_P)), "em_iterate")
+            return tr[:n_iter]
+        _check(_lib.em_iterate(self._h, int(n_iter), None), "em_iterate")
+        return None
+
+    def iterate_tol(self, max_iter: int, tol: float, check_every: int = 1, trace: bool = False):
+        done = ctypes.c_int32(0)
+        rc = np.zeros(max(max_iter, 1), np.float64)
+        tr = np.zeros(max(max_iter, 1), np.float64) if trace else None
+        _check(_lib.em_iterate_tol(self._h, int(max_iter), float(tol), int(check_every),
+                                   ctypes.byref(done),
+                                   tr.ctypes.data_as(_P) if tr is not None else None,
+                                   rc.ctypes.data_as(_P)), "em_iterate_tol")
+        k = done.value
+        return k, rc[:k], (tr[:k] if tr is not None else None)
+
+    def loglik(self) -> float:
+        out = ctypes.c_double(0.0)
+        _check(_lib.em_loglik(self._h, ctypes.byref(out)), "em_loglik")
+        return out.value
+
+    def terms(self):
+        """(B, Dn) of Eq. (2) at the current iterate, as new device tensors."""
+        torch = _torch()
+        B = torch.empty(self.p.latent_shape, dtype=torch.float32, device=self.ws.device)
+        Dn = torch.empty_like(B)
+        _check(_lib.em_terms(self._h, _dev_ptr(B, "B"), _dev_ptr(Dn, "Dn")), "em_terms")
+        return B, Dn
+
+    def sync(self):
+        _check(_lib.em_sync(self._h), "em_sync")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.em_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def forward_op(p: Problem, psf, x, m=None, workspace=None, stream=None):
+    """m_t = F_t x for every frame (n, Hf, Wf)."""
+    torch = _torch()
+    if m is None:
+        m = torch.empty((p.n_frames, p.frame_h, p.frame_w), dtype=torch.float32, device=x.device)
+    ws = workspace if workspace is not None else alloc_workspace(p, device=x.device)
+    sp, _ = _stream_ptr(stream)
+    nl = p.latent_shape[0] * p.latent_shape[1]
+    _check(_lib.em_forward_op(ctypes.byref(p), _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
+                              _dev_ptr(x, "x", nl),
+                              _dev_ptr(m, "m", p.n_frames * p.frame_h * p.frame_w),
+                              _dev_ptr(ws, "workspace"), ws.numel(), sp), "em_forward_op")
+    return m
+
+
+def adjoint_op(p: Problem, psf, r, s=None, workspace=None, stream=None):
+    """s_t = F_t^T r_t for every frame (n, Hl, Wl)."""
+    torch = _torch()
+    hl, wl = p.latent_shape
+    if s is None:
+        s = torch.empty((p.n_frames, hl, wl), dtype=torch.float32, device=r.device)
+    ws = workspace if workspace is not None else alloc_workspace(p, device=r.device)
+    sp, _ = _stream_ptr(stream)
+    _check(_lib.em_adjoint_op(ctypes.byref(p), _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
+                              _dev_ptr(r, "r", p.n_frames * p.frame_h * p.frame_w),
+                              _dev_ptr(s, "s", p.n_frames * hl * wl),
+                              _dev_ptr(ws, "workspace"), ws.numel(), sp), "em_adjoint_op")
+    return s

@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every entry point include/em.h declares.
+
+No compute call is made here: these run without a GPU.
+"""
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "em.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(em_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("em_init", "em_iterate", "em_loglik", "em_destroy", "em_workspace_bytes",
+                     "em_last_error"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    em = pytest.importorskip("paper_2302_05804_amd.em")
+    lib = ctypes.CDLL(em.LIB_PATH)
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    # the binding covers the same set
+    assert set(em.exported_symbols()) >= set(declared_functions())
+
+
+def test_workspace_bytes_host_logic():
+    em = pytest.importorskip("paper_2302_05804_amd.em")
+    P = em.Problem.make
+    good = P(4, 128, 128, 15)
+    nb = em.workspace_bytes(good)
+    # u and r planes alone need 2 * n * Hf * Wf floats
+    assert nb >= 2 * 4 * 128 * 128 * 4
+    assert nb % 256 == 0
+    assert em.workspace_bytes(P(33, 4096, 4096, 43)) > em.workspace_bytes(P(8, 1024, 1024, 43))
+    sr2 = em.workspace_bytes(P(16, 2048, 2048, 43, sr=2))
+    assert sr2 >= 2 * 16 * 2048 * 2048 * 4 + 4096 * 4096 * 4
+    for bad in (P(0, 8, 8, 3), P(1, 0, 8, 3), P(1, 8, 8, 4), P(1, 8, 8, 45), P(1, 8, 8, 3, sr=3),
+                P(1, 8, 8, 3, precision=9), P(1, 8, 8, 3, weight_mode=7), P(1, 8, 8, -1)):
+        assert em.workspace_bytes(bad) == 0
+
+
+def test_version_string():
+    em = pytest.importorskip("paper_2302_05804_amd.em")
+    assert "gfx950" in em.version()

@@ -1,0 +1,255 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+Bars (FP32 path): rel L2 of the iterate x <= 1e-5 after the full iteration
+count; operators F_t x and F_t^T r within 2e-6 rel L2 and 1e-5 of the
+largest |value|; the log-likelihood trace within 1e-6 relative.  Sizes span
+several tiles and ragged tails in both directions.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_05804_amd import synth
+from tests.gpu_common import gpu_run, log, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+X_TOL = 1e-5
+LL_TOL = 1e-6
+
+
+def _em():
+    from paper_2302_05804_amd import em
+    return em
+
+
+# ---------------------------------------------------------------------------
+# operators
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sr,K,hf,wf,n", [
+    (1, 15, 70, 131, 3), (1, 43, 150, 97, 2), (1, 43, 65, 64, 1), (1, 7, 33, 200, 2),
+    (2, 43, 75, 66, 2), (2, 15, 40, 70, 3), (2, 43, 17, 130, 1), (1, 43, 5, 3, 2), (2, 43, 3, 2, 1),
+])
+def test_forward_and_adjoint_operators(sr, K, hf, wf, n):
+    em = _em()
+    log(f"operators sr={sr} K={K} frame={hf}x{wf} n={n}")
+    rng = np.random.default_rng(K * 1000 + hf)
+    psf = rng.uniform(0, 1, (n, K, K)).astype(np.float32)
+    psf /= psf.sum(axis=(1, 2), keepdims=True)
+    hl, wl = hf * sr, wf * sr
+    x = rng.uniform(0, 100, (hl, wl)).astype(np.float32)
+    r = rng.normal(0, 1, (n, hf, wf)).astype(np.float32)
+    p = em.Problem.make(n, hf, wf, K, sr=sr)
+    m = em.forward_op(p, to_dev(psf), to_dev(x)).cpu().numpy()
+    s = em.adjoint_op(p, to_dev(psf), to_dev(r)).cpu().numpy()
+    for t in range(n):
+        mo = oracle.forward(psf[t], x, sr)
+        so = oracle.adjoint(psf[t], r[t], sr)
+        assert rel_l2(m[t], mo) < 2e-6
+        assert np.abs(m[t] - mo).max() <= 1e-5 * np.abs(mo).max()
+        assert rel_l2(s[t], so) < 2e-6
+        assert np.abs(s[t] - so).max() <= 1e-5 * np.abs(so).max()
+
+
+# ---------------------------------------------------------------------------
+# full EM runs vs the oracle
+# ---------------------------------------------------------------------------
+
+def _compare_run(prob, n_iter, x0, tag):
+    log(f"run {tag}: frames {prob.y.shape} K={prob.K} sr={prob.sr} iters={n_iter}")
+    xg, trg = gpu_run(prob.y, prob.v, prob.psf, prob.sr, n_iter, x0=x0)
+    xo, tro, _ = oracle.run(prob.y, prob.v, prob.psf, x0, n_iter, prob.sr, trace=True)
+    err = rel_l2(xg, xo)
+    llerr = np.abs(trg - tro).max() / np.abs(tro).max()
+    log(f"  rel L2(x) = {err:.3e}   max rel err(loglik) = {llerr:.3e}")
+    assert err <= X_TOL
+    assert llerr <= LL_TOL
+    assert (xg >= 0).all()
+    assert (np.diff(trg) >= -1e-9 * np.abs(trg[1:])).all()
+    return xg, trg
+
+
+def test_c1_workload_full_parity():
+    p = synth.make_problem("c1")
+    x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v), np.float32)
+    _compare_run(p, p.n_iter, x0, "c1")
+
+
+def test_c2_recipe_ragged_parity():
+    p = synth.make_problem("c2", H=200, W=173, n=3)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v), 1.0), seed=7)
+    _compare_run(p, 10, x0, "c2-ragged")
+
+
+def test_c3_recipe_streaks_parity():
+    p = synth.make_problem("c3", H=130, W=257, n=5)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v), 1.0), seed=8)
+    _compare_run(p, 8, x0, "c3-streaks")
+
+
+def test_c4_recipe_super_resolution_parity():
+    p = synth.make_problem("c4", H=192, W=134, n=3)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v, 2), 0.25), seed=9)
+    _compare_run(p, 10, x0, "c4-sr2")
+
+
+def test_flat_start_matches_oracle_rule():
+    p = synth.make_problem("c2", H=96, W=80, n=2)
+    xg, _ = gpu_run(p.y, p.v, p.psf, 1, 0, x0=None, trace=False)
+    assert np.allclose(xg, oracle.flat_x0(p.y, p.v), rtol=1e-6)
+    p2 = synth.make_problem("c4", H=96, W=80, n=2)
+    xg2, _ = gpu_run(p2.y, p2.v, p2.psf, 2, 0, x0=None, trace=False)
+    assert np.allclose(xg2, oracle.flat_x0(p2.y, p2.v, 2), rtol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# closed forms on the GPU (delta PSFs)
+# ---------------------------------------------------------------------------
+
+def test_delta_psf_weighted_mean_on_gpu():
+    n, H, W, K = 4, 70, 90, 43
+    rng = np.random.default_rng(3)
+    psf = np.zeros((n, K, K), np.float32)
+    psf[:, K // 2, K // 2] = 1.0
+    y = rng.normal(30, 40, (n, H, W)).astype(np.float32)
+    v = rng.uniform(5, 50, (n, H, W)).astype(np.float32)
+    mk = rng.uniform(size=(n, H, W)) < 0.2
+    mk[:, 5, 7] = True
+    y[mk] = np.nan
+    v[mk] = np.inf
+    x0 = synth.positive_start((H, W), 10.0, seed=4)
+    xg, _ = gpu_run(y, v, psf, 1, 3, x0=x0, trace=False)
+    u = np.where(mk, 0.0, 1.0 / v.astype(np.float64))
+    yy = np.where(mk, 0.0, y.astype(np.float64))
+    su = u.sum(0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = np.maximum((u * yy).sum(0) / su, 0.0)
+    expect = np.where(su > 0, mean, x0)
+    assert rel_l2(xg, expect) < 1e-6
+    assert xg[5, 7] == x0[5, 7]
+
+
+# ---------------------------------------------------------------------------
+# edge cases and errors
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("sr,K,hf,wf,n", [(1, 1, 1, 1, 1), (1, 43, 1, 1, 2), (1, 3, 2, 67, 1),
+                                          (2, 1, 1, 1, 1), (2, 43, 1, 3, 3), (1, 43, 64, 64, 1)])
+def test_tiny_and_degenerate_shapes(sr, K, hf, wf, n):
+    log(f"tiny sr={sr} K={K} frame={hf}x{wf} n={n}")
+    rng = np.random.default_rng(K + hf + wf)
+    psf = rng.uniform(0.1, 1, (n, K, K)).astype(np.float32)
+    y = rng.uniform(1, 50, (n, hf, wf)).astype(np.float32)
+    v = rng.uniform(1, 5, (n, hf, wf)).astype(np.float32)
+    x0 = synth.positive_start((hf * sr, wf * sr), 5.0, seed=1)
+    xg, trg = gpu_run(y, v, psf, sr, 5, x0=x0)
+    xo, tro, _ = oracle.run(y, v, psf, x0, 5, sr, trace=True)
+    assert rel_l2(xg, xo) <= X_TOL
+    assert np.abs(trg - tro).max() <= LL_TOL * np.abs(tro).max()
+
+
+def test_zero_iterations_and_zero_start():
+    p = synth.make_problem("c1", H=64, W=64, n=2)
+    x0 = synth.positive_start(p.latent_shape, 5.0, seed=2)
+    x0[10:20, 10:20] = 0.0
+    xg, _ = gpu_run(p.y, p.v, p.psf, 1, 0, x0=x0, trace=False)
+    assert np.array_equal(xg, x0.astype(np.float64))
+    xg, _ = gpu_run(p.y, p.v, p.psf, 1, 4, x0=x0, trace=False)
+    assert (xg[10:20, 10:20] == 0).all()
+    xo = oracle.run(p.y, p.v, p.psf, x0, 4)
+    assert rel_l2(xg, xo) <= X_TOL
+
+
+def test_invalid_inputs_are_rejected():
+    import torch
+    em = _em()
+    p = synth.make_problem("c1", H=32, W=32, n=2)
+    prob = em.Problem.make(2, 32, 32, 15)
+    x = torch.empty((32, 32), dtype=torch.float32, device="cuda")
+
+    def init(y=p.y, v=p.v, psf=p.psf, x0=None, prob=prob, ws=None):
+        return em.Context(prob, to_dev(y), to_dev(v), to_dev(psf), x,
+                          x0=None if x0 is None else to_dev(x0), workspace=ws)
+
+    for bad in (0.0, -2.0, np.nan, -np.inf):
+        vb = p.v.copy()
+        vb[1, 3, 4] = bad
+        with pytest.raises(em.EMError) as ei:
+            init(v=vb)
+        assert ei.value.code == em.EINVAL
+    yb = p.y.copy()
+    yb[0, 0, 0] = np.inf
+    with pytest.raises(em.EMError):
+        init(y=yb)
+    pb = p.psf.copy()
+    pb[0, 7, 7] = -1e-3
+    with pytest.raises(em.EMError):
+        init(psf=pb)
+    with pytest.raises(em.EMError):
+        init(x0=np.full((32, 32), -1.0, np.float32))
+    with pytest.raises(em.EMError) as ei:
+        init(ws=torch.empty(1024, dtype=torch.uint8, device="cuda"))
+    assert ei.value.code == em.ENOMEM
+    with pytest.raises(em.EMError) as ei:
+        init(prob=em.Problem.make(2, 32, 32, 15, precision=em.FP16_SPLIT))
+    assert ei.value.code == em.ENOTSUP
+    # masked pixels with NaN exposures are fine and never read as numbers
+    y2 = p.y.copy()
+    v2 = p.v.copy()
+    y2[0, 1, 1] = np.nan
+    v2[0, 1, 1] = np.inf
+    init(y=y2, v=v2).close()
+
+
+def test_masked_values_do_not_matter_bitwise():
+    p = synth.make_problem("c2", H=96, W=100, n=3)
+    x0 = synth.positive_start(p.latent_shape, 20.0, seed=5)
+    a, _ = gpu_run(p.y, p.v, p.psf, 1, 6, x0=x0, trace=False)
+    y2 = p.y.copy()
+    y2[~np.isfinite(p.v)] = 12345.0
+    b, _ = gpu_run(y2, p.v, p.psf, 1, 6, x0=x0, trace=False)
+    assert np.array_equal(a, b)
+
+
+def test_deterministic_bitwise():
+    p = synth.make_problem("c2", H=160, W=96, n=4)
+    x0 = synth.positive_start(p.latent_shape, 20.0, seed=6)
+    a, ta = gpu_run(p.y, p.v, p.psf, 1, 5, x0=x0)
+    b, tb = gpu_run(p.y, p.v, p.psf, 1, 5, x0=x0)
+    assert np.array_equal(a, b) and np.array_equal(ta, tb)
+
+
+def test_loglik_and_terms_match_oracle():
+    import torch
+    em = _em()
+    p = synth.make_problem("c2", H=120, W=88, n=3)
+    x0 = synth.positive_start(p.latent_shape, 20.0, seed=7)
+    prob = em.Problem.make(3, 120, 88, 43)
+    x = torch.empty((120, 88), dtype=torch.float32, device="cuda")
+    ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+    ll = ctx.loglik()
+    llo = oracle.loglik(p.y, p.v, p.psf, x0)
+    assert abs(ll - llo) <= LL_TOL * abs(llo)
+    B, Dn = ctx.terms()
+    Bo = oracle.numerator(p.y, p.v, p.psf)
+    Do = oracle.denominator(p.y, p.v, p.psf, x0)
+    assert rel_l2(B.cpu().numpy(), Bo) < 1e-5
+    assert rel_l2(Dn.cpu().numpy(), Do) < 2e-6
+    ctx.close()
+
+
+def test_iterate_tol_stops():
+    import torch
+    em = _em()
+    p = synth.make_problem("c1", H=64, W=64, n=2)
+    prob = em.Problem.make(2, 64, 64, 15)
+    x = torch.empty((64, 64), dtype=torch.float32, device="cuda")
+    ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x)
+    k, rc, tr = ctx.iterate_tol(500, 3e-3, check_every=5, trace=True)
+    assert 0 < k < 500 and k % 5 == 0
+    assert rc[-5:].min() < 3e-3 and (rc[:-5] >= 3e-3).all()
+    x0 = np.full((64, 64), oracle.flat_x0(p.y, p.v), np.float32)
+    _, _, rco = oracle.run(p.y, p.v, p.psf, x0, k, relchange=True)
+    np.testing.assert_allclose(rc, rco, rtol=1e-4)
+    ctx.close()
