@@ -155,6 +155,19 @@ int em_loglik(em_ctx* ctx, double* out);
  */
 int em_terms(em_ctx* ctx, float* B_out, float* Dn_out);
 
+/*
+ * Measurement: runs n_iter iterations like em_iterate (no trace) and times
+ * every kernel launch of the iteration with HIP events recorded on the job's
+ * stream.  Writes the mean duration in milliseconds per launch of
+ *   phase_ms[0]  the forward kernel  (F_t x, weighting; all frames)
+ *   phase_ms[1]  the adjoint kernel  (F_t^T r, frame sum; fused update if
+ *                                     the adjoint is not split over frame groups)
+ *   phase_ms[2]  the separate update kernel (0 when fused)
+ *   phase_ms[3]  the whole iteration
+ * Synchronous.
+ */
+int em_profile(em_ctx* ctx, int32_t n_iter, double* phase_ms);
+
 /* Wait for the job's stream; reports asynchronous device errors. */
 int em_sync(em_ctx* ctx);
 

@@ -460,6 +460,54 @@ int em_terms(em_ctx* c, float* B_out, float* Dn_out) {
   return EM_OK;
 }
 
+int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
+  if (!c || !phase_ms) return fail(EM_EINVAL, "NULL argument");
+  if (n_iter < 1) return fail(EM_EINVAL, "n_iter must be >= 1");
+  hipEvent_t ev[4];
+  for (int i = 0; i < 4; ++i) EM_HIP(hipEventCreate(&ev[i]));
+  double acc[4] = {0, 0, 0, 0};
+  int rc = EM_OK;
+  for (int k = 0; k < n_iter && rc == EM_OK; ++k) {
+    EM_HIP(hipEventRecord(ev[0], c->stream));
+    if ((rc = forward_pass(c, true, false))) break;
+    EM_HIP(hipEventRecord(ev[1], c->stream));
+    AdjLaunch a{};
+    a.in = c->r;
+    a.tab = c->tab;
+    a.n = c->g.n;
+    a.Hf = c->g.Hf;
+    a.Wf = c->g.Wf;
+    a.Hl = c->g.Hl;
+    a.Wl = c->g.Wl;
+    a.fpg = c->pl.adj_fpg;
+    const bool fused = c->pl.adj_groups == 1;
+    a.fused = fused ? 1 : 0;
+    a.x = c->x;
+    a.B = c->B;
+    a.plane = c->planes;
+    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+    EM_HIP(hipEventRecord(ev[2], c->stream));
+    if (!fused)
+      EM_HIP(launch_update(c->planes, c->pl.adj_groups, c->g.Nl, c->B, c->x, nullptr,
+                           c->pl.upd_blocks, c->stream));
+    EM_HIP(hipEventRecord(ev[3], c->stream));
+    EM_HIP(hipEventSynchronize(ev[3]));
+    float ms;
+    EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    acc[0] += ms;
+    EM_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
+    acc[1] += ms;
+    EM_HIP(hipEventElapsedTime(&ms, ev[2], ev[3]));
+    acc[2] += fused ? 0.0 : ms;
+    EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[3]));
+    acc[3] += ms;
+  }
+  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  if (rc) return rc;
+  for (int i = 0; i < 4; ++i) phase_ms[i] = acc[i] / n_iter;
+  return EM_OK;
+}
+
 int em_sync(em_ctx* c) {
   if (!c) return fail(EM_EINVAL, "ctx is NULL");
   EM_HIP(hipStreamSynchronize(c->stream));

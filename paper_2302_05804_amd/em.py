@@ -69,6 +69,7 @@ _sig = {
                                       ctypes.POINTER(ctypes.c_int32), _P, _P]),
     "em_loglik": (ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double)]),
     "em_terms": (ctypes.c_int, [_P, _P, _P]),
+    "em_profile": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "em_sync": (ctypes.c_int, [_P]),
     "em_destroy": (ctypes.c_int, [_P]),
     "em_forward_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -187,6 +188,12 @@ class Context:
         Dn = torch.empty_like(B)
         _check(_lib.em_terms(self._h, _dev_ptr(B, "B"), _dev_ptr(Dn, "Dn")), "em_terms")
         return B, Dn
+
+    def profile(self, n_iter: int):
+        """Mean per-launch ms of (forward, adjoint, separate update, iteration)."""
+        out = np.zeros(4, np.float64)
+        _check(_lib.em_profile(self._h, int(n_iter), out.ctypes.data_as(_P)), "em_profile")
+        return out
 
     def sync(self):
         _check(_lib.em_sync(self._h), "em_sync")
