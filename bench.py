@@ -101,7 +101,7 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16split", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=128)
     ap.add_argument("--cpu-iters", type=int, default=2)
@@ -130,7 +130,7 @@ def main() -> int:
         f"in {time.perf_counter() - t0:.1f} s")
 
     n, hf, wf = prob.y.shape
-    precision = {"fp32": em.FP32}[args.precision]
+    precision = {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "bf16": em.BF16}[args.precision]
     p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=precision)
     y = torch.from_numpy(prob.y).to(dev)
     v = torch.from_numpy(prob.v).to(dev)
@@ -170,10 +170,11 @@ def main() -> int:
     dom = 0 if phases[0] >= phases[1] else 1
     dom_name = ["forward", "adjoint"][dom]
     achieved = flops_per_launch / (phases[dom] / 1e3) / 1e12
-    peak = PEAKS_TFLOPS["fp32"]
+    mfma = args.precision != "fp32"
+    peak = PEAKS_TFLOPS["bf16" if mfma else "fp32"]
     kernel_key = f"{dom_name}-{args.workload}-{args.precision}"
     roofline = {
-        "bound": "alu",
+        "bound": "mfma" if mfma else "alu",
         "kernel": dom_name,
         "achieved": round(achieved, 2),
         "peak": peak,
@@ -196,7 +197,8 @@ def main() -> int:
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": {"fp32": "f32", "bf16split": "bf16x3 (hi+lo split), f32 accumulate",
+                  "bf16": "bf16, f32 accumulate"}[args.precision],
         "data": "synthetic (seeded generator shaped like the HSC testbed)",
         "config": {
             "workload": WORKLOADS[args.workload],

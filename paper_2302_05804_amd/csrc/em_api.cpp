@@ -79,16 +79,21 @@ bool make_geometry(const void* problem, Geometry* g, const char** why) {
 
 Plan make_plan(const Geometry& g) {
   Plan pl{};
-  const int target = 1024;  // ~4 workgroups per compute unit on 256 CUs
+  // ~4 workgroups per compute unit on 256 CUs (matrix-core kernels: one
+  // workgroup fills a compute unit's LDS, aim for 2 rounds)
+  const int target = uses_mfma(g) ? 512 : 1024;
   pl.fwd_variant = 0;
-  pl.fwd_tiles = (int)(cdiv(g.Wf, fwd_tile_w(g)) * cdiv(g.Hf, fwd_tile_h(g)));
+  const bool mf = uses_mfma(g);
+  pl.fwd_tiles = mf ? (int)(cdiv(g.Wf, mfma_tile_w()) * cdiv(g.Hf, mfma_tile_h()))
+                    : (int)(cdiv(g.Wf, fwd_tile_w(g)) * cdiv(g.Hf, fwd_tile_h(g)));
   int fg = (int)std::min<int64_t>(g.n, cdiv(target, pl.fwd_tiles));
   fg = std::max(fg, 1);
   pl.fwd_fpg = (int)cdiv(g.n, fg);
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.adj_variant = 0;
-  pl.adj_tiles = (int)(cdiv(g.Wl, adj_tile_w(g)) * cdiv(g.Hl, adj_tile_h(g)));
-  if (pl.adj_tiles >= target / 2) {
+  pl.adj_tiles = mf ? (int)(cdiv(g.Wl, mfma_tile_w()) * cdiv(g.Hl, mfma_tile_h()))
+                    : (int)(cdiv(g.Wl, adj_tile_w(g)) * cdiv(g.Hl, adj_tile_h(g)));
+  if (pl.adj_tiles >= (mf ? target / 4 : target / 2)) {
     pl.adj_groups = 1;
     pl.adj_fpg = g.n;
   } else {
@@ -121,6 +126,9 @@ Layout make_layout(const Geometry& g, const Plan& pl) {
   L.B = take((size_t)g.Nl * sizeof(float));
   L.planes = take(G > 1 ? (size_t)G * g.Nl * sizeof(float) : 0);
   L.tab = take((size_t)g.n * g.KC * TAB_LD * sizeof(float));
+  const size_t mtab = uses_mfma(g) ? (size_t)g.n * g.KT * 4 * 64 * 8 * sizeof(uint16_t) : 0;
+  L.mtab_fwd = take(mtab);
+  L.mtab_adj = take(mtab);
   L.part_ll = take((size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double));
   L.part_rc = take((size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double));
   L.part_prep = take((size_t)3 * pl.prep_blocks * sizeof(double));
@@ -178,6 +186,8 @@ struct em_ctx {
   float* B;
   float* planes;
   float* tab;
+  void* mtab_fwd;
+  void* mtab_adj;
   double* part_ll;
   double* part_rc;
   double* part_prep;
@@ -195,6 +205,8 @@ static void bind_views(em_ctx* c) {
   c->B = reinterpret_cast<float*>(w + L.B);
   c->planes = reinterpret_cast<float*>(w + L.planes);
   c->tab = reinterpret_cast<float*>(w + L.tab);
+  c->mtab_fwd = w + L.mtab_fwd;
+  c->mtab_adj = w + L.mtab_adj;
   c->part_ll = reinterpret_cast<double*>(w + L.part_ll);
   c->part_rc = reinterpret_cast<double*>(w + L.part_rc);
   c->part_prep = reinterpret_cast<double*>(w + L.part_prep);
@@ -222,21 +234,35 @@ size_t em_workspace_bytes(const em_problem* p) {
 
 }  // extern "C"
 
-// Adjoint over frames of `in` (n x Nf) into B-like output `out` (Nl floats),
-// never applying the update.
+// Adjoint of every frame of `in` (n x Nf), summed over frames, into `out`
+// (Nl floats); never applies the update.
 static int adjoint_sum(em_ctx* c, const float* in, float* out) {
-  AdjLaunch a{};
-  a.in = in;
-  a.tab = c->tab;
-  a.n = c->g.n;
-  a.Hf = c->g.Hf;
-  a.Wf = c->g.Wf;
-  a.Hl = c->g.Hl;
-  a.Wl = c->g.Wl;
-  a.fpg = c->pl.adj_fpg;
-  a.fused = 0;
-  a.plane = c->pl.adj_groups > 1 ? c->planes : out;
-  EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+  float* dst = c->pl.adj_groups > 1 ? c->planes : out;
+  if (uses_mfma(c->g)) {
+    MfmaLaunch m{};
+    m.in = in;
+    m.tab = c->mtab_adj;
+    m.plane = dst;
+    m.n = c->g.n;
+    m.H = c->g.Hl;
+    m.W = c->g.Wl;
+    m.fpg = c->pl.adj_fpg;
+    m.fused = 0;
+    EM_HIP(launch_mfma(c->g, 1, c->pl.adj_tiles, c->pl.adj_groups, m, c->stream));
+  } else {
+    AdjLaunch a{};
+    a.in = in;
+    a.tab = c->tab;
+    a.n = c->g.n;
+    a.Hf = c->g.Hf;
+    a.Wf = c->g.Wf;
+    a.Hl = c->g.Hl;
+    a.Wl = c->g.Wl;
+    a.fpg = c->pl.adj_fpg;
+    a.fused = 0;
+    a.plane = dst;
+    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+  }
   if (c->pl.adj_groups > 1)
     EM_HIP(launch_sum_planes(c->planes, c->pl.adj_groups, c->g.Nl, out, c->stream));
   return EM_OK;
@@ -244,6 +270,21 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
 
 // Forward pass at the current iterate: r = u F x (if write_r) and loglik partials.
 static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
+  if (uses_mfma(c->g)) {
+    MfmaLaunch m{};
+    m.in = c->x;
+    m.tab = c->mtab_fwd;
+    m.u = c->u;
+    m.y = c->y;
+    m.out = write_r ? c->r : nullptr;
+    m.part = loglik ? c->part_ll : nullptr;
+    m.n = c->g.n;
+    m.H = c->g.Hf;
+    m.W = c->g.Wf;
+    m.fpg = c->pl.fwd_fpg;
+    EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_tiles, c->pl.fwd_groups, m, c->stream));
+    return EM_OK;
+  }
   FwdLaunch f{};
   f.x = c->x;
   f.tab = c->tab;
@@ -261,35 +302,69 @@ static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
   return EM_OK;
 }
 
+// Adjoint of r summed over frames; with a single frame group the
+// multiplicative update is fused into its epilogue, else it writes the partial
+// planes (the update then runs separately, update_launch).
+static int adjoint_launch(em_ctx* c, double* part_rc) {
+  const bool fused = c->pl.adj_groups == 1;
+  if (uses_mfma(c->g)) {
+    MfmaLaunch m{};
+    m.in = c->r;
+    m.tab = c->mtab_adj;
+    m.n = c->g.n;
+    m.H = c->g.Hl;
+    m.W = c->g.Wl;
+    m.fpg = c->pl.adj_fpg;
+    m.fused = fused ? 1 : 0;
+    m.x = c->x;
+    m.B = c->B;
+    m.part = fused ? part_rc : nullptr;
+    m.plane = c->planes;
+    EM_HIP(launch_mfma(c->g, 1, c->pl.adj_tiles, c->pl.adj_groups, m, c->stream));
+  } else {
+    AdjLaunch a{};
+    a.in = c->r;
+    a.tab = c->tab;
+    a.n = c->g.n;
+    a.Hf = c->g.Hf;
+    a.Wf = c->g.Wf;
+    a.Hl = c->g.Hl;
+    a.Wl = c->g.Wl;
+    a.fpg = c->pl.adj_fpg;
+    a.fused = fused ? 1 : 0;
+    a.x = c->x;
+    a.B = c->B;
+    a.part = fused ? part_rc : nullptr;
+    a.plane = c->planes;
+    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+  }
+  return EM_OK;
+}
+
+static int update_launch(em_ctx* c, double* part_rc) {
+  EM_HIP(launch_update(c->planes, c->pl.adj_groups, c->g.Nl, c->B, c->x, part_rc,
+                       c->pl.upd_blocks, c->stream));
+  return EM_OK;
+}
+
+// Adjoint + update; *n_rc = number of change partials written.
+static int adjoint_update(em_ctx* c, double* part_rc, int* n_rc) {
+  int rc = adjoint_launch(c, part_rc);
+  if (rc) return rc;
+  if (c->pl.adj_groups == 1) {
+    *n_rc = c->pl.adj_tiles;
+    return EM_OK;
+  }
+  *n_rc = c->pl.upd_blocks;
+  return update_launch(c, part_rc);
+}
+
 // One EM iteration (Eq. (2)); optional FP64 loglik / relative-change bookkeeping.
 static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
   int rc = forward_pass(c, true, loglik);
   if (rc) return rc;
-  AdjLaunch a{};
-  a.in = c->r;
-  a.tab = c->tab;
-  a.n = c->g.n;
-  a.Hf = c->g.Hf;
-  a.Wf = c->g.Wf;
-  a.Hl = c->g.Hl;
-  a.Wl = c->g.Wl;
-  a.fpg = c->pl.adj_fpg;
-  int n_rc;
-  if (c->pl.adj_groups == 1) {
-    a.fused = 1;
-    a.x = c->x;
-    a.B = c->B;
-    a.part = relchange ? c->part_rc : nullptr;
-    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
-    n_rc = c->pl.adj_tiles;
-  } else {
-    a.fused = 0;
-    a.plane = c->planes;
-    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
-    EM_HIP(launch_update(c->planes, c->pl.adj_groups, c->g.Nl, c->B, c->x,
-                         relchange ? c->part_rc : nullptr, c->pl.upd_blocks, c->stream));
-    n_rc = c->pl.upd_blocks;
-  }
+  int n_rc = 0;
+  if ((rc = adjoint_update(c, relchange ? c->part_rc : nullptr, &n_rc))) return rc;
   if (loglik || relchange) {
     EM_HIP(launch_finalize_iter(loglik ? c->part_ll : nullptr, c->pl.fwd_tiles * c->pl.fwd_groups,
                                 relchange ? c->part_rc : nullptr, n_rc, c->scalars, c->trace_ll,
@@ -307,7 +382,10 @@ int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, c
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
-  if (g.precision != EM_FP32) return fail(EM_ENOTSUP, "precision %d not provided", g.precision);
+  if (g.precision == EM_FP16_SPLIT)
+    return fail(EM_ENOTSUP, "precision %d not provided", g.precision);
+  if (uses_mfma(g) && g.sr != 1)
+    return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
   if (g.weight_mode != EM_W_ADJOINT)
     return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
   const Plan pl = make_plan(g);
@@ -360,6 +438,9 @@ int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, c
     return bail(fail(EM_EDEVICE, "prep: %s", hipGetErrorString(e)));
   if ((e = launch_psf_tables(g, psf, c->tab, c->counters + 4, c->stream)) != hipSuccess)
     return bail(fail(EM_EDEVICE, "psf tables: %s", hipGetErrorString(e)));
+  if (uses_mfma(g) &&
+      (e = launch_mfma_tables(g, psf, c->mtab_fwd, c->mtab_adj, c->stream)) != hipSuccess)
+    return bail(fail(EM_EDEVICE, "mfma tables: %s", hipGetErrorString(e)));
   if ((rc = adjoint_sum(c, c->r, c->B))) return bail(rc);
   if ((e = launch_finalize_prep(c->part_prep, pl.prep_blocks, c->scalars, g.sr, c->stream)) !=
       hipSuccess)
@@ -467,29 +548,14 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
   for (int i = 0; i < 4; ++i) EM_HIP(hipEventCreate(&ev[i]));
   double acc[4] = {0, 0, 0, 0};
   int rc = EM_OK;
+  const bool fused = c->pl.adj_groups == 1;
   for (int k = 0; k < n_iter && rc == EM_OK; ++k) {
     EM_HIP(hipEventRecord(ev[0], c->stream));
     if ((rc = forward_pass(c, true, false))) break;
     EM_HIP(hipEventRecord(ev[1], c->stream));
-    AdjLaunch a{};
-    a.in = c->r;
-    a.tab = c->tab;
-    a.n = c->g.n;
-    a.Hf = c->g.Hf;
-    a.Wf = c->g.Wf;
-    a.Hl = c->g.Hl;
-    a.Wl = c->g.Wl;
-    a.fpg = c->pl.adj_fpg;
-    const bool fused = c->pl.adj_groups == 1;
-    a.fused = fused ? 1 : 0;
-    a.x = c->x;
-    a.B = c->B;
-    a.plane = c->planes;
-    EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
+    if ((rc = adjoint_launch(c, nullptr))) break;
     EM_HIP(hipEventRecord(ev[2], c->stream));
-    if (!fused)
-      EM_HIP(launch_update(c->planes, c->pl.adj_groups, c->g.Nl, c->B, c->x, nullptr,
-                           c->pl.upd_blocks, c->stream));
+    if (!fused && (rc = update_launch(c, nullptr))) break;
     EM_HIP(hipEventRecord(ev[3], c->stream));
     EM_HIP(hipEventSynchronize(ev[3]));
     float ms;
@@ -551,6 +617,20 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
   int* flags = reinterpret_cast<int*>(w + L.counters);
   EM_HIP(launch_reset_counters(flags, s));
   EM_HIP(launch_psf_tables(g, psf, tab, flags, s));
+  if (uses_mfma(g)) {
+    if (g.sr != 1) return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
+    EM_HIP(launch_mfma_tables(g, psf, w + L.mtab_fwd, w + L.mtab_adj, s));
+    MfmaLaunch mm{};
+    mm.in = x;
+    mm.tab = w + L.mtab_fwd;
+    mm.out = m;
+    mm.n = g.n;
+    mm.H = g.Hf;
+    mm.W = g.Wf;
+    mm.fpg = pl.fwd_fpg;
+    EM_HIP(launch_mfma(g, 0, pl.fwd_tiles, pl.fwd_groups, mm, s));
+    return EM_OK;
+  }
   FwdLaunch f{};
   f.x = x;
   f.tab = tab;
@@ -586,6 +666,21 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
   Plan per = pl;  // one frame per group: group t writes plane t = F_t^T r_t
   per.adj_fpg = 1;
   per.adj_groups = g.n;
+  if (uses_mfma(g)) {
+    if (g.sr != 1) return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
+    EM_HIP(launch_mfma_tables(g, psf, w + L.mtab_fwd, w + L.mtab_adj, s));
+    MfmaLaunch mm{};
+    mm.in = r;
+    mm.tab = w + L.mtab_adj;
+    mm.plane = sout;
+    mm.n = g.n;
+    mm.H = g.Hl;
+    mm.W = g.Wl;
+    mm.fpg = 1;
+    mm.fused = 0;
+    EM_HIP(launch_mfma(g, 1, pl.adj_tiles, g.n, mm, s));
+    return EM_OK;
+  }
   AdjLaunch a{};
   a.in = r;
   a.tab = tab;

@@ -13,6 +13,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include "em.h"
+
 namespace em {
 
 // Supported padded kernel sizes.  A smaller odd K is zero-padded symmetrically
@@ -68,9 +70,14 @@ struct Plan {
 
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct Layout {
-  size_t u, r, B, planes, tab, part_ll, part_rc, part_prep, scalars, trace_ll, trace_rc,
-      counters, total;
+  size_t u, r, B, planes, tab, mtab_fwd, mtab_adj, part_ll, part_rc, part_prep, scalars,
+      trace_ll, trace_rc, counters, total;
 };
+
+// true when the convolutions of geometry g run on the matrix cores
+inline bool uses_mfma(const Geometry& g) {
+  return g.precision == EM_BF16_SPLIT || g.precision == EM_BF16;
+}
 
 bool make_geometry(const void* problem, Geometry* g, const char** why);
 Plan make_plan(const Geometry& g);
@@ -97,6 +104,27 @@ struct AdjLaunch {
   int n, Hf, Wf, Hl, Wl, fpg;
   int fused;           // 1 => x update in the epilogue (G == 1)
 };
+
+// Matrix-core correlation kernels (em_mfma.hip), sr = 1.
+struct MfmaLaunch {
+  const float* in;     // forward: x; adjoint: r images (n x H x W)
+  const void* tab;     // Toeplitz fragment tables of the direction
+  const float* u;      // forward: weights (nullptr => raw output)
+  const float* y;      // forward: exposures (loglik)
+  float* out;          // forward output
+  double* part;        // forward: loglik partials; adjoint: change partials
+  float* plane;        // adjoint output planes
+  float* x;            // adjoint fused update
+  const float* B;
+  int n, H, W, fpg;
+  int fused;
+};
+hipError_t launch_mfma(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a,
+                       hipStream_t s);
+hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
+                              hipStream_t s);
+int mfma_tile_h();
+int mfma_tile_w();
 
 hipError_t launch_forward(const Geometry& g, const Plan& pl, const FwdLaunch& a, hipStream_t s);
 hipError_t launch_adjoint(const Geometry& g, const Plan& pl, const AdjLaunch& a, hipStream_t s);

@@ -1,0 +1,118 @@
+"""Parity of the BF16 matrix-core path (hi+lo split operands) with the FP64 oracle.
+
+Error model of one correlation output o = sum_k g_k in_k computed with split
+operands v = hi + lo (+ delta): each product loses the lo.lo term and the
+representation remainders, at most 3 * 2^-16 |g_k in_k|; FP32 accumulation adds
+at most ~(#terms) 2^-24 sum |g_k in_k| in the worst case.  The operator tests
+bound |o_gpu - o| <= 1e-4 * sum_k |g_k||in_k| element by element (computed by
+the oracle on absolute values).  Whole EM runs must stay within rel L2 1e-3 of
+the oracle's iterate (the accuracy bar of the mixed-precision form).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_05804_amd import synth
+from tests.gpu_common import gpu_run, log, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+OP_EPS = 1e-4
+SPLIT_X_TOL = 1e-3
+
+
+def _em():
+    from paper_2302_05804_amd import em
+    return em
+
+
+@pytest.mark.parametrize("K,h,w,n", [(43, 150, 131, 2), (15, 70, 260, 3), (43, 256, 128, 1),
+                                     (7, 33, 40, 2), (43, 5, 3, 1), (43, 129, 257, 1)])
+def test_split_operators_elementwise_bound(K, h, w, n):
+    em = _em()
+    log(f"mfma operators K={K} {h}x{w} n={n}")
+    rng = np.random.default_rng(K * 7 + h)
+    psf = rng.uniform(0, 1, (n, K, K)).astype(np.float32)
+    psf /= psf.sum(axis=(1, 2), keepdims=True)
+    x = rng.gamma(0.5, 200.0, (h, w)).astype(np.float32)
+    r = rng.normal(0, 1, (n, h, w)).astype(np.float32)
+    p = em.Problem.make(n, h, w, K, precision=em.BF16_SPLIT)
+    m = em.forward_op(p, to_dev(psf), to_dev(x)).cpu().numpy()
+    s = em.adjoint_op(p, to_dev(psf), to_dev(r)).cpu().numpy()
+    for t in range(n):
+        mo = oracle.forward(psf[t], x)
+        so = oracle.adjoint(psf[t], r[t])
+        mb = oracle.forward(np.abs(psf[t]), np.abs(x))
+        sb = oracle.adjoint(np.abs(psf[t]), np.abs(r[t]))
+        assert (np.abs(m[t] - mo) <= OP_EPS * mb + 1e-30).all()
+        assert (np.abs(s[t] - so) <= OP_EPS * sb + 1e-30).all()
+        log(f"  t={t}: rel L2 fwd {rel_l2(m[t], mo):.2e} adj {rel_l2(s[t], so):.2e}")
+
+
+def test_plain_bf16_operator_is_coarser():
+    em = _em()
+    rng = np.random.default_rng(5)
+    psf = rng.uniform(0, 1, (1, 43, 43)).astype(np.float32)
+    psf /= psf.sum()
+    x = rng.uniform(0, 100, (96, 96)).astype(np.float32)
+    ps = em.Problem.make(1, 96, 96, 43, precision=em.BF16_SPLIT)
+    pb = em.Problem.make(1, 96, 96, 43, precision=em.BF16)
+    mo = oracle.forward(psf[0], x)
+    es = rel_l2(em.forward_op(ps, to_dev(psf), to_dev(x)).cpu().numpy()[0], mo)
+    eb = rel_l2(em.forward_op(pb, to_dev(psf), to_dev(x)).cpu().numpy()[0], mo)
+    log(f"forward rel L2: split {es:.2e}, plain bf16 {eb:.2e}")
+    assert es < 1e-5 and eb > 10 * es
+
+
+def _run_both(prob, n_iter, x0, precision):
+    em = _em()
+    xg, trg = gpu_run(prob.y, prob.v, prob.psf, prob.sr, n_iter, x0=x0, precision=precision)
+    xo, tro, _ = oracle.run(prob.y, prob.v, prob.psf, x0, n_iter, prob.sr, trace=True)
+    err = rel_l2(xg, xo)
+    llerr = float(np.abs(trg - tro).max() / np.abs(tro).max())
+    return err, llerr, xg, trg
+
+
+def test_c1_split_full_run():
+    em = _em()
+    p = synth.make_problem("c1")
+    x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v), np.float32)
+    err, llerr, xg, trg = _run_both(p, p.n_iter, x0, em.BF16_SPLIT)
+    log(f"c1 bf16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= SPLIT_X_TOL
+    assert (xg >= 0).all()
+    assert (np.diff(trg) >= -1e-7 * np.abs(trg[1:])).all()
+
+
+def test_c2_recipe_split_ragged():
+    em = _em()
+    p = synth.make_problem("c2", H=200, W=173, n=3)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v), 1.0), seed=7)
+    err, llerr, xg, _ = _run_both(p, 10, x0, em.BF16_SPLIT)
+    log(f"c2-ragged bf16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= SPLIT_X_TOL and (xg >= 0).all()
+
+
+def test_c3_recipe_split_multi_tile():
+    em = _em()
+    p = synth.make_problem("c3", H=300, W=260, n=4)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v), 1.0), seed=8)
+    err, llerr, xg, _ = _run_both(p, 6, x0, em.BF16_SPLIT)
+    log(f"c3-tiles bf16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= SPLIT_X_TOL and (xg >= 0).all()
+
+
+def test_split_deterministic_and_sr2_unsupported():
+    import torch
+    em = _em()
+    p = synth.make_problem("c2", H=140, W=150, n=3)
+    x0 = synth.positive_start(p.latent_shape, 20.0, seed=6)
+    a, ta = gpu_run(p.y, p.v, p.psf, 1, 4, x0=x0, precision=em.BF16_SPLIT)
+    b, tb = gpu_run(p.y, p.v, p.psf, 1, 4, x0=x0, precision=em.BF16_SPLIT)
+    assert np.array_equal(a, b) and np.array_equal(ta, tb)
+    q = synth.make_problem("c4", H=64, W=64, n=1)
+    prob = em.Problem.make(1, 32, 32, 43, sr=2, precision=em.BF16_SPLIT)
+    x = torch.empty((64, 64), dtype=torch.float32, device="cuda")
+    with pytest.raises(em.EMError) as ei:
+        em.Context(prob, to_dev(q.y), to_dev(q.v), to_dev(q.psf), x)
+    assert ei.value.code == em.ENOTSUP
