@@ -140,6 +140,12 @@ def main() -> int:
     ctx = em.Context(p, y, v, f, x, x0=None, stream=stream)
     torch.cuda.synchronize()
     log("em_init done")
+    tuned = None
+    if args.precision != "fp32":
+        fv, av, tms = ctx.autotune(3)
+        tuned = {"forward_variant": fv, "adjoint_variant": av,
+                 "variant_ms": [[round(t, 4) for t in row] for row in tms.tolist()]}
+        log(f"autotune: forward variant {fv}, adjoint variant {av}, ms {tms.tolist()}")
 
     ctx.iterate(args.warmup)
     torch.cuda.synchronize()
@@ -209,6 +215,7 @@ def main() -> int:
             "per_launch_ms": {"forward": round(phases[0], 4), "adjoint": round(phases[1], 4),
                               "update": round(phases[2], 4), "iteration": round(phases[3], 4)},
             "result_finite_nonnegative": res_ok,
+            "autotune": tuned,
         },
         "roofline": roofline,
     }

@@ -168,6 +168,27 @@ int em_terms(em_ctx* ctx, float* B_out, float* Dn_out);
  */
 int em_profile(em_ctx* ctx, int32_t n_iter, double* phase_ms);
 
+/*
+ * Kernel variants of the matrix-core precisions (tile / wave layouts that
+ * compute the same sums; results may differ from one variant to another at the
+ * rounding level).  em_variant_count() gives their number; em_set_variants
+ * selects one per direction (0 = forward, 1 = adjoint) for ctx.
+ */
+int em_variant_count(void);
+int em_set_variants(em_ctx* ctx, int32_t fwd_variant, int32_t adj_variant);
+
+/*
+ * Autotuner: times every variant of the forward and the adjoint kernel on the
+ * job's own data (n_rep launches each after one warm-up, HIP events on the
+ * job's stream; the iterate x is not modified), selects the fastest for ctx
+ * and records the choice for later em_init calls of the same problem shape
+ * in this process.  Writes the chosen variants and, if ms != NULL, the mean
+ * launch times ms[dir * em_variant_count() + v].  Synchronous.
+ * EM_ENOTSUP for FP32 (one variant).
+ */
+int em_autotune(em_ctx* ctx, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_variant,
+                double* ms);
+
 /* Wait for the job's stream; reports asynchronous device errors. */
 int em_sync(em_ctx* ctx);
 

@@ -8,8 +8,11 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/em.h"
@@ -74,7 +77,18 @@ bool make_geometry(const void* problem, Geometry* g, const char** why) {
   g->precision = p->precision;
   g->weight_mode = p->weight_mode;
   if ((int64_t)g->n * g->Nf > ((int64_t)1 << 40)) { *why = "problem too large"; return false; }
+  if (g->Nl >= ((int64_t)1 << 31)) { *why = "latent image of 2^31 pixels or more"; return false; }
   return true;
+}
+
+// Kernel variants chosen by em_autotune, per problem shape and precision.
+// Process-wide; a job's variant depends only on its own shape.
+using TuneKey = std::tuple<int, int, int, int, int, int, int>;
+static std::mutex g_tune_mu;
+static std::map<TuneKey, std::pair<int, int>> g_tune;
+
+static TuneKey tune_key(const Geometry& g) {
+  return TuneKey(g.n, g.Hf, g.Wf, g.KT, g.sr, g.precision, g.weight_mode);
 }
 
 Plan make_plan(const Geometry& g) {
@@ -102,6 +116,16 @@ Plan make_plan(const Geometry& g) {
     pl.adj_fpg = (int)cdiv(g.n, ag);
     pl.adj_groups = (int)cdiv(g.n, pl.adj_fpg);
   }
+  pl.fwd_variant = 0;
+  pl.adj_variant = 0;
+  if (mf) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(g));
+    if (it != g_tune.end()) {
+      pl.fwd_variant = it->second.first;
+      pl.adj_variant = it->second.second;
+    }
+  }
   pl.prep_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv((int64_t)g.n * g.Nf, 256)));
   pl.upd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv(g.Nl, 256)));
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
@@ -126,9 +150,11 @@ Layout make_layout(const Geometry& g, const Plan& pl) {
   L.B = take((size_t)g.Nl * sizeof(float));
   L.planes = take(G > 1 ? (size_t)G * g.Nl * sizeof(float) : 0);
   L.tab = take((size_t)g.n * g.KC * TAB_LD * sizeof(float));
-  const size_t mtab = uses_mfma(g) ? (size_t)g.n * g.KT * 4 * 64 * 8 * sizeof(uint16_t) : 0;
+  const size_t mtab =
+      uses_mfma(g) ? (size_t)g.n * mfma_table_rows(g.KT) * 4 * 64 * 8 * sizeof(uint16_t) : 0;
   L.mtab_fwd = take(mtab);
   L.mtab_adj = take(mtab);
+  L.tune = take(uses_mfma(g) ? (size_t)g.Nl * sizeof(float) : 0);
   L.part_ll = take((size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double));
   L.part_rc = take((size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double));
   L.part_prep = take((size_t)3 * pl.prep_blocks * sizeof(double));
@@ -188,6 +214,7 @@ struct em_ctx {
   float* tab;
   void* mtab_fwd;
   void* mtab_adj;
+  float* tune;
   double* part_ll;
   double* part_rc;
   double* part_prep;
@@ -207,6 +234,7 @@ static void bind_views(em_ctx* c) {
   c->tab = reinterpret_cast<float*>(w + L.tab);
   c->mtab_fwd = w + L.mtab_fwd;
   c->mtab_adj = w + L.mtab_adj;
+  c->tune = reinterpret_cast<float*>(w + L.tune);
   c->part_ll = reinterpret_cast<double*>(w + L.part_ll);
   c->part_rc = reinterpret_cast<double*>(w + L.part_rc);
   c->part_prep = reinterpret_cast<double*>(w + L.part_prep);
@@ -248,7 +276,8 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
     m.W = c->g.Wl;
     m.fpg = c->pl.adj_fpg;
     m.fused = 0;
-    EM_HIP(launch_mfma(c->g, 1, c->pl.adj_tiles, c->pl.adj_groups, m, c->stream));
+    EM_HIP(launch_mfma(c->g, 1, c->pl.adj_variant, c->pl.adj_tiles, c->pl.adj_groups, m,
+                       c->stream));
   } else {
     AdjLaunch a{};
     a.in = in;
@@ -282,7 +311,8 @@ static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
     m.H = c->g.Hf;
     m.W = c->g.Wf;
     m.fpg = c->pl.fwd_fpg;
-    EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_tiles, c->pl.fwd_groups, m, c->stream));
+    EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_variant, c->pl.fwd_tiles, c->pl.fwd_groups, m,
+                       c->stream));
     return EM_OK;
   }
   FwdLaunch f{};
@@ -320,7 +350,8 @@ static int adjoint_launch(em_ctx* c, double* part_rc) {
     m.B = c->B;
     m.part = fused ? part_rc : nullptr;
     m.plane = c->planes;
-    EM_HIP(launch_mfma(c->g, 1, c->pl.adj_tiles, c->pl.adj_groups, m, c->stream));
+    EM_HIP(launch_mfma(c->g, 1, c->pl.adj_variant, c->pl.adj_tiles, c->pl.adj_groups, m,
+                       c->stream));
   } else {
     AdjLaunch a{};
     a.in = c->r;
@@ -574,6 +605,89 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
   return EM_OK;
 }
 
+int em_variant_count(void) { return mfma_variants(); }
+
+int em_set_variants(em_ctx* c, int32_t fwd_variant, int32_t adj_variant) {
+  if (!c) return fail(EM_EINVAL, "ctx is NULL");
+  if (!uses_mfma(c->g)) return fail(EM_ENOTSUP, "variants exist for matrix-core precisions only");
+  if (fwd_variant < 0 || fwd_variant >= mfma_variants() || adj_variant < 0 ||
+      adj_variant >= mfma_variants())
+    return fail(EM_EINVAL, "variant out of range");
+  c->pl.fwd_variant = fwd_variant;
+  c->pl.adj_variant = adj_variant;
+  return EM_OK;
+}
+
+int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_variant,
+                double* ms) {
+  if (!c) return fail(EM_EINVAL, "ctx is NULL");
+  if (!uses_mfma(c->g)) return fail(EM_ENOTSUP, "variants exist for matrix-core precisions only");
+  if (n_rep < 1) return fail(EM_EINVAL, "n_rep must be >= 1");
+  const int nv = mfma_variants();
+  hipEvent_t e0, e1;
+  EM_HIP(hipEventCreate(&e0));
+  EM_HIP(hipEventCreate(&e1));
+  std::vector<double> t(2 * nv, 0.0);
+  int rc = EM_OK;
+  for (int dir = 0; dir < 2 && rc == EM_OK; ++dir) {
+    for (int v = 0; v < nv && rc == EM_OK; ++v) {
+      MfmaLaunch m{};
+      m.n = c->g.n;
+      m.H = c->g.Hl;
+      m.W = c->g.Wl;
+      int tiles, groups;
+      if (dir == 0) {
+        // the forward writes r, which every iteration recomputes before use
+        m.in = c->x;
+        m.tab = c->mtab_fwd;
+        m.u = c->u;
+        m.out = c->r;
+        m.fpg = c->pl.fwd_fpg;
+        tiles = c->pl.fwd_tiles;
+        groups = c->pl.fwd_groups;
+      } else {
+        // the adjoint writes partial planes (never the iterate)
+        m.in = c->r;
+        m.tab = c->mtab_adj;
+        m.fused = 0;
+        m.plane = c->pl.adj_groups > 1 ? c->planes : c->tune;
+        m.fpg = c->pl.adj_fpg;
+        tiles = c->pl.adj_tiles;
+        groups = c->pl.adj_groups;
+      }
+      for (int k = 0; k <= n_rep && rc == EM_OK; ++k) {
+        if (k == 1) EM_HIP(hipEventRecord(e0, c->stream));
+        hipError_t e = launch_mfma(c->g, dir, v, tiles, groups, m, c->stream);
+        if (e != hipSuccess) rc = fail(EM_EDEVICE, "autotune launch: %s", hipGetErrorString(e));
+      }
+      if (rc) break;
+      EM_HIP(hipEventRecord(e1, c->stream));
+      EM_HIP(hipEventSynchronize(e1));
+      float el = 0.f;
+      EM_HIP(hipEventElapsedTime(&el, e0, e1));
+      t[dir * nv + v] = el / n_rep;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc) return rc;
+  int bf = 0, ba = 0;
+  for (int v = 1; v < nv; ++v) {
+    if (t[v] < t[bf]) bf = v;
+    if (t[nv + v] < t[nv + ba]) ba = v;
+  }
+  c->pl.fwd_variant = bf;
+  c->pl.adj_variant = ba;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(c->g)] = std::make_pair(bf, ba);
+  }
+  if (fwd_variant) *fwd_variant = bf;
+  if (adj_variant) *adj_variant = ba;
+  if (ms) std::copy(t.begin(), t.end(), ms);
+  return EM_OK;
+}
+
 int em_sync(em_ctx* c) {
   if (!c) return fail(EM_EINVAL, "ctx is NULL");
   EM_HIP(hipStreamSynchronize(c->stream));
@@ -628,7 +742,7 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
     mm.H = g.Hf;
     mm.W = g.Wf;
     mm.fpg = pl.fwd_fpg;
-    EM_HIP(launch_mfma(g, 0, pl.fwd_tiles, pl.fwd_groups, mm, s));
+    EM_HIP(launch_mfma(g, 0, pl.fwd_variant, pl.fwd_tiles, pl.fwd_groups, mm, s));
     return EM_OK;
   }
   FwdLaunch f{};
@@ -678,7 +792,7 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
     mm.W = g.Wl;
     mm.fpg = 1;
     mm.fused = 0;
-    EM_HIP(launch_mfma(g, 1, pl.adj_tiles, g.n, mm, s));
+    EM_HIP(launch_mfma(g, 1, pl.adj_variant, pl.adj_tiles, g.n, mm, s));
     return EM_OK;
   }
   AdjLaunch a{};

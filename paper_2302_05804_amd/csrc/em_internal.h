@@ -70,7 +70,7 @@ struct Plan {
 
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct Layout {
-  size_t u, r, B, planes, tab, mtab_fwd, mtab_adj, part_ll, part_rc, part_prep, scalars,
+  size_t u, r, B, planes, tab, mtab_fwd, mtab_adj, tune, part_ll, part_rc, part_prep, scalars,
       trace_ll, trace_rc, counters, total;
 };
 
@@ -119,8 +119,10 @@ struct MfmaLaunch {
   int n, H, W, fpg;
   int fused;
 };
-hipError_t launch_mfma(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a,
-                       hipStream_t s);
+hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
+                       const MfmaLaunch& a, hipStream_t s);
+int mfma_table_rows(int KT);
+int mfma_variants();
 hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                               hipStream_t s);
 int mfma_tile_h();

@@ -35,11 +35,30 @@ namespace em {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-constexpr int MF_BR = 4, MF_BC = 4;          // 16x16 blocks per wave (rows, cols)
-constexpr int MF_TH = 128, MF_TW = 128;      // outputs per workgroup
-constexpr int MF_COLS = MF_TW + 48;          // LDS columns read by fragments
-constexpr int MF_PITCH = 184;                // bf16 per LDS row (368 bytes)
-constexpr int MF_NT = 256;
+// Row pitch (bf16 elements) of an LDS plane holding `cols` columns: rows stay
+// 16-byte aligned and the pitch is an odd number of 16-byte chunks.
+__host__ __device__ constexpr int mf_pitch(int cols) {
+  return (((cols + 7) / 8) % 2 == 1) ? ((cols + 7) / 8) * 8 : ((cols + 7) / 8) * 8 + 8;
+}
+
+// Tile configuration: each wave owns BR x BC blocks of 16 x 16 outputs, the
+// workgroup WR x WC waves.
+template <int KT_, int NS_, int BR_, int BC_, int WR_, int WC_, int PFA_, int PFT_>
+struct MfCfg {
+  static constexpr int KT = KT_, NS = NS_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  // PFA: load the A fragments of the next fragment row before the products of
+  // the current one; PFT: fetch the next tap class's Toeplitz fragments early.
+  static constexpr int PFA = PFA_, PFT = PFT_;
+  static constexpr int NW = WR * WC, NT = 64 * NW;
+  static constexpr int TH = 16 * BR * WR, TW = 16 * BC * WC;
+  static constexpr int ROWS = TH + KT - 1;
+  static constexpr int COLS = TW + 48;
+  static constexpr int PITCH = mf_pitch(COLS);
+  static constexpr int MMAX = (KT + 15) / 16;   // members of the largest tap class
+  static constexpr int KTP = 16 * MMAX;         // table rows (zero beyond KT)
+};
+
+constexpr int MF_TILE = 128;   // every variant covers 128 x 128 outputs
 
 __device__ inline unsigned short bf16_bits(__bf16 v) { return __builtin_bit_cast(unsigned short, v); }
 
@@ -51,13 +70,13 @@ __device__ inline void split_bf16(float v, unsigned short& hi, unsigned short& l
   lo = bf16_bits((__bf16)rest);
 }
 
-// Stage an input tile (FP32 image, rows [r0, r0 + ROWS), cols [q0, q0 + MF_COLS),
+// Stage an input tile (FP32 image, rows [r0, r0 + ROWS), cols [q0, q0 + COLS),
 // zero outside [0,H) x [0,W)) into the hi / lo LDS planes.
-template <int ROWS>
+template <class C>
 __device__ inline void stage_tile(const float* __restrict__ src, int H, int W, int r0, int q0,
                                   unsigned short* sh_hi, unsigned short* sh_lo) {
-  constexpr int HALF = MF_COLS / 2;
-  for (int e = threadIdx.x; e < ROWS * HALF; e += MF_NT) {
+  constexpr int HALF = C::COLS / 2;
+  for (int e = threadIdx.x; e < C::ROWS * HALF; e += C::NT) {
     const int row = e / HALF, cp = e - row * HALF;
     const int gy = r0 + row, gx = q0 + 2 * cp;
     float v0 = 0.f, v1 = 0.f;
@@ -69,52 +88,76 @@ __device__ inline void stage_tile(const float* __restrict__ src, int H, int W, i
     unsigned short h0, l0, h1, l1;
     split_bf16(v0, h0, l0);
     split_bf16(v1, h1, l1);
-    const int o = row * MF_PITCH + 2 * cp;
+    const int o = row * C::PITCH + 2 * cp;
     *reinterpret_cast<unsigned int*>(sh_hi + o) = (unsigned int)h0 | ((unsigned int)h1 << 16);
     *reinterpret_cast<unsigned int*>(sh_lo + o) = (unsigned int)l0 | ((unsigned int)l1 << 16);
   }
 }
 
-// One class of kernel rows a = r + 16 m, m < NM: accumulate into acc.
-template <int NM, int NS>
-__device__ inline void mfma_class(int r, const unsigned short* sh_hi, const unsigned short* sh_lo,
-                                  const bf16x8* __restrict__ tab_t, int row_base, int col_base,
-                                  f32x4 (&acc)[MF_BR][MF_BC]) {
+// Toeplitz fragments of tap class r (rows a = r + 16 m, m < MMAX), both k-halves,
+// hi and (split) lo parts.
+template <class C>
+__device__ inline void load_T(bf16x8 (&T)[C::MMAX][2][2], const bf16x8* __restrict__ tab_t, int r) {
   const int lane = threadIdx.x & 63;
-  const int i = lane & 15, g = lane >> 4;
-  // Toeplitz fragments U_a for a = r + 16m, both k-halves, hi (and lo)
-  bf16x8 T[NM][2][2];
 #pragma unroll
-  for (int m = 0; m < NM; ++m)
+  for (int m = 0; m < C::MMAX; ++m)
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int s = 0; s < (NS == 3 ? 2 : 1); ++s)
+      for (int s = 0; s < (C::NS == 3 ? 2 : 1); ++s)
         T[m][h][s] = tab_t[(((r + 16 * m) * 2 + h) * 2 + s) * 64 + lane];
+}
+
+// A fragments (hi, lo) of fragment row rho for every column position kappa.
+template <class C>
+__device__ inline void load_A(bf16x8 (&A)[C::BC + 2][2], const unsigned short* sh_hi,
+                              const unsigned short* sh_lo, int lrow, int col_base) {
+  const int g = (threadIdx.x & 63) >> 4;
 #pragma unroll
-  for (int rho = 0; rho < MF_BR + NM - 1; ++rho) {
-    const int lrow = row_base + r + 16 * rho + i;
+  for (int kap = 0; kap < C::BC + 2; ++kap) {
+    const int o = lrow * C::PITCH + col_base + 16 * kap + 8 * g;
+    A[kap][0] = *reinterpret_cast<const bf16x8*>(sh_hi + o);
+    if (C::NS == 3) A[kap][1] = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+  }
+}
+
+// One tap class: NM members a = r + 16 m.  The A fragment of rows
+// r + 16 rho + i serves block rows beta = rho - m; fragments of the next rho
+// are loaded before the products of the current one are issued, and products
+// are ordered by split term so that consecutive MFMAs write different blocks.
+template <class C, int NM>
+__device__ inline void mfma_class(int r, const unsigned short* sh_hi, const unsigned short* sh_lo,
+                                  const bf16x8 (&T)[C::MMAX][2][2], int row_base, int col_base,
+                                  f32x4 (&acc)[C::BR][C::BC]) {
+  const int i = threadIdx.x & 15;
+  constexpr int NRHO = C::BR + NM - 1;
+  bf16x8 A[C::PFA ? 2 : 1][C::BC + 2][2];
+  if (C::PFA) load_A<C>(A[0], sh_hi, sh_lo, row_base + r + i, col_base);
 #pragma unroll
-    for (int kap = 0; kap < MF_BC + 2; ++kap) {
-      const int o = lrow * MF_PITCH + col_base + 16 * kap + 8 * g;
-      const bf16x8 Ah = *reinterpret_cast<const bf16x8*>(sh_hi + o);
-      bf16x8 Al;
-      if (NS == 3) Al = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+  for (int rho = 0; rho < NRHO; ++rho) {
+    if (C::PFA) {
+      if (rho + 1 < NRHO)
+        load_A<C>(A[(rho + 1) & 1], sh_hi, sh_lo, row_base + r + 16 * (rho + 1) + i, col_base);
+    } else {
+      load_A<C>(A[0], sh_hi, sh_lo, row_base + r + 16 * rho + i, col_base);
+    }
+    const int cur = C::PFA ? (rho & 1) : 0;
 #pragma unroll
-      for (int m = 0; m < NM; ++m) {
-        const int beta = rho - m;
-        if (beta < 0 || beta >= MF_BR) continue;
+    for (int s = 0; s < C::NS; ++s) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int gam = kap - 2 * h;
-          if (gam < 0 || gam >= MF_BC) continue;
-          acc[beta][gam] =
-              __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, T[m][h][0], acc[beta][gam], 0, 0, 0);
-          if (NS == 3) {
+      for (int kap = 0; kap < C::BC + 2; ++kap) {
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          const int beta = rho - m;
+          if (beta < 0 || beta >= C::BR) continue;
+#pragma unroll
+          for (int h = 0; h < 2; ++h) {
+            const int gam = kap - 2 * h;
+            if (gam < 0 || gam >= C::BC) continue;
+            const bf16x8& a_op = A[cur][kap][s == 1 ? 1 : 0];
+            const bf16x8& b_op = T[m][h][s == 2 ? 1 : 0];
             acc[beta][gam] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(Al, T[m][h][0], acc[beta][gam], 0, 0, 0);
-            acc[beta][gam] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(Ah, T[m][h][1], acc[beta][gam], 0, 0, 0);
+                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_op, b_op, acc[beta][gam], 0, 0, 0);
           }
         }
       }
@@ -122,35 +165,71 @@ __device__ inline void mfma_class(int r, const unsigned short* sh_hi, const unsi
   }
 }
 
-// All kernel rows of one frame.
-template <int KT, int NS>
+// All kernel rows of one frame; the Toeplitz fragments of the next class are
+// fetched while the current class runs.
+template <class C>
 __device__ inline void mfma_frame(const unsigned short* sh_hi, const unsigned short* sh_lo,
                                   const bf16x8* __restrict__ tab_t, int row_base, int col_base,
-                                  f32x4 (&acc)[MF_BR][MF_BC]) {
-  // classes r with 3, 2 and 1 members (KT = 43: r<=10 -> 3, else 2; KT = 15: r<=14 -> 1)
-  constexpr int R3 = KT > 32 ? KT - 32 : 0;
-  constexpr int R2 = KT > 16 ? (KT - 16 < 16 ? KT - 16 : 16) : 0;
-  constexpr int R1 = KT < 16 ? KT : 16;
-  int r = 0;
-  for (; r < R3; ++r) mfma_class<3, NS>(r, sh_hi, sh_lo, tab_t, row_base, col_base, acc);
-  for (; r < R2; ++r) mfma_class<2, NS>(r, sh_hi, sh_lo, tab_t, row_base, col_base, acc);
-  for (; r < R1; ++r) mfma_class<1, NS>(r, sh_hi, sh_lo, tab_t, row_base, col_base, acc);
+                                  f32x4 (&acc)[C::BR][C::BC]) {
+  // classes with MMAX members first, then MMAX-1 (KT = 43: r <= 10 -> 3, r >= 11 -> 2;
+  // KT = 15: r <= 14 -> 1)
+  constexpr int RFULL = C::KT - 16 * (C::MMAX - 1);
+  constexpr int RLAST = (C::MMAX == 1) ? C::KT : 16;
+  bf16x8 Tc[C::MMAX][2][2];
+  if (C::PFT) {
+    bf16x8 Tn[C::MMAX][2][2];
+    load_T<C>(Tc, tab_t, 0);
+    int r = 0;
+    for (; r < RFULL; ++r) {
+      if (r + 1 < RLAST) load_T<C>(Tn, tab_t, r + 1);
+      mfma_class<C, C::MMAX>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+#pragma unroll
+      for (int m = 0; m < C::MMAX; ++m)
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) Tc[m][h][q] = Tn[m][h][q];
+    }
+    if constexpr (C::MMAX > 1) {
+      for (; r < RLAST; ++r) {
+        if (r + 1 < RLAST) load_T<C>(Tn, tab_t, r + 1);
+        mfma_class<C, C::MMAX - 1>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+#pragma unroll
+        for (int m = 0; m < C::MMAX; ++m)
+#pragma unroll
+          for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int q = 0; q < 2; ++q) Tc[m][h][q] = Tn[m][h][q];
+      }
+    }
+  } else {
+    int r = 0;
+    for (; r < RFULL; ++r) {
+      load_T<C>(Tc, tab_t, r);
+      mfma_class<C, C::MMAX>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+    }
+    if constexpr (C::MMAX > 1) {
+      for (; r < RLAST; ++r) {
+        load_T<C>(Tc, tab_t, r);
+        mfma_class<C, C::MMAX - 1>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+      }
+    }
+  }
 }
 
 // Forward: r_t = u_t * (f_t * x) for the frames of this group, x tile staged once.
-template <int KT, int NS>
-__global__ __launch_bounds__(MF_NT) void mfma_fwd_kernel(MfmaLaunch a) {
-  constexpr int c = (KT - 1) / 2;
-  constexpr int ROWS = MF_TH + KT - 1;
-  __shared__ __align__(16) unsigned short sh_hi[ROWS * MF_PITCH];
-  __shared__ __align__(16) unsigned short sh_lo[ROWS * MF_PITCH];
-  __shared__ double red[MF_NT / 64];
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd_kernel(MfmaLaunch a) {
+  constexpr int c = (C::KT - 1) / 2;
+  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ double red[C::NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int tiles_x = (a.W + MF_TW - 1) / MF_TW;
+  const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
+  const int tiles_x = (a.W + C::TW - 1) / C::TW;
   const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-  const int k0 = ty * MF_TH, l0 = tx * MF_TW;
-  stage_tile<ROWS>(a.in, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
+  const int k0 = ty * C::TH, l0 = tx * C::TW;
+  stage_tile<C>(a.in, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
   __syncthreads();
 
   const int t0 = blockIdx.y * a.fpg;
@@ -158,32 +237,40 @@ __global__ __launch_bounds__(MF_NT) void mfma_fwd_kernel(MfmaLaunch a) {
   const int64_t N = (int64_t)a.H * a.W;
   double llp = 0.0;
   for (int t = t0; t < t1; ++t) {
-    f32x4 acc[MF_BR][MF_BC];
+    // The staged tile does not change between frames; this fence keeps the
+    // compiler from hoisting every fragment read of the tile out of the frame
+    // loop (which would need hundreds of live registers).
+    __asm__ volatile("" ::: "memory");
+    f32x4 acc[C::BR][C::BC];
 #pragma unroll
-    for (int b = 0; b < MF_BR; ++b)
+    for (int b = 0; b < C::BR; ++b)
 #pragma unroll
-      for (int q = 0; q < MF_BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * KT * 4 * 64;
-    mfma_frame<KT, NS>(sh_hi, sh_lo, tab_t, wr * 64, wc * 64, acc);
-    const int64_t base = (int64_t)t * N;
+      for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
+    mfma_frame<C>(sh_hi, sh_lo, tab_t, row_base, col_base, acc);
+    // epilogue: per-frame base pointers (wave-uniform) + 32-bit in-frame offsets
+    const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
+    const float* yt = a.y ? a.y + (int64_t)t * N : nullptr;
+    float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
 #pragma unroll
-    for (int b = 0; b < MF_BR; ++b)
+    for (int b = 0; b < C::BR; ++b)
 #pragma unroll
-      for (int q = 0; q < MF_BC; ++q) {
-        const int l = l0 + wc * 64 + 16 * q + (lane & 15);
+      for (int q = 0; q < C::BC; ++q) {
+        const int l = l0 + col_base + 16 * q + (lane & 15);
+        const int kb = k0 + row_base + 16 * b + 4 * (lane >> 4);
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          const int k = k0 + wr * 64 + 16 * b + 4 * (lane >> 4) + v;
+          const int k = kb + v;
           if (k < a.H && l < a.W) {
-            const int64_t idx = base + (int64_t)k * a.W + l;
+            const int off = k * a.W + l;
             const float m = acc[b][q][v];
-            if (a.u == nullptr) {
-              a.out[idx] = m;
+            if (ut == nullptr) {
+              ot[off] = m;
             } else {
-              const float uu = a.u[idx];
-              if (a.out) a.out[idx] = uu * m;
+              const float uu = ut[off];
+              if (ot) ot[off] = uu * m;
               if (a.part != nullptr && uu > 0.f) {
-                const double d = (double)a.y[idx] - (double)m;
+                const double d = (double)yt[off] - (double)m;
                 llp += (double)uu * d * d;
               }
             }
@@ -192,7 +279,7 @@ __global__ __launch_bounds__(MF_NT) void mfma_fwd_kernel(MfmaLaunch a) {
       }
   }
   if (a.part != nullptr) {
-    const double s = block_sum<MF_NT>(llp, red);
+    const double s = block_sum<C::NT>(llp, red);
     if (threadIdx.x == 0) a.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
   }
 }
@@ -206,64 +293,65 @@ __device__ inline float mf_update_value(float xo, float Bv, float Dn) {
 
 // Adjoint: sum over the frames of this group of F_t^T r_t; the r_t tile is
 // staged per frame.  Epilogue: partial plane, or the fused update of Eq. (2).
-template <int KT, int NS>
-__global__ __launch_bounds__(MF_NT) void mfma_adj_kernel(MfmaLaunch a) {
-  constexpr int c = (KT - 1) / 2;
-  constexpr int ROWS = MF_TH + KT - 1;
-  __shared__ __align__(16) unsigned short sh_hi[ROWS * MF_PITCH];
-  __shared__ __align__(16) unsigned short sh_lo[ROWS * MF_PITCH];
-  __shared__ double red[2 * MF_NT / 64];
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
+  constexpr int c = (C::KT - 1) / 2;
+  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ double red[2 * C::NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wr = w >> 1, wc = w & 1;
-  const int tiles_x = (a.W + MF_TW - 1) / MF_TW;
+  const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
+  const int tiles_x = (a.W + C::TW - 1) / C::TW;
   const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
-  const int k0 = ty * MF_TH, l0 = tx * MF_TW;
+  const int k0 = ty * C::TH, l0 = tx * C::TW;
   const int64_t N = (int64_t)a.H * a.W;
 
-  f32x4 acc[MF_BR][MF_BC];
+  f32x4 acc[C::BR][C::BC];
 #pragma unroll
-  for (int b = 0; b < MF_BR; ++b)
+  for (int b = 0; b < C::BR; ++b)
 #pragma unroll
-    for (int q = 0; q < MF_BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
   const int t0 = blockIdx.y * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
-    stage_tile<ROWS>(a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
+    stage_tile<C>(a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
     __syncthreads();
-    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * KT * 4 * 64;
-    mfma_frame<KT, NS>(sh_hi, sh_lo, tab_t, wr * 64, wc * 64, acc);
+    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
+    mfma_frame<C>(sh_hi, sh_lo, tab_t, row_base, col_base, acc);
   }
 
   double dsq = 0.0, xsq = 0.0;
+  float* pl = a.fused ? nullptr : a.plane + (int64_t)blockIdx.y * N;
 #pragma unroll
-  for (int b = 0; b < MF_BR; ++b)
+  for (int b = 0; b < C::BR; ++b)
 #pragma unroll
-    for (int q = 0; q < MF_BC; ++q) {
-      const int l = l0 + wc * 64 + 16 * q + (lane & 15);
+    for (int q = 0; q < C::BC; ++q) {
+      const int l = l0 + col_base + 16 * q + (lane & 15);
+      const int kb = k0 + row_base + 16 * b + 4 * (lane >> 4);
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int k = k0 + wr * 64 + 16 * b + 4 * (lane >> 4) + v;
+        const int k = kb + v;
         if (k < a.H && l < a.W) {
-          const int64_t idx = (int64_t)k * a.W + l;
+          const int off = k * a.W + l;
           if (a.fused) {
-            const float xo = a.x[idx];
-            const float xn = mf_update_value(xo, a.B[idx], acc[b][q][v]);
-            a.x[idx] = xn;
+            const float xo = a.x[off];
+            const float xn = mf_update_value(xo, a.B[off], acc[b][q][v]);
+            a.x[off] = xn;
             const double d = (double)xn - (double)xo;
             dsq += d * d;
             xsq += (double)xo * (double)xo;
           } else {
-            a.plane[(int64_t)blockIdx.y * N + idx] = acc[b][q][v];
+            pl[off] = acc[b][q][v];
           }
         }
       }
     }
   if (a.fused && a.part != nullptr) {
-    const double s1 = block_sum<MF_NT>(dsq, red);
+    const double s1 = block_sum<C::NT>(dsq, red);
     __syncthreads();
-    const double s2 = block_sum<MF_NT>(xsq, red + MF_NT / 64);
+    const double s2 = block_sum<C::NT>(xsq, red + C::NW);
     if (threadIdx.x == 0) {
       a.part[2 * blockIdx.x] = s1;
       a.part[2 * blockIdx.x + 1] = s2;
@@ -275,20 +363,20 @@ __global__ __launch_bounds__(MF_NT) void mfma_adj_kernel(MfmaLaunch a) {
 // [t][a][h][s][lane] holds the 8 bf16 values U_a[32h + 8(lane/16) + e][lane%16],
 // e = 0..7, of part s (0 = hi, 1 = lo) of g = flip(f) (dir 0, forward) or
 // g = f (dir 1, adjoint), f zero-padded from K to KT.
-__global__ __launch_bounds__(256) void mfma_table_kernel(const float* psf, int K, int KT, int dir,
-                                                         unsigned short* tab) {
-  const int t = blockIdx.x, a = blockIdx.y;
+__global__ __launch_bounds__(256) void mfma_table_kernel(const float* psf, int K, int KT, int KTP,
+                                                         int dir, unsigned short* tab) {
+  const int t = blockIdx.x, a = blockIdx.y;   // a in [0, KTP); rows a >= KT are zero
   const int off = (KT - K) / 2;
   const float* f = psf + (int64_t)t * K * K;
   const int idx = threadIdx.x;          // (h, s, lane) = 2 x 2 x 64
   const int lane = idx & 63, s = (idx >> 6) & 1, h = idx >> 7;
   const int j = lane & 15, gq = lane >> 4;
-  unsigned short* dst = tab + ((((int64_t)t * KT + a) * 2 + h) * 2 + s) * 64 * 8 + lane * 8;
+  unsigned short* dst = tab + ((((int64_t)t * KTP + a) * 2 + h) * 2 + s) * 64 * 8 + lane * 8;
   for (int e = 0; e < 8; ++e) {
     const int p = 32 * h + 8 * gq + e;
     const int b = p - j;                 // column of g
     float gv = 0.f;
-    if (b >= 0 && b < KT) {
+    if (a < KT && b >= 0 && b < KT) {
       // g[a][b]: forward uses the 180-degree flip of f
       const int fa = dir == 0 ? KT - 1 - a : a;
       const int fb = dir == 0 ? KT - 1 - b : b;
@@ -301,41 +389,55 @@ __global__ __launch_bounds__(256) void mfma_table_kernel(const float* psf, int K
   }
 }
 
+int mfma_table_rows(int KT) { return 16 * ((KT + 15) / 16); }
+
 hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                               hipStream_t s) {
-  dim3 grid(g.n, g.KT);
-  hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, 0,
+  const int KTP = mfma_table_rows(g.KT);
+  dim3 grid(g.n, KTP);
+  hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, KTP, 0,
                      static_cast<unsigned short*>(tab_fwd));
-  hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, 1,
+  hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, KTP, 1,
                      static_cast<unsigned short*>(tab_adj));
   return hipGetLastError();
 }
 
-int mfma_tile_h() { return MF_TH; }
-int mfma_tile_w() { return MF_TW; }
+int mfma_tile_h() { return MF_TILE; }
+int mfma_tile_w() { return MF_TILE; }
+int mfma_variants() { return 3; }
 
-hipError_t launch_mfma(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a,
-                       hipStream_t s) {
-  dim3 grid(tiles, groups), block(MF_NT);
-  const bool split = g.precision == EM_BF16_SPLIT;
+namespace {
+// variant v: 0 = 4 waves of 4x4 blocks; 1 = 8 waves of 4x2 blocks; 2 = 8 waves of 2x4 blocks
+template <int KT, int NS>
+hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipStream_t s) {
+  using C0 = MfCfg<KT, NS, 4, 4, 2, 2, 1, 1>;
+  using C1 = MfCfg<KT, NS, 4, 2, 2, 4, 0, 1>;
+  using C2 = MfCfg<KT, NS, 2, 4, 4, 2, 0, 1>;
+  static_assert(C0::TH == MF_TILE && C0::TW == MF_TILE, "tile");
+  static_assert(C1::TH == MF_TILE && C1::TW == MF_TILE, "tile");
+  static_assert(C2::TH == MF_TILE && C2::TW == MF_TILE, "tile");
   if (dir == 0) {
-    if (g.KT == KT_LARGE) {
-      if (split) hipLaunchKernelGGL((mfma_fwd_kernel<KT_LARGE, 3>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((mfma_fwd_kernel<KT_LARGE, 1>), grid, block, 0, s, a);
-    } else {
-      if (split) hipLaunchKernelGGL((mfma_fwd_kernel<KT_SMALL, 3>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((mfma_fwd_kernel<KT_SMALL, 1>), grid, block, 0, s, a);
-    }
+    if (variant == 1) hipLaunchKernelGGL(mfma_fwd_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
+    else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
+    else hipLaunchKernelGGL(mfma_fwd_kernel<C0>, grid, dim3(C0::NT), 0, s, a);
   } else {
-    if (g.KT == KT_LARGE) {
-      if (split) hipLaunchKernelGGL((mfma_adj_kernel<KT_LARGE, 3>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((mfma_adj_kernel<KT_LARGE, 1>), grid, block, 0, s, a);
-    } else {
-      if (split) hipLaunchKernelGGL((mfma_adj_kernel<KT_SMALL, 3>), grid, block, 0, s, a);
-      else hipLaunchKernelGGL((mfma_adj_kernel<KT_SMALL, 1>), grid, block, 0, s, a);
-    }
+    if (variant == 1) hipLaunchKernelGGL(mfma_adj_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
+    else if (variant == 2) hipLaunchKernelGGL(mfma_adj_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
+    else hipLaunchKernelGGL(mfma_adj_kernel<C0>, grid, dim3(C0::NT), 0, s, a);
   }
   return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
+                       const MfmaLaunch& a, hipStream_t s) {
+  dim3 grid(tiles, groups);
+  const bool split = g.precision == EM_BF16_SPLIT;
+  if (g.KT == KT_LARGE)
+    return split ? launch_dir<KT_LARGE, 3>(dir, variant, grid, a, s)
+                 : launch_dir<KT_LARGE, 1>(dir, variant, grid, a, s);
+  return split ? launch_dir<KT_SMALL, 3>(dir, variant, grid, a, s)
+               : launch_dir<KT_SMALL, 1>(dir, variant, grid, a, s);
 }
 
 }  // namespace em

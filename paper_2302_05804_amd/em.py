@@ -71,6 +71,10 @@ _sig = {
     "em_terms": (ctypes.c_int, [_P, _P, _P]),
     "em_profile": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "em_sync": (ctypes.c_int, [_P]),
+    "em_variant_count": (ctypes.c_int, []),
+    "em_set_variants": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
+    "em_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.POINTER(ctypes.c_int32), _P]),
     "em_destroy": (ctypes.c_int, [_P]),
     "em_forward_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "em_adjoint_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
@@ -194,6 +198,19 @@ class Context:
         out = np.zeros(4, np.float64)
         _check(_lib.em_profile(self._h, int(n_iter), out.ctypes.data_as(_P)), "em_profile")
         return out
+
+    def set_variants(self, fwd: int, adj: int):
+        _check(_lib.em_set_variants(self._h, int(fwd), int(adj)), "em_set_variants")
+
+    def autotune(self, n_rep: int = 3):
+        """Time every kernel variant on this job; returns (fwd, adj, ms[2, nv])."""
+        nv = int(_lib.em_variant_count())
+        ms = np.zeros(2 * nv, np.float64)
+        f = ctypes.c_int32(0)
+        a = ctypes.c_int32(0)
+        _check(_lib.em_autotune(self._h, int(n_rep), ctypes.byref(f), ctypes.byref(a),
+                                ms.ctypes.data_as(_P)), "em_autotune")
+        return f.value, a.value, ms.reshape(2, nv)
 
     def sync(self):
         _check(_lib.em_sync(self._h), "em_sync")

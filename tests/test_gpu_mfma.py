@@ -116,3 +116,39 @@ def test_split_deterministic_and_sr2_unsupported():
     with pytest.raises(em.EMError) as ei:
         em.Context(prob, to_dev(q.y), to_dev(q.v), to_dev(q.psf), x)
     assert ei.value.code == em.ENOTSUP
+
+
+def test_every_variant_and_autotune_match_oracle():
+    import torch
+    em = _em()
+    p = synth.make_problem("c3", H=260, W=300, n=3)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v), 1.0), seed=12)
+    xo = oracle.run(p.y, p.v, p.psf, x0, 4)
+    prob = em.Problem.make(3, 260, 300, 43, precision=em.BF16_SPLIT)
+    nv = em._lib.em_variant_count()
+    assert nv >= 2
+    outs = []
+    for fv in range(nv):
+        for av in range(nv):
+            x = torch.empty((260, 300), dtype=torch.float32, device="cuda")
+            ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+            ctx.set_variants(fv, av)
+            ctx.iterate(4)
+            ctx.sync()
+            xg = x.cpu().numpy()
+            ctx.close()
+            err = rel_l2(xg, xo)
+            log(f"variant fwd={fv} adj={av}: rel L2 {err:.2e}")
+            assert err <= SPLIT_X_TOL
+            outs.append(xg)
+    # autotune leaves the iterate alone and picks valid variants
+    x = torch.empty((260, 300), dtype=torch.float32, device="cuda")
+    ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+    before = x.clone()
+    f, a, ms = ctx.autotune(2)
+    assert torch.equal(before, x)
+    assert 0 <= f < nv and 0 <= a < nv and (ms > 0).all()
+    ctx.iterate(4)
+    ctx.sync()
+    assert rel_l2(x.cpu().numpy(), xo) <= SPLIT_X_TOL
+    ctx.close()
