@@ -207,6 +207,64 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
 int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* s,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of deconvolution jobs on one GPU.
+ *
+ * A server owns one device arena of hbm_budget bytes (allocated once) and a
+ * worker thread.  Jobs are admitted in arrival order whenever one of
+ * max_slots slots and enough of the arena are free; admitted jobs keep their
+ * inputs, iterate and workspace resident and advance together, one EM
+ * iteration (Eq. (2)) per round, in one batched launch per kernel family
+ * (captured in a HIP graph while the set of jobs is unchanged).  A finished
+ * job's iterate and final log-likelihood are copied to host memory and its
+ * arena space is reused at once.  Each job's result does not depend on what
+ * else runs (fixed per-shape launch plan, no cross-job reductions).
+ * All em_server calls are thread-safe.
+ * ------------------------------------------------------------------------ */
+
+/* stream: hipStream_t (as void*) for the server's work, or NULL for a stream
+ * the server creates.  EM_ENOMEM if the budget cannot be allocated. */
+int em_server_create(em_server** out, size_t hbm_budget, int32_t max_slots, void* stream);
+
+/* Stops the worker (pending and running jobs are cancelled) and frees all. */
+int em_server_destroy(em_server* server);
+
+/* Device bytes a job of problem p takes from the server's budget. */
+size_t em_job_bytes(const em_problem* p);
+
+/*
+ * Queue one job (non-blocking).  y_host, v_host (n x frame_h x frame_w) and
+ * psf_host (n x K x K) are host float32 arrays copied before the call returns
+ * (the caller may free them).  The starting guess is the flat rule of
+ * em_init.  Returns EM_ENOMEM if the job can never fit the budget, EM_EINVAL /
+ * EM_ENOTSUP for a bad problem (data errors are reported by em_poll/em_wait).
+ */
+int em_submit(em_server* server, const em_problem* p, const float* y_host, const float* v_host,
+              const float* psf_host, int32_t n_iter, em_job_id* out);
+
+/*
+ * EM_OK when the job is done: copies its iterate (H_lat x W_lat float32) to
+ * x_host_out and its final log-likelihood l(x^(n_iter)) to loglik_out (either
+ * may be NULL); EM_EAGAIN while queued or running; EM_ECANCELED; or the
+ * job's error.  em_wait blocks until the job leaves the pending states.
+ */
+int em_poll(em_server* server, em_job_id id, float* x_host_out, double* loglik_out);
+int em_wait(em_server* server, em_job_id id, float* x_host_out, double* loglik_out);
+
+/* Cancel a queued or running job (running jobs stop at the next round). */
+int em_cancel(em_server* server, em_job_id id);
+
+/* Forget a finished job and free its host result (EM_EAGAIN if pending). */
+int em_release(em_server* server, em_job_id id);
+
+/* Steady-clock seconds at which the job was submitted, admitted, finished. */
+int em_job_times(em_server* server, em_job_id id, double* t_submit, double* t_admit,
+                 double* t_done);
+
+/* stats[8]: queued, active, done, failed, cancelled, rounds run, round graphs
+ * built, arena bytes in use. */
+int em_server_stats(em_server* server, int64_t* stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -132,6 +132,24 @@ Plan make_plan(const Geometry& g) {
   return pl;
 }
 
+// Plan of a job run by the serving loop: the frame sum of the adjoint is never
+// split (update fused, no partial planes), the forward uses groups of at most
+// four frames (the grouping does not change its arithmetic), and the matrix-core
+// kernels use fixed variants.  The plan depends on the job's shape only.
+Plan make_serving_plan(const Geometry& g) {
+  Plan pl = make_plan(g);
+  pl.adj_groups = 1;
+  pl.adj_fpg = g.n;
+  pl.fwd_fpg = std::min(g.n, 4);
+  pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
+  pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
+  if (uses_mfma(g)) {
+    pl.fwd_variant = 1;
+    pl.adj_variant = 2;
+  }
+  return pl;
+}
+
 static size_t al256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 Layout make_layout(const Geometry& g, const Plan& pl) {
@@ -196,35 +214,7 @@ static int check_device_range(const void* ptr, size_t bytes, const char* name) {
 
 using namespace em;
 
-struct em_ctx {
-  Geometry g;
-  Plan pl;
-  Layout lay;
-  hipStream_t stream;
-  const float* y;
-  const float* v;
-  const float* psf;
-  float* x;
-  char* ws;
-  // device views into the workspace
-  float* u;
-  float* r;
-  float* B;
-  float* planes;
-  float* tab;
-  void* mtab_fwd;
-  void* mtab_adj;
-  float* tune;
-  double* part_ll;
-  double* part_rc;
-  double* part_prep;
-  double* scalars;
-  double* trace_ll;
-  double* trace_rc;
-  int* counters;  // [0] iteration counter, [4..7] validation flags
-};
-
-static void bind_views(em_ctx* c) {
+void em_bind_views(em_ctx* c) {
   char* w = c->ws;
   const Layout& L = c->lay;
   c->u = reinterpret_cast<float*>(w + L.u);
@@ -275,6 +265,7 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
     m.H = c->g.Hl;
     m.W = c->g.Wl;
     m.fpg = c->pl.adj_fpg;
+    m.ntiles = c->pl.adj_tiles;
     m.fused = 0;
     EM_HIP(launch_mfma(c->g, 1, c->pl.adj_variant, c->pl.adj_tiles, c->pl.adj_groups, m,
                        c->stream));
@@ -288,6 +279,7 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
     a.Hl = c->g.Hl;
     a.Wl = c->g.Wl;
     a.fpg = c->pl.adj_fpg;
+    a.ntiles = c->pl.adj_tiles;
     a.fused = 0;
     a.plane = dst;
     EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
@@ -297,37 +289,89 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
   return EM_OK;
 }
 
+namespace em {
+
+void fill_forward_mfma(const em_ctx* c, MfmaLaunch* m, bool write_r, bool loglik) {
+  *m = MfmaLaunch{};
+  m->in = c->x;
+  m->tab = c->mtab_fwd;
+  m->u = c->u;
+  m->y = c->y;
+  m->out = write_r ? c->r : nullptr;
+  m->part = loglik ? c->part_ll : nullptr;
+  m->n = c->g.n;
+  m->H = c->g.Hf;
+  m->W = c->g.Wf;
+  m->fpg = c->pl.fwd_fpg;
+  m->ntiles = c->pl.fwd_tiles;
+}
+
+void fill_forward_fp32(const em_ctx* c, FwdLaunch* f, bool write_r, bool loglik) {
+  *f = FwdLaunch{};
+  f->x = c->x;
+  f->tab = c->tab;
+  f->u = c->u;
+  f->y = c->y;
+  f->out = write_r ? c->r : nullptr;
+  f->part = loglik ? c->part_ll : nullptr;
+  f->n = c->g.n;
+  f->Hf = c->g.Hf;
+  f->Wf = c->g.Wf;
+  f->Hl = c->g.Hl;
+  f->Wl = c->g.Wl;
+  f->fpg = c->pl.fwd_fpg;
+  f->ntiles = c->pl.fwd_tiles;
+}
+
+void fill_adjoint_mfma(const em_ctx* c, MfmaLaunch* m, double* part_rc) {
+  const bool fused = c->pl.adj_groups == 1;
+  *m = MfmaLaunch{};
+  m->in = c->r;
+  m->tab = c->mtab_adj;
+  m->n = c->g.n;
+  m->H = c->g.Hl;
+  m->W = c->g.Wl;
+  m->fpg = c->pl.adj_fpg;
+  m->ntiles = c->pl.adj_tiles;
+  m->fused = fused ? 1 : 0;
+  m->x = c->x;
+  m->B = c->B;
+  m->part = fused ? part_rc : nullptr;
+  m->plane = c->planes;
+}
+
+void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc) {
+  const bool fused = c->pl.adj_groups == 1;
+  *a = AdjLaunch{};
+  a->in = c->r;
+  a->tab = c->tab;
+  a->n = c->g.n;
+  a->Hf = c->g.Hf;
+  a->Wf = c->g.Wf;
+  a->Hl = c->g.Hl;
+  a->Wl = c->g.Wl;
+  a->fpg = c->pl.adj_fpg;
+  a->ntiles = c->pl.adj_tiles;
+  a->fused = fused ? 1 : 0;
+  a->x = c->x;
+  a->B = c->B;
+  a->part = fused ? part_rc : nullptr;
+  a->plane = c->planes;
+}
+
+}  // namespace em
+
 // Forward pass at the current iterate: r = u F x (if write_r) and loglik partials.
 static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
   if (uses_mfma(c->g)) {
-    MfmaLaunch m{};
-    m.in = c->x;
-    m.tab = c->mtab_fwd;
-    m.u = c->u;
-    m.y = c->y;
-    m.out = write_r ? c->r : nullptr;
-    m.part = loglik ? c->part_ll : nullptr;
-    m.n = c->g.n;
-    m.H = c->g.Hf;
-    m.W = c->g.Wf;
-    m.fpg = c->pl.fwd_fpg;
+    MfmaLaunch m;
+    fill_forward_mfma(c, &m, write_r, loglik);
     EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_variant, c->pl.fwd_tiles, c->pl.fwd_groups, m,
                        c->stream));
     return EM_OK;
   }
-  FwdLaunch f{};
-  f.x = c->x;
-  f.tab = c->tab;
-  f.u = c->u;
-  f.y = c->y;
-  f.out = write_r ? c->r : nullptr;
-  f.part = loglik ? c->part_ll : nullptr;
-  f.n = c->g.n;
-  f.Hf = c->g.Hf;
-  f.Wf = c->g.Wf;
-  f.Hl = c->g.Hl;
-  f.Wl = c->g.Wl;
-  f.fpg = c->pl.fwd_fpg;
+  FwdLaunch f;
+  fill_forward_fp32(c, &f, write_r, loglik);
   EM_HIP(launch_forward(c->g, c->pl, f, c->stream));
   return EM_OK;
 }
@@ -336,37 +380,14 @@ static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
 // multiplicative update is fused into its epilogue, else it writes the partial
 // planes (the update then runs separately, update_launch).
 static int adjoint_launch(em_ctx* c, double* part_rc) {
-  const bool fused = c->pl.adj_groups == 1;
   if (uses_mfma(c->g)) {
-    MfmaLaunch m{};
-    m.in = c->r;
-    m.tab = c->mtab_adj;
-    m.n = c->g.n;
-    m.H = c->g.Hl;
-    m.W = c->g.Wl;
-    m.fpg = c->pl.adj_fpg;
-    m.fused = fused ? 1 : 0;
-    m.x = c->x;
-    m.B = c->B;
-    m.part = fused ? part_rc : nullptr;
-    m.plane = c->planes;
+    MfmaLaunch m;
+    fill_adjoint_mfma(c, &m, part_rc);
     EM_HIP(launch_mfma(c->g, 1, c->pl.adj_variant, c->pl.adj_tiles, c->pl.adj_groups, m,
                        c->stream));
   } else {
-    AdjLaunch a{};
-    a.in = c->r;
-    a.tab = c->tab;
-    a.n = c->g.n;
-    a.Hf = c->g.Hf;
-    a.Wf = c->g.Wf;
-    a.Hl = c->g.Hl;
-    a.Wl = c->g.Wl;
-    a.fpg = c->pl.adj_fpg;
-    a.fused = fused ? 1 : 0;
-    a.x = c->x;
-    a.B = c->B;
-    a.part = fused ? part_rc : nullptr;
-    a.plane = c->planes;
+    AdjLaunch a;
+    fill_adjoint_fp32(c, &a, part_rc);
     EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
   }
   return EM_OK;
@@ -404,10 +425,54 @@ static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
   return EM_OK;
 }
 
+
+static void drop_graphs(em_ctx* c) {
+  for (int k = 0; k < 2; ++k) {
+    if (c->graph_ok[k]) (void)hipGraphExecDestroy(c->graph[k]);
+    c->graph_ok[k] = false;
+  }
+}
+
+// n iterations; when the job's stream is a created stream (graph capture is not
+// available on the legacy default stream) one iteration is captured once into
+// a HIP graph and replayed.  The captured iteration holds kernels only.
+static int run_iterations(em_ctx* c, int n, bool loglik) {
+  if (n <= 0) return EM_OK;
+  const int k = loglik ? 1 : 0;
+  if (c->stream != nullptr && !c->graph_ok[k]) {
+    hipGraph_t gr = nullptr;
+    if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
+      const int rc = one_iteration(c, loglik, false);
+      const hipError_t e = hipStreamEndCapture(c->stream, &gr);
+      if (rc != EM_OK) {
+        if (gr) (void)hipGraphDestroy(gr);
+        return rc;
+      }
+      if (e == hipSuccess && gr != nullptr &&
+          hipGraphInstantiate(&c->graph[k], gr, nullptr, nullptr, 0) == hipSuccess)
+        c->graph_ok[k] = true;
+      if (gr) (void)hipGraphDestroy(gr);
+    }
+    (void)hipGetLastError();
+  }
+  if (c->graph_ok[k]) {
+    for (int i = 0; i < n; ++i) EM_HIP(hipGraphLaunch(c->graph[k], c->stream));
+    return EM_OK;
+  }
+  for (int i = 0; i < n; ++i) {
+    const int rc = one_iteration(c, loglik, false);
+    if (rc) return rc;
+  }
+  return EM_OK;
+}
+
 extern "C" {
 
-int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, const float* psf,
-            const float* x0, float* x, void* workspace, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float* v,
+                 const float* psf, const float* x0, float* x, void* workspace, size_t ws_bytes,
+                 void* stream, bool serving) {
   if (!out) return fail(EM_EINVAL, "out is NULL");
   *out = nullptr;
   Geometry g;
@@ -419,7 +484,7 @@ int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, c
     return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
   if (g.weight_mode != EM_W_ADJOINT)
     return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
-  const Plan pl = make_plan(g);
+  const Plan pl = serving ? make_serving_plan(g) : make_plan(g);
   const Layout L = make_layout(g, pl);
   if (ws_bytes < L.total)
     return fail(EM_ENOMEM, "workspace of %zu bytes, %zu needed", ws_bytes, L.total);
@@ -446,7 +511,7 @@ int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, c
   c->psf = psf;
   c->x = x;
   c->ws = static_cast<char*>(workspace);
-  bind_views(c);
+  em_bind_views(c);
 
   auto bail = [&](int code) {
     delete c;
@@ -490,6 +555,13 @@ int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, c
   return EM_OK;
 }
 
+extern "C" {
+
+int em_init(em_ctx** out, const em_problem* p, const float* y, const float* v, const float* psf,
+            const float* x0, float* x, void* workspace, size_t ws_bytes, void* stream) {
+  return init_ctx(out, p, y, v, psf, x0, x, workspace, ws_bytes, stream, false);
+}
+
 int em_iterate(em_ctx* c, int32_t n_iter, double* loglik_trace) {
   if (!c) return fail(EM_EINVAL, "ctx is NULL");
   if (n_iter < 0) return fail(EM_EINVAL, "n_iter < 0");
@@ -498,10 +570,8 @@ int em_iterate(em_ctx* c, int32_t n_iter, double* loglik_trace) {
   while (done < n_iter) {
     const int chunk = std::min(n_iter - done, TRACE_CAP);
     if (tr) EM_HIP(launch_reset_counters(c->counters, c->stream));
-    for (int k = 0; k < chunk; ++k) {
-      int rc = one_iteration(c, tr, false);
-      if (rc) return rc;
-    }
+    int rc = run_iterations(c, chunk, tr);
+    if (rc) return rc;
     if (tr) {
       EM_HIP(hipMemcpyAsync(loglik_trace + done, c->trace_ll, sizeof(double) * chunk,
                             hipMemcpyDeviceToHost, c->stream));
@@ -615,6 +685,7 @@ int em_set_variants(em_ctx* c, int32_t fwd_variant, int32_t adj_variant) {
     return fail(EM_EINVAL, "variant out of range");
   c->pl.fwd_variant = fwd_variant;
   c->pl.adj_variant = adj_variant;
+  drop_graphs(c);
   return EM_OK;
 }
 
@@ -643,8 +714,10 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
         m.u = c->u;
         m.out = c->r;
         m.fpg = c->pl.fwd_fpg;
+    m.ntiles = c->pl.fwd_tiles;
         tiles = c->pl.fwd_tiles;
         groups = c->pl.fwd_groups;
+        m.ntiles = tiles;
       } else {
         // the adjoint writes partial planes (never the iterate)
         m.in = c->r;
@@ -652,8 +725,10 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
         m.fused = 0;
         m.plane = c->pl.adj_groups > 1 ? c->planes : c->tune;
         m.fpg = c->pl.adj_fpg;
+    m.ntiles = c->pl.adj_tiles;
         tiles = c->pl.adj_tiles;
         groups = c->pl.adj_groups;
+        m.ntiles = tiles;
       }
       for (int k = 0; k <= n_rep && rc == EM_OK; ++k) {
         if (k == 1) EM_HIP(hipEventRecord(e0, c->stream));
@@ -678,6 +753,7 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
   }
   c->pl.fwd_variant = bf;
   c->pl.adj_variant = ba;
+  drop_graphs(c);
   {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[tune_key(c->g)] = std::make_pair(bf, ba);
@@ -695,6 +771,7 @@ int em_sync(em_ctx* c) {
 }
 
 int em_destroy(em_ctx* c) {
+  if (c) drop_graphs(c);
   delete c;
   return EM_OK;
 }
@@ -742,6 +819,7 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
     mm.H = g.Hf;
     mm.W = g.Wf;
     mm.fpg = pl.fwd_fpg;
+    mm.ntiles = pl.fwd_tiles;
     EM_HIP(launch_mfma(g, 0, pl.fwd_variant, pl.fwd_tiles, pl.fwd_groups, mm, s));
     return EM_OK;
   }
@@ -758,6 +836,7 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
   f.Hl = g.Hl;
   f.Wl = g.Wl;
   f.fpg = pl.fwd_fpg;
+  f.ntiles = pl.fwd_tiles;
   EM_HIP(launch_forward(g, pl, f, s));
   return EM_OK;
 }
@@ -791,6 +870,7 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
     mm.H = g.Hl;
     mm.W = g.Wl;
     mm.fpg = 1;
+    mm.ntiles = pl.adj_tiles;
     mm.fused = 0;
     EM_HIP(launch_mfma(g, 1, pl.adj_variant, pl.adj_tiles, g.n, mm, s));
     return EM_OK;
@@ -806,6 +886,7 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
   a.Wl = g.Wl;
   a.fpg = 1;
   a.fused = 0;
+  a.ntiles = pl.adj_tiles;
   EM_HIP(launch_adjoint(g, per, a, s));
   return EM_OK;
 }

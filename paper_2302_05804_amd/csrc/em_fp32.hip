@@ -10,7 +10,10 @@
 //    per kernel column b it loads the column segment into registers and applies
 //    the K taps of column b, which are wave-uniform and therefore come from
 //    scalar registers (s_load from the coefficient table);
-//  * R*K FMAs per R+K-1 LDS values keeps the kernels VALU-bound.
+//  * R*K FMAs per R+K-1 LDS values keeps the kernels VALU-bound;
+//  * sums are formed in levels (one kernel column, then one frame, then the
+//    total), which keeps the FP32 rounding error of a K*K*n-term sum near that
+//    of its ~K-term pieces instead of growing with the full chain.
 // The forward kernels loop over frames inside the workgroup (x is shared by all
 // frames, its tile is loaded once); the adjoint kernels loop over frames with
 // the per-pixel sum over frames held in registers (fixed frame order, no
@@ -26,7 +29,7 @@ namespace em {
 //   epilogue: r_t = u_t m_t (or m_t raw), FP64 partial of u (y - m)^2.
 // ---------------------------------------------------------------------------
 template <int KT, int R, int WV>
-__global__ __launch_bounds__(64 * WV) void fwd1_kernel(FwdLaunch a) {
+__device__ inline void fwd1_body(const FwdLaunch& a, const int tile, const int group) {
   constexpr int c = (KT - 1) / 2;
   constexpr int TW = 64, TH = R * WV;
   constexpr int LW = TW + KT - 1;
@@ -39,7 +42,7 @@ __global__ __launch_bounds__(64 * WV) void fwd1_kernel(FwdLaunch a) {
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tiles_x = (a.Wf + TW - 1) / TW;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int j0 = tx * TW, i0 = ty * TH;
 
   for (int e = threadIdx.x; e < LW * P; e += 64 * WV) {
@@ -52,7 +55,7 @@ __global__ __launch_bounds__(64 * WV) void fwd1_kernel(FwdLaunch a) {
   }
   __syncthreads();
 
-  const int t0 = blockIdx.y * a.fpg;
+  const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   const int64_t Nf = (int64_t)a.Hf * a.Wf;
   const int j = j0 + lane;
@@ -71,12 +74,17 @@ __global__ __launch_bounds__(64 * WV) void fwd1_kernel(FwdLaunch a) {
         xc[q] = v4.x; xc[q + 1] = v4.y; xc[q + 2] = v4.z; xc[q + 3] = v4.w;
       }
       cfloat_ptr fb = tb + b * TAB_LD;
+      float part[R];   // two-level sum: one kernel column, then the total
+#pragma unroll
+      for (int r = 0; r < R; ++r) part[r] = 0.f;
 #pragma unroll
       for (int aa = 0; aa < KT; ++aa) {
         const float fv = fb[aa];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fmaf(fv, xc[r + KT - 1 - aa], acc[r]);
+        for (int r = 0; r < R; ++r) part[r] = fmaf(fv, xc[r + KT - 1 - aa], part[r]);
       }
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += part[r];
     }
     if (j < a.Wf) {
       const int64_t base = (int64_t)t * Nf;
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(64 * WV) void fwd1_kernel(FwdLaunch a) {
   }
   if (a.part != nullptr) {
     const double s = block_sum<64 * WV>(llp, red);
-    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) a.part[(int64_t)group * a.ntiles + tile] = s;
   }
 }
 
@@ -112,7 +120,7 @@ __global__ __launch_bounds__(64 * WV) void fwd1_kernel(FwdLaunch a) {
 // phases (even / odd latent columns) so that lanes read consecutive LDS rows.
 // ---------------------------------------------------------------------------
 template <int KT, int R, int WV>
-__global__ __launch_bounds__(64 * WV) void fwd2_kernel(FwdLaunch a) {
+__device__ inline void fwd2_body(const FwdLaunch& a, const int tile, const int group) {
   constexpr int c = (KT - 1) / 2;
   constexpr int KC = KT + 1;
   constexpr int TW = 64, TH = R * WV;          // frame pixels
@@ -127,7 +135,7 @@ __global__ __launch_bounds__(64 * WV) void fwd2_kernel(FwdLaunch a) {
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tiles_x = (a.Wf + TW - 1) / TW;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int J0 = tx * TW, I0 = ty * TH;
   const int Y0 = 2 * I0 + c + 1 - KT, X0 = 2 * J0 + c + 1 - KT;
 
@@ -141,7 +149,7 @@ __global__ __launch_bounds__(64 * WV) void fwd2_kernel(FwdLaunch a) {
   }
   __syncthreads();
 
-  const int t0 = blockIdx.y * a.fpg;
+  const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   const int64_t Nf = (int64_t)a.Hf * a.Wf;
   const int J = J0 + lane;
@@ -161,12 +169,17 @@ __global__ __launch_bounds__(64 * WV) void fwd2_kernel(FwdLaunch a) {
         xc[q] = v4.x; xc[q + 1] = v4.y; xc[q + 2] = v4.z; xc[q + 3] = v4.w;
       }
       cfloat_ptr fb = tb + b * TAB_LD;
+      float part[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) part[r] = 0.f;
 #pragma unroll
       for (int aa = 0; aa < KC; ++aa) {
         const float fv = fb[aa];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fmaf(fv, xc[2 * r + KT - aa], acc[r]);
+        for (int r = 0; r < R; ++r) part[r] = fmaf(fv, xc[2 * r + KT - aa], part[r]);
       }
+#pragma unroll
+      for (int r = 0; r < R; ++r) acc[r] += part[r];
     }
     if (J < a.Wf) {
       const int64_t base = (int64_t)t * Nf;
@@ -192,7 +205,7 @@ __global__ __launch_bounds__(64 * WV) void fwd2_kernel(FwdLaunch a) {
   }
   if (a.part != nullptr) {
     const double s = block_sum<64 * WV>(llp, red);
-    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) a.part[(int64_t)group * a.ntiles + tile] = s;
   }
 }
 
@@ -212,7 +225,7 @@ __device__ inline float em_update_value(float xo, float Bv, float Dn) {
 // sr = 1 adjoint: s[k,l] = sum_{a,b} f_t[a,b] r_t[k-c+a, l-c+b], summed over t.
 // ---------------------------------------------------------------------------
 template <int KT, int R, int WV>
-__global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
+__device__ inline void adj1_body(const AdjLaunch& a, const int tile, const int group) {
   constexpr int c = (KT - 1) / 2;
   constexpr int TW = 64, TH = R * WV;
   constexpr int LW = TW + KT - 1;
@@ -225,7 +238,7 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
 
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int tiles_x = (a.Wl + TW - 1) / TW;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int l0 = tx * TW, k0 = ty * TH;
   const int64_t Nf = (int64_t)a.Hf * a.Wf;
 
@@ -233,7 +246,7 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.f;
 
-  const int t0 = blockIdx.y * a.fpg;
+  const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   for (int t = t0; t < t1; ++t) {
     const float* src = a.in + (int64_t)t * Nf;
@@ -248,6 +261,9 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
     }
     __syncthreads();
     cfloat_ptr tb = as_const(a.tab) + (int64_t)t * KT * TAB_LD;
+    float facc[R];   // this frame's sum (three-level sum: column, frame, total)
+#pragma unroll
+    for (int r = 0; r < R; ++r) facc[r] = 0.f;
     for (int b = 0; b < KT; ++b) {
       const float* col = rs + (lane + b) * P + w * R;
       float rc[NR4];
@@ -257,13 +273,20 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
         rc[q] = v4.x; rc[q + 1] = v4.y; rc[q + 2] = v4.z; rc[q + 3] = v4.w;
       }
       cfloat_ptr fb = tb + b * TAB_LD;
+      float part[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) part[r] = 0.f;
 #pragma unroll
       for (int aa = 0; aa < KT; ++aa) {
         const float fv = fb[aa];
 #pragma unroll
-        for (int r = 0; r < R; ++r) acc[r] = fmaf(fv, rc[r + aa], acc[r]);
+        for (int r = 0; r < R; ++r) part[r] = fmaf(fv, rc[r + aa], part[r]);
       }
+#pragma unroll
+      for (int r = 0; r < R; ++r) facc[r] += part[r];
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += facc[r];
   }
 
   const int l = l0 + lane;
@@ -282,7 +305,7 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
           dsq += d * d;
           xsq += (double)xo * (double)xo;
         } else {
-          a.plane[(int64_t)blockIdx.y * a.Hl * a.Wl + idx] = acc[r];
+          a.plane[(int64_t)group * a.Hl * a.Wl + idx] = acc[r];
         }
       }
     }
@@ -292,8 +315,8 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
     __syncthreads();
     const double s2 = block_sum<64 * WV>(xsq, red + WV);
     if (threadIdx.x == 0) {
-      a.part[2 * blockIdx.x] = s1;
-      a.part[2 * blockIdx.x + 1] = s2;
+      a.part[2 * tile] = s1;
+      a.part[2 * tile + 1] = s2;
     }
   }
 }
@@ -307,7 +330,7 @@ __global__ __launch_bounds__(64 * WV) void adj1_kernel(AdjLaunch a) {
 //   I = k0/2 + w R/2 + e - h        -> a' = 2 e - rr,    rr = row in strip
 // ---------------------------------------------------------------------------
 template <int KT, int R, int WV>
-__global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
+__device__ inline void adj2_body(const AdjLaunch& a, const int tile, const int group) {
   constexpr int c = (KT - 1) / 2;
   static_assert(c % 2 == 1, "sr=2 adjoint assumes odd c");
   static_assert(R % 8 == 0, "strip height must keep 16-byte LDS alignment");
@@ -326,7 +349,7 @@ __global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   const int ph = wid & 1, w = wid >> 1;
   const int tiles_x = (a.Wl + TWL - 1) / TWL;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int l0 = tx * TWL, k0 = ty * THL;
   const int Jb = l0 / 2 - h, Ib = k0 / 2 - h;
   const int64_t Nf = (int64_t)a.Hf * a.Wf;
@@ -335,7 +358,7 @@ __global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
 #pragma unroll
   for (int r = 0; r < R; ++r) acc[r] = 0.f;
 
-  const int t0 = blockIdx.y * a.fpg;
+  const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   for (int t = t0; t < t1; ++t) {
     const float* src = a.in + (int64_t)t * Nf;
@@ -350,6 +373,9 @@ __global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
     }
     __syncthreads();
     cfloat_ptr tb = as_const(a.tab) + (int64_t)t * KC * TAB_LD;
+    float facc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) facc[r] = 0.f;
     for (int dd = 0; dd < 2 * h; ++dd) {
       const float* col = rs + (lane + dd + ph) * P + w * (R / 2);
       float rc[NE4];
@@ -362,15 +388,22 @@ __global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
       float fk[KC];
 #pragma unroll
       for (int aa = 0; aa < KC; ++aa) fk[aa] = fb[aa];
+      float part[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) part[r] = 0.f;
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const int ap = 2 * e - r;
-          if (ap >= 0 && ap < KC) acc[r] = fmaf(fk[ap], rc[e], acc[r]);
+          if (ap >= 0 && ap < KC) part[r] = fmaf(fk[ap], rc[e], part[r]);
         }
       }
+#pragma unroll
+      for (int r = 0; r < R; ++r) facc[r] += part[r];
     }
+#pragma unroll
+    for (int r = 0; r < R; ++r) acc[r] += facc[r];
   }
 
   const int l = l0 + 2 * lane + ph;
@@ -389,7 +422,7 @@ __global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
           dsq += d * d;
           xsq += (double)xo * (double)xo;
         } else {
-          a.plane[(int64_t)blockIdx.y * a.Hl * a.Wl + idx] = acc[r];
+          a.plane[(int64_t)group * a.Hl * a.Wl + idx] = acc[r];
         }
       }
     }
@@ -399,11 +432,39 @@ __global__ __launch_bounds__(128 * WV) void adj2_kernel(AdjLaunch a) {
     __syncthreads();
     const double s2 = block_sum<NT>(xsq, red + NT / 64);
     if (threadIdx.x == 0) {
-      a.part[2 * blockIdx.x] = s1;
-      a.part[2 * blockIdx.x + 1] = s2;
+      a.part[2 * tile] = s1;
+      a.part[2 * tile + 1] = s2;
     }
   }
 }
+
+// ---------------------------------------------------------------------------
+// Entry points.  `*_kernel`: one job, grid (tiles, frame groups).  `*_batched`:
+// several jobs in one launch -- each work item names a job descriptor, a tile
+// and a frame group; the workgroups stride over the items (persistent loop with
+// a fixed bound, so every wave exits).  A job's arithmetic is identical in both.
+// ---------------------------------------------------------------------------
+#define EM_FP32_ENTRY(NAME, LAUNCH, BOUND)                                                      \
+  template <int KT, int R, int WV>                                                             \
+  __global__ __launch_bounds__(BOUND) void NAME##_kernel(LAUNCH a) {                           \
+    NAME##_body<KT, R, WV>(a, blockIdx.x, blockIdx.y);                                         \
+  }                                                                                            \
+  template <int KT, int R, int WV>                                                             \
+  __global__ __launch_bounds__(BOUND) void NAME##_batched(const LAUNCH* __restrict__ descs,    \
+                                                          const int4* __restrict__ items,      \
+                                                          int n_items) {                       \
+    for (int i = blockIdx.x; i < n_items; i += gridDim.x) {                                    \
+      const int4 w = items[i];                                                                 \
+      const LAUNCH d = descs[w.x];                                                             \
+      NAME##_body<KT, R, WV>(d, w.y, w.z);                                                     \
+      __syncthreads();                                                                         \
+    }                                                                                          \
+  }
+
+EM_FP32_ENTRY(fwd1, FwdLaunch, 64 * WV)
+EM_FP32_ENTRY(fwd2, FwdLaunch, 64 * WV)
+EM_FP32_ENTRY(adj1, AdjLaunch, 64 * WV)
+EM_FP32_ENTRY(adj2, AdjLaunch, 128 * WV)
 
 // ---------------------------------------------------------------------------
 // launchers
@@ -453,6 +514,44 @@ hipError_t launch_adjoint(const Geometry& g, const Plan& pl, const AdjLaunch& a,
       hipLaunchKernelGGL((adj2_kernel<KT_LARGE, A2_R, A2_WV>), grid, block, 0, s, a);
     else
       hipLaunchKernelGGL((adj2_kernel<KT_SMALL, A2_R, A2_WV>), grid, block, 0, s, a);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_forward_batched(int sr, int KT, const FwdLaunch* descs, const int4* items,
+                                  int n_items, int grid, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (sr == 1) {
+    dim3 block(64 * F1_WV);
+    if (KT == KT_LARGE)
+      hipLaunchKernelGGL((fwd1_batched<KT_LARGE, F1_R, F1_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+    else
+      hipLaunchKernelGGL((fwd1_batched<KT_SMALL, F1_R, F1_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+  } else {
+    dim3 block(64 * F2_WV);
+    if (KT == KT_LARGE)
+      hipLaunchKernelGGL((fwd2_batched<KT_LARGE, F2_R, F2_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+    else
+      hipLaunchKernelGGL((fwd2_batched<KT_SMALL, F2_R, F2_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_adjoint_batched(int sr, int KT, const AdjLaunch* descs, const int4* items,
+                                  int n_items, int grid, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (sr == 1) {
+    dim3 block(64 * A1_WV);
+    if (KT == KT_LARGE)
+      hipLaunchKernelGGL((adj1_batched<KT_LARGE, A1_R, A1_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+    else
+      hipLaunchKernelGGL((adj1_batched<KT_SMALL, A1_R, A1_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+  } else {
+    dim3 block(128 * A2_WV);
+    if (KT == KT_LARGE)
+      hipLaunchKernelGGL((adj2_batched<KT_LARGE, A2_R, A2_WV>), dim3(grid), block, 0, s, descs, items, n_items);
+    else
+      hipLaunchKernelGGL((adj2_batched<KT_SMALL, A2_R, A2_WV>), dim3(grid), block, 0, s, descs, items, n_items);
   }
   return hipGetLastError();
 }

@@ -92,6 +92,7 @@ struct FwdLaunch {
   float* out;          // r_t = u_t F_t x  (or F_t x when u == nullptr)
   double* part;        // loglik partials (nullptr => none)
   int n, Hf, Wf, Hl, Wl, fpg;
+  int ntiles;          // tiles of the job (partial index = group * ntiles + tile)
 };
 
 struct AdjLaunch {
@@ -103,6 +104,7 @@ struct AdjLaunch {
   double* part;        // change partials (fused update, may be nullptr)
   int n, Hf, Wf, Hl, Wl, fpg;
   int fused;           // 1 => x update in the epilogue (G == 1)
+  int ntiles;
 };
 
 // Matrix-core correlation kernels (em_mfma.hip), sr = 1.
@@ -118,10 +120,17 @@ struct MfmaLaunch {
   const float* B;
   int n, H, W, fpg;
   int fused;
+  int ntiles;
 };
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s);
 int mfma_table_rows(int KT);
+hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
+                               const int4* items, int n_items, int grid, hipStream_t s);
+hipError_t launch_forward_batched(int sr, int KT, const FwdLaunch* descs, const int4* items,
+                                  int n_items, int grid, hipStream_t s);
+hipError_t launch_adjoint_batched(int sr, int KT, const AdjLaunch* descs, const int4* items,
+                                  int n_items, int grid, hipStream_t s);
 int mfma_variants();
 hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                               hipStream_t s);
@@ -163,4 +172,54 @@ hipError_t launch_finalize_loglik(const double* part_ll, int n_ll, double* scala
 hipError_t launch_reset_counters(int* counters, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t s);
 
+}  // namespace em
+
+// One deconvolution job (opaque in the C ABI).
+struct em_ctx {
+  em::Geometry g;
+  em::Plan pl;
+  em::Layout lay;
+  hipStream_t stream;
+  const float* y;
+  const float* v;
+  const float* psf;
+  float* x;
+  char* ws;
+  // device views into the workspace
+  float* u;
+  float* r;
+  float* B;
+  float* planes;
+  float* tab;
+  void* mtab_fwd;
+  void* mtab_adj;
+  float* tune;
+  double* part_ll;
+  double* part_rc;
+  double* part_prep;
+  double* scalars;
+  double* trace_ll;
+  double* trace_rc;
+  int* counters;  // [0] iteration counter, [4..7] validation flags
+  // captured iteration (em_iterate without / with the FP64 trace bookkeeping)
+  hipGraphExec_t graph[2];
+  bool graph_ok[2];
+};
+
+
+void em_bind_views(em_ctx* c);
+namespace em {
+int fail(int code, const char* fmt, ...);
+// fill the launch descriptors of ctx's forward / adjoint (fused update) passes
+void fill_forward_fp32(const em_ctx* c, FwdLaunch* f, bool write_r, bool loglik);
+void fill_forward_mfma(const em_ctx* c, MfmaLaunch* m, bool write_r, bool loglik);
+void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc);
+void fill_adjoint_mfma(const em_ctx* c, MfmaLaunch* m, double* part_rc);
+// em_init with the plan used by the serving loop (single frame group in the
+// adjoint, fixed kernel variants), so a served job computes the same way
+// alone and in any mix.
+int init_ctx(em_ctx** out, const em_problem* p, const float* y, const float* v, const float* psf,
+             const float* x0, float* x, void* workspace, size_t ws_bytes, void* stream,
+             bool serving);
+Plan make_serving_plan(const Geometry& g);
 }  // namespace em

@@ -219,7 +219,7 @@ __device__ inline void mfma_frame(const unsigned short* sh_hi, const unsigned sh
 
 // Forward: r_t = u_t * (f_t * x) for the frames of this group, x tile staged once.
 template <class C>
-__global__ __launch_bounds__(C::NT) void mfma_fwd_kernel(MfmaLaunch a) {
+__device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const int group) {
   constexpr int c = (C::KT - 1) / 2;
   __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
   __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
@@ -227,12 +227,12 @@ __global__ __launch_bounds__(C::NT) void mfma_fwd_kernel(MfmaLaunch a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int k0 = ty * C::TH, l0 = tx * C::TW;
   stage_tile<C>(a.in, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
   __syncthreads();
 
-  const int t0 = blockIdx.y * a.fpg;
+  const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   const int64_t N = (int64_t)a.H * a.W;
   double llp = 0.0;
@@ -280,7 +280,7 @@ __global__ __launch_bounds__(C::NT) void mfma_fwd_kernel(MfmaLaunch a) {
   }
   if (a.part != nullptr) {
     const double s = block_sum<C::NT>(llp, red);
-    if (threadIdx.x == 0) a.part[(int64_t)blockIdx.y * gridDim.x + blockIdx.x] = s;
+    if (threadIdx.x == 0) a.part[(int64_t)group * a.ntiles + tile] = s;
   }
 }
 
@@ -294,7 +294,7 @@ __device__ inline float mf_update_value(float xo, float Bv, float Dn) {
 // Adjoint: sum over the frames of this group of F_t^T r_t; the r_t tile is
 // staged per frame.  Epilogue: partial plane, or the fused update of Eq. (2).
 template <class C>
-__global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
+__device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const int group) {
   constexpr int c = (C::KT - 1) / 2;
   __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
   __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
@@ -302,7 +302,7 @@ __global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;
-  const int tx = blockIdx.x % tiles_x, ty = blockIdx.x / tiles_x;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int k0 = ty * C::TH, l0 = tx * C::TW;
   const int64_t N = (int64_t)a.H * a.W;
 
@@ -312,7 +312,7 @@ __global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
 #pragma unroll
     for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
 
-  const int t0 = blockIdx.y * a.fpg;
+  const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
@@ -323,7 +323,7 @@ __global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
   }
 
   double dsq = 0.0, xsq = 0.0;
-  float* pl = a.fused ? nullptr : a.plane + (int64_t)blockIdx.y * N;
+  float* pl = a.fused ? nullptr : a.plane + (int64_t)group * N;
 #pragma unroll
   for (int b = 0; b < C::BR; ++b)
 #pragma unroll
@@ -353,9 +353,42 @@ __global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
     __syncthreads();
     const double s2 = block_sum<C::NT>(xsq, red + C::NW);
     if (threadIdx.x == 0) {
-      a.part[2 * blockIdx.x] = s1;
-      a.part[2 * blockIdx.x + 1] = s2;
+      a.part[2 * tile] = s1;
+      a.part[2 * tile + 1] = s2;
     }
+  }
+}
+
+// Entry points: one job (grid = tiles x frame groups) or a batch of jobs
+// (persistent workgroups striding over (job, tile, frame group) work items).
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd_kernel(MfmaLaunch a) {
+  mfma_fwd_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
+  mfma_adj_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd_batched(const MfmaLaunch* __restrict__ descs,
+                                                          const int4* __restrict__ items,
+                                                          int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const int4 w = items[i];
+    const MfmaLaunch d = descs[w.x];
+    mfma_fwd_body<C>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_adj_batched(const MfmaLaunch* __restrict__ descs,
+                                                          const int4* __restrict__ items,
+                                                          int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const int4 w = items[i];
+    const MfmaLaunch d = descs[w.x];
+    mfma_adj_body<C>(d, w.y, w.z);
+    __syncthreads();
   }
 }
 
@@ -428,6 +461,37 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
   return hipGetLastError();
 }
 }  // namespace
+
+namespace {
+template <int KT, int NS>
+hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* d, const int4* it,
+                              int n, hipStream_t s) {
+  using C0 = MfCfg<KT, NS, 4, 4, 2, 2, 1, 1>;
+  using C1 = MfCfg<KT, NS, 4, 2, 2, 4, 0, 1>;
+  using C2 = MfCfg<KT, NS, 2, 4, 4, 2, 0, 1>;
+  if (dir == 0) {
+    if (variant == 1) hipLaunchKernelGGL(mfma_fwd_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
+    else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
+    else hipLaunchKernelGGL(mfma_fwd_batched<C0>, dim3(grid), dim3(C0::NT), 0, s, d, it, n);
+  } else {
+    if (variant == 1) hipLaunchKernelGGL(mfma_adj_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
+    else if (variant == 2) hipLaunchKernelGGL(mfma_adj_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
+    else hipLaunchKernelGGL(mfma_adj_batched<C0>, dim3(grid), dim3(C0::NT), 0, s, d, it, n);
+  }
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
+                               const int4* items, int n_items, int grid, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const bool split = precision == EM_BF16_SPLIT;
+  if (KT == KT_LARGE)
+    return split ? launch_dir_batched<KT_LARGE, 3>(dir, variant, grid, descs, items, n_items, s)
+                 : launch_dir_batched<KT_LARGE, 1>(dir, variant, grid, descs, items, n_items, s);
+  return split ? launch_dir_batched<KT_SMALL, 3>(dir, variant, grid, descs, items, n_items, s)
+               : launch_dir_batched<KT_SMALL, 1>(dir, variant, grid, descs, items, n_items, s);
+}
 
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s) {

@@ -71,6 +71,19 @@ _sig = {
     "em_terms": (ctypes.c_int, [_P, _P, _P]),
     "em_profile": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
     "em_sync": (ctypes.c_int, [_P]),
+    "em_server_create": (ctypes.c_int, [_PP, ctypes.c_size_t, ctypes.c_int32, _P]),
+    "em_server_destroy": (ctypes.c_int, [_P]),
+    "em_job_bytes": (ctypes.c_size_t, [ctypes.POINTER(Problem)]),
+    "em_submit": (ctypes.c_int, [_P, ctypes.POINTER(Problem), _P, _P, _P, ctypes.c_int32,
+                                 ctypes.POINTER(ctypes.c_int64)]),
+    "em_poll": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "em_wait": (ctypes.c_int, [_P, ctypes.c_int64, _P, ctypes.POINTER(ctypes.c_double)]),
+    "em_cancel": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "em_release": (ctypes.c_int, [_P, ctypes.c_int64]),
+    "em_job_times": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double),
+                                    ctypes.POINTER(ctypes.c_double)]),
+    "em_server_stats": (ctypes.c_int, [_P, _P]),
     "em_variant_count": (ctypes.c_int, []),
     "em_set_variants": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "em_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
@@ -255,3 +268,89 @@ def adjoint_op(p: Problem, psf, r, s=None, workspace=None, stream=None):
                               _dev_ptr(s, "s", p.n_frames * hl * wl),
                               _dev_ptr(ws, "workspace"), ws.numel(), sp), "em_adjoint_op")
     return s
+
+
+def job_bytes(p: Problem) -> int:
+    return int(_lib.em_job_bytes(ctypes.byref(p)))
+
+
+class Server:
+    """Continuous-batching server (em_server_create / em_submit / em_poll / em_wait).
+
+    Inputs are host numpy float32 arrays; they are copied on submit.
+    """
+
+    def __init__(self, hbm_budget: int, max_slots: int = 8, stream=None):
+        h = ctypes.c_void_p()
+        sp = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        _check(_lib.em_server_create(ctypes.byref(h), int(hbm_budget), int(max_slots), sp),
+               "em_server_create")
+        self._h = h
+        self._shapes = {}
+
+    def submit(self, p: Problem, y, v, psf, n_iter: int) -> int:
+        y = np.ascontiguousarray(y, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        psf = np.ascontiguousarray(psf, dtype=np.float32)
+        if y.size != p.n_frames * p.frame_h * p.frame_w or v.size != y.size:
+            raise ValueError("y / v do not match the problem")
+        if psf.size != p.n_frames * p.psf_k ** 2:
+            raise ValueError("psf does not match the problem")
+        jid = ctypes.c_int64(0)
+        _check(_lib.em_submit(self._h, ctypes.byref(p), y.ctypes.data_as(_P),
+                              v.ctypes.data_as(_P), psf.ctypes.data_as(_P), int(n_iter),
+                              ctypes.byref(jid)), "em_submit")
+        self._shapes[jid.value] = p.latent_shape
+        return jid.value
+
+    def _result(self, fn, jid):
+        shape = self._shapes.get(jid)
+        x = np.empty(shape, np.float32) if shape is not None else None
+        ll = ctypes.c_double(0.0)
+        code = fn(self._h, int(jid), x.ctypes.data_as(_P) if x is not None else None,
+                  ctypes.byref(ll))
+        return code, x, ll.value
+
+    def poll(self, jid: int):
+        """(x, loglik) when done, None while pending; raises on failure."""
+        code, x, ll = self._result(_lib.em_poll, jid)
+        if code == EAGAIN:
+            return None
+        _check(code, "em_poll")
+        return x, ll
+
+    def wait(self, jid: int):
+        code, x, ll = self._result(_lib.em_wait, jid)
+        _check(code, "em_wait")
+        return x, ll
+
+    def cancel(self, jid: int):
+        _check(_lib.em_cancel(self._h, int(jid)), "em_cancel")
+
+    def release(self, jid: int):
+        _check(_lib.em_release(self._h, int(jid)), "em_release")
+        self._shapes.pop(jid, None)
+
+    def times(self, jid: int):
+        a, b, c = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        _check(_lib.em_job_times(self._h, int(jid), ctypes.byref(a), ctypes.byref(b),
+                                 ctypes.byref(c)), "em_job_times")
+        return a.value, b.value, c.value
+
+    def stats(self):
+        st = np.zeros(8, np.int64)
+        _check(_lib.em_server_stats(self._h, st.ctypes.data_as(_P)), "em_server_stats")
+        keys = ["queued", "active", "done", "failed", "cancelled", "rounds", "graphs",
+                "arena_bytes_in_use"]
+        return dict(zip(keys, st.tolist()))
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.em_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -253,3 +253,18 @@ def test_iterate_tol_stops():
     _, _, rco = oracle.run(p.y, p.v, p.psf, x0, k, relchange=True)
     np.testing.assert_allclose(rc, rco, rtol=1e-4)
     ctx.close()
+
+
+def test_hundred_iterations_fp32_and_split():
+    """The full iteration count of the workloads: FP32 within 1e-5 and the
+    split-precision matrix-core form within 1e-3 of the FP64 oracle."""
+    from paper_2302_05804_amd import em
+    p = synth.make_problem("c2", H=128, W=128, n=4, seed=101)
+    x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v), np.float32)
+    xo, tro, _ = oracle.run(p.y, p.v, p.psf, x0, 100, trace=True)
+    for prec, tol in ((em.FP32, X_TOL), (em.BF16_SPLIT, 1e-3)):
+        xg, trg = gpu_run(p.y, p.v, p.psf, 1, 100, x0=x0, precision=prec)
+        err = rel_l2(xg, xo)
+        llerr = np.abs(trg - tro).max() / np.abs(tro).max()
+        log(f"100 iterations precision {prec}: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+        assert err <= tol and llerr <= LL_TOL

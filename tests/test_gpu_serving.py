@@ -1,0 +1,126 @@
+"""Serving loop (em_submit / em_poll / em_wait): continuous batching of jobs of
+uneven size, frame count and super-resolution factor.
+
+* Each job's result is bitwise the same alone and in a mix (the launch plan of
+  a served job depends on its own shape; no reduction crosses jobs).
+* Served results match the FP64 oracle within the bar of their precision.
+* Admission respects the HBM budget and the slot count; errors, cancellation.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_05804_amd import synth
+from tests.gpu_common import log, rel_l2
+
+pytestmark = pytest.mark.gpu
+
+
+def _em():
+    from paper_2302_05804_amd import em
+    return em
+
+
+def _jobs():
+    em = _em()
+    specs = [  # (recipe, latent H, W, n, sr, precision, iterations)
+        ("c2", 96, 96, 3, 1, em.BF16_SPLIT, 7),
+        ("c3", 160, 128, 5, 1, em.FP32, 5),
+        ("c4", 128, 96, 2, 2, em.FP32, 6),
+        ("c2", 200, 136, 2, 1, em.BF16_SPLIT, 9),
+        ("c1", 64, 64, 4, 1, em.FP32, 12),
+        ("c4", 64, 192, 3, 2, em.FP32, 4),
+    ]
+    out = []
+    for k, (rec, H, W, n, sr, prec, it) in enumerate(specs):
+        p = synth.make_problem(rec, H=H, W=W, n=n, seed=700 + k)
+        prob = em.Problem.make(n, H // sr, W // sr, p.K, sr=sr, precision=prec)
+        out.append((p, prob, it))
+    return out
+
+
+def _serve(jobs, budget, slots):
+    em = _em()
+    srv = em.Server(budget, max_slots=slots)
+    ids = [srv.submit(prob, p.y, p.v, p.psf, it) for p, prob, it in jobs]
+    res = [srv.wait(j) for j in ids]
+    st = srv.stats()
+    times = [srv.times(j) for j in ids]
+    srv.close()
+    return res, st, times
+
+
+def test_alone_vs_mix_bitwise():
+    em = _em()
+    jobs = _jobs()
+    need = max(em.job_bytes(prob) for _, prob, _ in jobs)
+    alone = []
+    for job in jobs:
+        (r,), st, _ = _serve([job], need + (1 << 20), 1)
+        assert st["done"] == 1
+        alone.append(r)
+    # a budget for about three jobs at a time, four slots: jobs queue and are
+    # admitted as others finish
+    budget = int(3.2 * need)
+    mix, st, times = _serve(jobs, budget, 4)
+    log(f"mix stats: {st}")
+    assert st["done"] == len(jobs) and st["failed"] == 0
+    for (xa, la), (xm, lm) in zip(alone, mix):
+        assert np.array_equal(xa, xm)
+        assert la == lm
+    # continuous batching: some job was admitted after another finished
+    admits = sorted(t[1] for t in times)
+    dones = sorted(t[2] for t in times)
+    assert admits[-1] >= dones[0]
+
+
+def test_served_results_match_oracle():
+    em = _em()
+    jobs = _jobs()
+    res, st, _ = _serve(jobs, 512 << 20, 8)
+    for (p, prob, it), (x, ll) in zip(jobs, res):
+        x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v, p.sr), np.float32)
+        xo = oracle.run(p.y, p.v, p.psf, x0, it, p.sr)
+        llo = oracle.loglik(p.y, p.v, p.psf, xo, p.sr)
+        err = rel_l2(x, xo)
+        tol = 1e-5 if prob.precision == em.FP32 else 1e-3
+        log(f"job {p.name} {p.latent_shape} sr={p.sr} prec={prob.precision}: rel L2 {err:.2e}, "
+            f"loglik rel err {abs(ll - llo) / abs(llo):.2e}")
+        assert err <= tol
+        assert abs(ll - llo) <= 1e-5 * abs(llo)
+
+
+def test_budget_errors_cancel_and_release():
+    em = _em()
+    p = synth.make_problem("c2", H=96, W=96, n=2, seed=9)
+    prob = em.Problem.make(2, 96, 96, 43)
+    need = em.job_bytes(prob)
+    srv = em.Server(need + (1 << 20), max_slots=1)
+    big = em.Problem.make(8, 512, 512, 43)
+    yb = np.zeros((8, 512, 512), np.float32)
+    with pytest.raises(em.EMError) as ei:
+        srv.submit(big, yb, yb + 1, np.ones((8, 43, 43), np.float32), 3)
+    assert ei.value.code == em.ENOMEM
+    bad_v = p.v.copy()
+    bad_v[0, 3, 3] = 0.0
+    j_bad = srv.submit(prob, p.y, bad_v, p.psf, 3)
+    j1 = srv.submit(prob, p.y, p.v, p.psf, 40)
+    j2 = srv.submit(prob, p.y, p.v, p.psf, 5)     # queued behind j1 (one slot)
+    srv.cancel(j2)
+    with pytest.raises(em.EMError) as ei:
+        srv.wait(j_bad)
+    assert ei.value.code == em.EINVAL
+    x1, ll1 = srv.wait(j1)
+    assert np.isfinite(x1).all() and (x1 >= 0).all()
+    with pytest.raises(em.EMError) as ei:
+        srv.wait(j2)
+    assert ei.value.code == em.ECANCELED
+    j0 = srv.submit(prob, p.y, p.v, p.psf, 0)      # zero iterations: the flat start
+    x0, _ = srv.wait(j0)
+    assert np.allclose(x0, oracle.flat_x0(p.y, p.v), rtol=1e-6)
+    srv.release(j1)
+    with pytest.raises(em.EMError):
+        srv.poll(j1)
+    st = srv.stats()
+    assert st["arena_bytes_in_use"] == 0 and st["active"] == 0
+    srv.close()
