@@ -6,10 +6,15 @@ exposures of the workload: forward model F_t x for every frame, inverse-variance
 weighting, adjoint correlation, sum over frames and the multiplicative update.
 Inputs are synthetic, seeded, and resident in HBM before timing starts.
 
+Default: the HSC-shaped workload (33 frames of 4096^2, 43x43 PSFs) timed in
+the BF16 hi+lo split matrix-core form (the reported value) and in plain FP32
+on the same data, with sampled full-size pixels checked against the FP64
+oracle.  --workload c5 runs the serving stream instead.
+
 Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
-                    [--precision fp32] [--no-cpu-baseline]
+                    [--precision auto|fp32|bf16split|bf16] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -24,8 +29,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-HBM_PEAK_GBS = 8000.0
 PEAKS_TFLOPS = {"fp32": 157.3, "bf16": 2500.0}
+METRIC = "frame-Mpix EM updates/s"
 
 WORKLOADS = {
     "c1": "c1: 4 frames 128x128, latent 128x128, 15x15 Gaussian PSFs, sr=1",
@@ -34,7 +39,11 @@ WORKLOADS = {
           "1% masked (streaks, bad columns), sr=1",
     "c4": "c4: super-resolution x2, 16 frames 2048x2048, latent 4096x4096, "
           "43x43 PSFs on the latent grid, 2x2 box downsampling",
+    "c5": "c5: serving stream, Poisson arrivals, frame tiles 256-2048 px (log-uniform), "
+          "4-33 frames, sr 1 or 2, 43x43 Moffat PSFs, 50-200 iterations per job",
 }
+DTYPES = {"fp32": "f32", "bf16split": "bf16x3 (hi+lo split), f32 accumulate",
+          "bf16": "bf16, f32 accumulate"}
 
 
 def log(msg: str) -> None:
@@ -75,6 +84,7 @@ def cpu_baseline(prob, crop: int, iters: int):
 
     import oracle
     H, W = prob.frame_shape
+    crop = min(crop, H, W)
     cy, cx = (H - crop) // 2, (W - crop) // 2
     y = np.ascontiguousarray(prob.y[:, cy:cy + crop, cx:cx + crop])
     v = np.ascontiguousarray(prob.v[:, cy:cy + crop, cx:cx + crop])
@@ -87,11 +97,216 @@ def cpu_baseline(prob, crop: int, iters: int):
     fpix = prob.n * crop * crop * iters
     return {
         "value": round(fpix / dt / 1e6, 6),
-        "unit": "frame-Mpix EM updates/s",
+        "unit": METRIC,
         "cores": 1,
         "kind": "oracle",
         "sample": f"{crop}x{crop} centre crop of every frame ({prob.n} frames), {iters} "
                   f"iterations, FP64 single-threaded C oracle, {dt:.1f} s",
+    }
+
+
+def time_form(em, prob, tensors, prec_name, steps, warmup, stream):
+    """Time one precision form on resident inputs; returns a dict of figures."""
+    import torch
+    y, v, f = tensors
+    n, hf, wf = prob.y.shape
+    prec = {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "bf16": em.BF16}[prec_name]
+    p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec)
+    x = torch.empty(p.latent_shape, dtype=torch.float32, device=y.device)
+    torch.cuda.synchronize()
+    with torch.cuda.stream(stream):
+        ctx = em.Context(p, y, v, f, x, x0=None, stream=stream)
+    torch.cuda.synchronize()
+    tuned = None
+    if prec_name != "fp32":
+        fv, av, tms = ctx.autotune(3)
+        tuned = {"forward_variant": fv, "adjoint_variant": av,
+                 "variant_ms": [[round(t, 4) for t in row] for row in tms.tolist()]}
+        log(f"  autotune: forward variant {fv}, adjoint variant {av}")
+    ctx.iterate(warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    ctx.iterate(steps)          # graph-captured iteration, replayed `steps` times
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    gpu_ms = ev0.elapsed_time(ev1)
+    fpix = n * hf * wf
+    value = fpix * steps / (gpu_ms / 1e3) / 1e6
+    phases = ctx.profile(max(2, min(steps, 10)))
+    ok = bool(torch.isfinite(x).all().item()) and bool((x >= 0).all().item())
+    ctx.close()
+    kc = prob.K if prob.sr == 1 else prob.K + 1
+    flops = 2.0 * kc * kc * fpix    # one K_eff x K_eff convolution per frame pixel
+    dom = 0 if phases[0] >= phases[1] else 1
+    achieved = flops / (phases[dom] / 1e3) / 1e12
+    mf = prec_name != "fp32"
+    peak = PEAKS_TFLOPS["bf16" if mf else "fp32"]
+    name = ["forward", "adjoint"][dom]
+    log(f"  {prec_name}: {gpu_ms / steps:.3f} ms/step, {value:.1f} frame-Mpix/s; per launch "
+        f"forward {phases[0]:.3f} ms, adjoint {phases[1]:.3f} ms")
+    return {
+        "value": value, "ms_per_step": gpu_ms / steps, "tuned": tuned, "ok": ok,
+        "per_launch_ms": {"forward": round(phases[0], 4), "adjoint": round(phases[1], 4),
+                          "update": round(phases[2], 4), "iteration": round(phases[3], 4)},
+        "roofline": {"bound": "mfma" if mf else "alu", "kernel": name,
+                     "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
+                     "frac": round(achieved / peak, 4),
+                     "traffic": recorded_traffic(f"{name}-{prob.name}-{prec_name}")},
+    }
+
+
+def sampled_check(em, prob, tensors, prec_names, npts=6, seed=77):
+    """One iteration from a non-flat positive start on the full-size inputs;
+    x^(1) at sampled pixels vs the oracle evaluated at those pixels only."""
+    import numpy as np
+    import torch
+
+    import oracle
+    from paper_2302_05804_amd import synth
+    y, v, f = tensors
+    n, hf, wf = prob.y.shape
+    hl, wl = prob.latent_shape
+    level = max(oracle.flat_x0(prob.y, prob.v, prob.sr), 1.0)
+    x0 = synth.positive_start((hl, wl), level, seed=seed)
+    rng = np.random.default_rng(seed)
+    rows = rng.integers(0, hl, npts)
+    cols = rng.integers(0, wl, npts)
+    rows[0], cols[0] = 0, wl - 1          # a corner: the halo edge case
+    t0 = time.perf_counter()
+    _, _, x1o = oracle.step_at(prob.y, prob.v, prob.psf, x0, rows, cols, prob.sr)
+    log(f"  oracle at {npts} sampled pixels: {time.perf_counter() - t0:.1f} s")
+    out = {}
+    x0d = torch.from_numpy(x0).to(y.device)
+    for prec_name in prec_names:
+        prec = {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "bf16": em.BF16}[prec_name]
+        p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec)
+        x = torch.empty((hl, wl), dtype=torch.float32, device=y.device)
+        ctx = em.Context(p, y, v, f, x, x0=x0d)
+        ctx.iterate(1)
+        ctx.sync()
+        xs = x[torch.from_numpy(rows).to(y.device), torch.from_numpy(cols).to(y.device)]
+        xs = xs.double().cpu().numpy()
+        ctx.close()
+        err = float(np.max(np.abs(xs - x1o) / np.maximum(np.abs(x1o), 1e-30)))
+        out[prec_name] = err
+        log(f"  {prec_name}: max relative error of x^(1) at sampled pixels {err:.2e}")
+    return {"pixels": npts, "max_rel_err": {k: float(f"{e:.3e}") for k, e in out.items()}}
+
+
+# ---------------------------------------------------------------------------
+# serving stream (workload c5)
+# ---------------------------------------------------------------------------
+
+def serving_bench(args):
+    import numpy as np
+    import torch
+
+    from paper_2302_05804_amd import em, synth
+    t0 = time.perf_counter()
+    side_max = 2048
+    base = {1: synth.make_problem("c2", H=side_max, W=side_max, n=33, seed=5101),
+            2: synth.make_problem("c4", H=2 * side_max, W=2 * side_max, n=33, seed=5102)}
+    log(f"generated serving base data in {time.perf_counter() - t0:.1f} s")
+    jobs = synth.serving_stream(args.jobs, rate=1.0, seed=5000)
+    rng = np.random.default_rng(5003)
+
+    def job_data(j):
+        b = base[j.sr]
+        s = j.frame_side
+        oy = int(rng.integers(0, side_max - s + 1))
+        ox = int(rng.integers(0, side_max - s + 1))
+        y = np.ascontiguousarray(b.y[:j.n, oy:oy + s, ox:ox + s])
+        v = np.ascontiguousarray(b.v[:j.n, oy:oy + s, ox:ox + s])
+        return y, v, np.ascontiguousarray(b.psf[:j.n])
+
+    data = [job_data(j) for j in jobs]
+    fpix_iters = [j.n * j.frame_side ** 2 * j.n_iter for j in jobs]
+
+    def problem(j, mixed):
+        prec = em.BF16_SPLIT if (mixed and j.sr == 1) else em.FP32
+        return em.Problem.make(j.n, j.frame_side, j.frame_side, 43, sr=j.sr, precision=prec)
+
+    budget = int(args.serve_budget_gib * (1 << 30))
+
+    def run_server(arrivals):
+        srv = em.Server(budget, max_slots=args.slots)
+        t_start = time.perf_counter()
+        ids = []
+        for j, (y, v, psf), at in zip(jobs, data, arrivals):
+            delay = t_start + at - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            ids.append(srv.submit(problem(j, True), y, v, psf, j.n_iter))
+        for i in ids:
+            srv.wait(i)
+        t_end = time.perf_counter()
+        tms = [srv.times(i) for i in ids]
+        st = srv.stats()
+        srv.close()
+        lat = np.array([t[2] - t[0] for t in tms])
+        return t_end - t_start, lat, st
+
+    # capacity: everything submitted at once
+    mk, _, st = run_server([0.0] * len(jobs))
+    capacity = len(jobs) / mk
+    log(f"saturated: {len(jobs)} jobs in {mk:.2f} s = {capacity:.2f} jobs/s; stats {st}")
+    # latency at 0.8 x capacity, Poisson arrivals
+    rate = 0.8 * capacity
+    gaps = np.random.default_rng(5004).exponential(1.0 / rate, len(jobs))
+    arrivals = np.cumsum(gaps) - gaps[0]
+    mk2, lat, st2 = run_server(arrivals.tolist())
+    p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
+    log(f"Poisson at {rate:.2f} jobs/s: makespan {mk2:.2f} s, p50 {p50 * 1e3:.0f} ms, "
+        f"p99 {p99 * 1e3:.0f} ms")
+    # one job at a time, FP32, same trace: service times measured, queue simulated
+    svc = []
+    torch.cuda.synchronize()
+    for k, (j, (y, v, psf)) in enumerate(zip(jobs, data)):
+        t1 = time.perf_counter()
+        p = problem(j, False)
+        yd = torch.from_numpy(y).cuda()
+        vd = torch.from_numpy(v).cuda()
+        fd = torch.from_numpy(psf).cuda()
+        x = torch.empty(p.latent_shape, dtype=torch.float32, device="cuda")
+        ctx = em.Context(p, yd, vd, fd, x)
+        ctx.iterate(j.n_iter)
+        ctx.loglik()
+        _ = x.cpu()
+        ctx.close()
+        svc.append(time.perf_counter() - t1)
+        if (k + 1) % 50 == 0:
+            log(f"  FP32 one-at-a-time: {k + 1} jobs, {sum(svc):.1f} s")
+    finish, lat0 = 0.0, []
+    for at, s in zip(arrivals, svc):
+        start = max(at, finish)
+        finish = start + s
+        lat0.append(finish - at)
+    lat0 = np.array(lat0)
+    base_cap = len(jobs) / sum(svc)
+    log(f"FP32 one at a time: {sum(svc):.2f} s busy = {base_cap:.2f} jobs/s; same trace p50 "
+        f"{np.percentile(lat0, 50) * 1e3:.0f} ms, p99 {np.percentile(lat0, 99) * 1e3:.0f} ms")
+    total_fpix = float(sum(fpix_iters))
+    return {
+        "value": total_fpix / mk / 1e6,
+        "ms_per_step": mk / max(1, sum(j.n_iter for j in jobs)) * 1e3,
+        "serving": {
+            "jobs": len(jobs), "slots": args.slots, "hbm_budget_gib": args.serve_budget_gib,
+            "capacity_jobs_per_s": round(capacity, 3),
+            "arrival_rate_jobs_per_s": round(rate, 3),
+            "p50_latency_ms": round(float(p50) * 1e3, 1),
+            "p99_latency_ms": round(float(p99) * 1e3, 1),
+            "mixed_precision": "bf16 hi+lo split for sr=1 jobs, fp32 for sr=2 jobs",
+            "fp32_one_at_a_time": {
+                "capacity_jobs_per_s": round(base_cap, 3),
+                "frame_mpix_per_s": round(total_fpix / sum(svc) / 1e6, 1),
+                "p50_latency_ms": round(float(np.percentile(lat0, 50)) * 1e3, 1),
+                "p99_latency_ms": round(float(np.percentile(lat0, 99)) * 1e3, 1),
+            },
+            "rounds": st["rounds"], "round_graphs": st["graphs"],
+        },
     }
 
 
@@ -101,10 +316,14 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "bf16split", "bf16"])
+    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16split", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--cpu-crop", type=int, default=128)
     ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--jobs", type=int, default=200, help="c5: jobs in the stream")
+    ap.add_argument("--slots", type=int, default=16, help="c5: server slots")
+    ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="c5: HBM budget")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -114,7 +333,6 @@ def main() -> int:
               "Run with --gpus 1.", file=sys.stderr)
         return 2
 
-    import numpy as np
     import torch
 
     from paper_2302_05804_amd import em, synth
@@ -123,102 +341,56 @@ def main() -> int:
         log("no GPU visible")
         return 1
     dev = torch.device("cuda:0")
+    out = {"metric": METRIC, "unit": METRIC, "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None,
+           "data": "synthetic (seeded generator shaped like the HSC testbed)"}
+
+    if args.workload == "c5":
+        r = serving_bench(args)
+        out.update({"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                    "dtype": DTYPES["bf16split"] + " (sr=1 jobs); f32 (sr=2 jobs)",
+                    "config": {"workload": WORKLOADS["c5"], "serving": r["serving"]}})
+        print(json.dumps(out), flush=True)
+        return 0
 
     t0 = time.perf_counter()
     prob = synth.make_problem(args.workload)
     log(f"generated {args.workload}: frames {prob.y.shape} K={prob.K} sr={prob.sr} "
         f"in {time.perf_counter() - t0:.1f} s")
+    tensors = tuple(torch.from_numpy(a).to(dev) for a in (prob.y, prob.v, prob.psf))
+    stream = torch.cuda.Stream(dev)
 
+    if args.precision == "auto":
+        forms = ["bf16split", "fp32"] if prob.sr == 1 else ["fp32"]
+    else:
+        forms = [args.precision]
+    res = {}
+    for fm in forms:
+        log(f"timing {fm}")
+        res[fm] = time_form(em, prob, tensors, fm, args.steps, args.warmup, stream)
+    head = res[forms[0]]
     n, hf, wf = prob.y.shape
-    precision = {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "bf16": em.BF16}[args.precision]
-    p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=precision)
-    y = torch.from_numpy(prob.y).to(dev)
-    v = torch.from_numpy(prob.v).to(dev)
-    f = torch.from_numpy(prob.psf).to(dev)
-    x = torch.empty(p.latent_shape, dtype=torch.float32, device=dev)
-    stream = torch.cuda.current_stream(dev)
-    ctx = em.Context(p, y, v, f, x, x0=None, stream=stream)
-    torch.cuda.synchronize()
-    log("em_init done")
-    tuned = None
-    if args.precision != "fp32":
-        fv, av, tms = ctx.autotune(3)
-        tuned = {"forward_variant": fv, "adjoint_variant": av,
-                 "variant_ms": [[round(t, 4) for t in row] for row in tms.tolist()]}
-        log(f"autotune: forward variant {fv}, adjoint variant {av}, ms {tms.tolist()}")
-
-    ctx.iterate(args.warmup)
-    torch.cuda.synchronize()
-    log(f"warmup {args.warmup} done")
-
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    w0 = time.perf_counter()
-    ev0.record(stream)
-    ctx.iterate(args.steps)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - w0
-    gpu_ms = ev0.elapsed_time(ev1)
-    ms_per_step = gpu_ms / args.steps
-    fpix = n * hf * wf
-    value = fpix * args.steps / (gpu_ms / 1e3) / 1e6
-    log(f"timed {args.steps} steps: {gpu_ms:.2f} ms (wall {wall * 1e3:.2f} ms), "
-        f"{ms_per_step:.3f} ms/step, {value:.1f} frame-Mpix/s")
-
-    # per-kernel durations on the job's stream (HIP events around each launch)
-    phases = ctx.profile(max(2, min(args.steps, 10)))
-    log(f"per launch: forward {phases[0]:.3f} ms, adjoint {phases[1]:.3f} ms, "
-        f"update {phases[2]:.3f} ms, iteration {phases[3]:.3f} ms")
-    kc = prob.K if prob.sr == 1 else prob.K + 1
-    flops_per_launch = 2.0 * kc * kc * fpix   # one K_eff x K_eff conv per frame pixel
-    dom = 0 if phases[0] >= phases[1] else 1
-    dom_name = ["forward", "adjoint"][dom]
-    achieved = flops_per_launch / (phases[dom] / 1e3) / 1e12
-    mfma = args.precision != "fp32"
-    peak = PEAKS_TFLOPS["bf16" if mfma else "fp32"]
-    kernel_key = f"{dom_name}-{args.workload}-{args.precision}"
-    roofline = {
-        "bound": "mfma" if mfma else "alu",
-        "kernel": dom_name,
-        "achieved": round(achieved, 2),
-        "peak": peak,
-        "unit": "TFLOP/s",
-        "frac": round(achieved / peak, 4),
-        "traffic": recorded_traffic(kernel_key),
+    cfg = {
+        "workload": WORKLOADS[args.workload],
+        "frames": n, "frame_h": hf, "frame_w": wf,
+        "latent_h": prob.latent_shape[0], "latent_w": prob.latent_shape[1],
+        "psf_k": prob.K, "sr": prob.sr, "precision": forms[0],
+        "iterations_per_job": prob.n_iter,
+        "per_launch_ms": head["per_launch_ms"],
+        "result_finite_nonnegative": head["ok"],
+        "autotune": head["tuned"],
+        "forms": {fm: {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                       "per_launch_ms": r["per_launch_ms"], "roofline": r["roofline"]}
+                  for fm, r in res.items()},
     }
-
-    res_ok = bool(torch.isfinite(x).all().item()) and bool((x >= 0).all().item())
-    ctx.close()
-
-    out = {
-        "metric": "frame-Mpix EM updates/s",
-        "value": round(value, 2),
-        "unit": "frame-Mpix EM updates/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_per_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": {"fp32": "f32", "bf16split": "bf16x3 (hi+lo split), f32 accumulate",
-                  "bf16": "bf16, f32 accumulate"}[args.precision],
-        "data": "synthetic (seeded generator shaped like the HSC testbed)",
-        "config": {
-            "workload": WORKLOADS[args.workload],
-            "frames": n, "frame_h": hf, "frame_w": wf,
-            "latent_h": p.latent_shape[0], "latent_w": p.latent_shape[1],
-            "psf_k": prob.K, "sr": prob.sr, "precision": args.precision,
-            "iterations_per_job": prob.n_iter,
-            "per_launch_ms": {"forward": round(phases[0], 4), "adjoint": round(phases[1], 4),
-                              "update": round(phases[2], 4), "iteration": round(phases[3], 4)},
-            "result_finite_nonnegative": res_ok,
-            "autotune": tuned,
-        },
-        "roofline": roofline,
-    }
+    if "fp32" in res and forms[0] != "fp32":
+        cfg["speedup_vs_fp32"] = round(head["value"] / res["fp32"]["value"], 3)
+    if not args.no_check:
+        log("sampled full-size check against the oracle")
+        cfg["sampled_oracle_check"] = sampled_check(em, prob, tensors, forms)
+    out.update({"value": round(head["value"], 2), "ms_per_step": round(head["ms_per_step"], 4),
+                "dtype": DTYPES[forms[0]], "config": cfg, "roofline": head["roofline"]})
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a crop ...")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_crop, args.cpu_iters)
