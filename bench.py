@@ -324,6 +324,8 @@ def main() -> int:
     ap.add_argument("--jobs", type=int, default=200, help="c5: jobs in the stream")
     ap.add_argument("--slots", type=int, default=16, help="c5: server slots")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="c5: HBM budget")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -341,6 +343,14 @@ def main() -> int:
         log("no GPU visible")
         return 1
     dev = torch.device("cuda:0")
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_launch": src.numel() * 4, "launches": 3}), flush=True)
+        return 0
     out = {"metric": METRIC, "unit": METRIC, "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None,
