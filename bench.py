@@ -226,7 +226,7 @@ def serving_bench(args):
     fpix_iters = [j.n * j.frame_side ** 2 * j.n_iter for j in jobs]
 
     def problem(j, mixed):
-        prec = em.BF16_SPLIT if (mixed and j.sr == 1) else em.FP32
+        prec = em.BF16_SPLIT if mixed else em.FP32
         return em.Problem.make(j.n, j.frame_side, j.frame_side, 43, sr=j.sr, precision=prec)
 
     budget = int(args.serve_budget_gib * (1 << 30))
@@ -298,7 +298,7 @@ def serving_bench(args):
             "arrival_rate_jobs_per_s": round(rate, 3),
             "p50_latency_ms": round(float(p50) * 1e3, 1),
             "p99_latency_ms": round(float(p99) * 1e3, 1),
-            "mixed_precision": "bf16 hi+lo split for sr=1 jobs, fp32 for sr=2 jobs",
+            "mixed_precision": "bf16 hi+lo split (matrix cores) for every job",
             "fp32_one_at_a_time": {
                 "capacity_jobs_per_s": round(base_cap, 3),
                 "frame_mpix_per_s": round(total_fpix / sum(svc) / 1e6, 1),
@@ -359,7 +359,7 @@ def main() -> int:
     if args.workload == "c5":
         r = serving_bench(args)
         out.update({"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
-                    "dtype": DTYPES["bf16split"] + " (sr=1 jobs); f32 (sr=2 jobs)",
+                    "dtype": DTYPES["bf16split"],
                     "config": {"workload": WORKLOADS["c5"], "serving": r["serving"]}})
         print(json.dumps(out), flush=True)
         return 0
@@ -372,7 +372,7 @@ def main() -> int:
     stream = torch.cuda.Stream(dev)
 
     if args.precision == "auto":
-        forms = ["bf16split", "fp32"] if prob.sr == 1 else ["fp32"]
+        forms = ["bf16split", "fp32"]
     else:
         forms = [args.precision]
     res = {}

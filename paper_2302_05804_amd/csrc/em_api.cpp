@@ -98,15 +98,23 @@ Plan make_plan(const Geometry& g) {
   const int target = uses_mfma(g) ? 512 : 1024;
   pl.fwd_variant = 0;
   const bool mf = uses_mfma(g);
-  pl.fwd_tiles = mf ? (int)(cdiv(g.Wf, mfma_tile_w()) * cdiv(g.Hf, mfma_tile_h()))
-                    : (int)(cdiv(g.Wf, fwd_tile_w(g)) * cdiv(g.Hf, fwd_tile_h(g)));
+  if (mf && g.sr == 2)
+    pl.fwd_tiles = (int)(cdiv(g.Wf, mfma2_fwd_tile()) * cdiv(g.Hf, mfma2_fwd_tile()));
+  else if (mf)
+    pl.fwd_tiles = (int)(cdiv(g.Wf, mfma_tile_w()) * cdiv(g.Hf, mfma_tile_h()));
+  else
+    pl.fwd_tiles = (int)(cdiv(g.Wf, fwd_tile_w(g)) * cdiv(g.Hf, fwd_tile_h(g)));
   int fg = (int)std::min<int64_t>(g.n, cdiv(target, pl.fwd_tiles));
   fg = std::max(fg, 1);
   pl.fwd_fpg = (int)cdiv(g.n, fg);
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.adj_variant = 0;
-  pl.adj_tiles = mf ? (int)(cdiv(g.Wl, mfma_tile_w()) * cdiv(g.Hl, mfma_tile_h()))
-                    : (int)(cdiv(g.Wl, adj_tile_w(g)) * cdiv(g.Hl, adj_tile_h(g)));
+  if (mf && g.sr == 2)
+    pl.adj_tiles = (int)(cdiv(g.Wl, mfma2_adj_tile()) * cdiv(g.Hl, mfma2_adj_tile()));
+  else if (mf)
+    pl.adj_tiles = (int)(cdiv(g.Wl, mfma_tile_w()) * cdiv(g.Hl, mfma_tile_h()));
+  else
+    pl.adj_tiles = (int)(cdiv(g.Wl, adj_tile_w(g)) * cdiv(g.Hl, adj_tile_h(g)));
   if (pl.adj_tiles >= (mf ? target / 4 : target / 2)) {
     pl.adj_groups = 1;
     pl.adj_fpg = g.n;
@@ -144,8 +152,8 @@ Plan make_serving_plan(const Geometry& g) {
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
   if (uses_mfma(g)) {
-    pl.fwd_variant = 1;
-    pl.adj_variant = 2;
+    pl.fwd_variant = g.sr == 1 ? 1 : 0;
+    pl.adj_variant = g.sr == 1 ? 2 : 0;
   }
   return pl;
 }
@@ -168,10 +176,8 @@ Layout make_layout(const Geometry& g, const Plan& pl) {
   L.B = take((size_t)g.Nl * sizeof(float));
   L.planes = take(G > 1 ? (size_t)G * g.Nl * sizeof(float) : 0);
   L.tab = take((size_t)g.n * g.KC * TAB_LD * sizeof(float));
-  const size_t mtab =
-      uses_mfma(g) ? (size_t)g.n * mfma_table_rows(g.KT) * 4 * 64 * 8 * sizeof(uint16_t) : 0;
-  L.mtab_fwd = take(mtab);
-  L.mtab_adj = take(mtab);
+  L.mtab_fwd = take(uses_mfma(g) ? mfma_table_bytes(g, 0) : 0);
+  L.mtab_adj = take(uses_mfma(g) ? mfma_table_bytes(g, 1) : 0);
   L.tune = take(uses_mfma(g) ? (size_t)g.Nl * sizeof(float) : 0);
   L.part_ll = take((size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double));
   L.part_rc = take((size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double));
@@ -480,8 +486,6 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
   if (g.precision == EM_FP16_SPLIT)
     return fail(EM_ENOTSUP, "precision %d not provided", g.precision);
-  if (uses_mfma(g) && g.sr != 1)
-    return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
   if (g.weight_mode != EM_W_ADJOINT)
     return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
   const Plan pl = serving ? make_serving_plan(g) : make_plan(g);
@@ -809,7 +813,6 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
   EM_HIP(launch_reset_counters(flags, s));
   EM_HIP(launch_psf_tables(g, psf, tab, flags, s));
   if (uses_mfma(g)) {
-    if (g.sr != 1) return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
     EM_HIP(launch_mfma_tables(g, psf, w + L.mtab_fwd, w + L.mtab_adj, s));
     MfmaLaunch mm{};
     mm.in = x;
@@ -860,7 +863,6 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
   per.adj_fpg = 1;
   per.adj_groups = g.n;
   if (uses_mfma(g)) {
-    if (g.sr != 1) return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
     EM_HIP(launch_mfma_tables(g, psf, w + L.mtab_fwd, w + L.mtab_adj, s));
     MfmaLaunch mm{};
     mm.in = r;

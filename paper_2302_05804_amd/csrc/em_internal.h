@@ -125,6 +125,16 @@ struct MfmaLaunch {
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s);
 int mfma_table_rows(int KT);
+// sr = 2 matrix-core kernels (em_mfma2.hip); K <= 43 padded to 43
+hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int groups,
+                        const MfmaLaunch& a, hipStream_t s);
+hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
+                                const int4* items, int n_items, int grid, hipStream_t s);
+hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
+                               hipStream_t s);
+size_t mfma2_table_bytes(int n, int dir);
+int mfma2_fwd_tile();
+int mfma2_adj_tile();
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
                                const int4* items, int n_items, int grid, hipStream_t s);
 hipError_t launch_forward_batched(int sr, int KT, const FwdLaunch* descs, const int4* items,
@@ -136,6 +146,7 @@ hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd
                               hipStream_t s);
 int mfma_tile_h();
 int mfma_tile_w();
+size_t mfma_table_bytes(const Geometry& g, int dir);
 
 hipError_t launch_forward(const Geometry& g, const Plan& pl, const FwdLaunch& a, hipStream_t s);
 hipError_t launch_adjoint(const Geometry& g, const Plan& pl, const AdjLaunch& a, hipStream_t s);

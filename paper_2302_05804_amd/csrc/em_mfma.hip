@@ -29,17 +29,11 @@
 //    order of the MFMA B operand and read from global memory (L2-resident).
 #include "em_device.h"
 #include "em_internal.h"
+#include "em_mfma_common.h"
 
 namespace em {
 
-typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
-typedef __attribute__((ext_vector_type(4))) float f32x4;
-
-// Row pitch (bf16 elements) of an LDS plane holding `cols` columns: rows stay
-// 16-byte aligned and the pitch is an odd number of 16-byte chunks.
-__host__ __device__ constexpr int mf_pitch(int cols) {
-  return (((cols + 7) / 8) % 2 == 1) ? ((cols + 7) / 8) * 8 : ((cols + 7) / 8) * 8 + 8;
-}
+constexpr int MF_TILE = 128;   // every sr = 1 variant covers 128 x 128 outputs
 
 // Tile configuration: each wave owns BR x BC blocks of 16 x 16 outputs, the
 // workgroup WR x WC waves.
@@ -57,18 +51,6 @@ struct MfCfg {
   static constexpr int MMAX = (KT + 15) / 16;   // members of the largest tap class
   static constexpr int KTP = 16 * MMAX;         // table rows (zero beyond KT)
 };
-
-constexpr int MF_TILE = 128;   // every variant covers 128 x 128 outputs
-
-__device__ inline unsigned short bf16_bits(__bf16 v) { return __builtin_bit_cast(unsigned short, v); }
-
-// v = hi + lo with hi = bf16(v), lo = bf16(v - hi) (round to nearest even).
-__device__ inline void split_bf16(float v, unsigned short& hi, unsigned short& lo) {
-  const __bf16 h = (__bf16)v;
-  const float rest = v - (float)h;
-  hi = bf16_bits(h);
-  lo = bf16_bits((__bf16)rest);
-}
 
 // Stage an input tile (FP32 image, rows [r0, r0 + ROWS), cols [q0, q0 + COLS),
 // zero outside [0,H) x [0,W)) into the hi / lo LDS planes.
@@ -284,12 +266,6 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
   }
 }
 
-__device__ inline float mf_update_value(float xo, float Bv, float Dn) {
-  if (xo == 0.f) return 0.f;
-  if (Dn == 0.f) return xo;
-  const float q = fmaxf(Bv, 0.f) / Dn;
-  return xo * q;
-}
 
 // Adjoint: sum over the frames of this group of F_t^T r_t; the r_t tile is
 // staged per frame.  Epilogue: partial plane, or the fused update of Eq. (2).
@@ -426,6 +402,7 @@ int mfma_table_rows(int KT) { return 16 * ((KT + 15) / 16); }
 
 hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                               hipStream_t s) {
+  if (g.sr == 2) return launch_mfma2_tables(g, psf, tab_fwd, tab_adj, s);
   const int KTP = mfma_table_rows(g.KT);
   dim3 grid(g.n, KTP);
   hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, KTP, 0,
@@ -437,6 +414,11 @@ hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd
 
 int mfma_tile_h() { return MF_TILE; }
 int mfma_tile_w() { return MF_TILE; }
+
+size_t mfma_table_bytes(const Geometry& g, int dir) {
+  if (g.sr == 2) return mfma2_table_bytes(g.n, dir);
+  return (size_t)g.n * mfma_table_rows(g.KT) * 4 * 64 * 8 * sizeof(uint16_t);
+}
 int mfma_variants() { return 3; }
 
 namespace {
@@ -495,6 +477,7 @@ hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, cons
 
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s) {
+  if (g.sr == 2) return launch_mfma2(g, dir, variant, tiles, groups, a, s);
   dim3 grid(tiles, groups);
   const bool split = g.precision == EM_BF16_SPLIT;
   if (g.KT == KT_LARGE)

@@ -1,0 +1,540 @@
+// em_mfma2.hip -- BF16 matrix-core (MFMA) form of the two convolutions of one
+// EM iteration with super-resolution factor 2 (arXiv:2302.05804, Sec. 2,
+// Eq. (3) and Eq. (2)).
+//
+// With k = h * 1_{2x2} (the (K+1) x (K+1) kernel of the 2x2 box sum of
+// h * x read at stride 2; K = 43, K+1 = 44, c+1 = 22):
+//   forward  m[I][J] = sum_{a,b} g[a][b] x[2I - 21 + a][2J - 21 + b],  g = k flipped,
+//   adjoint  s[k][l] = sum_{I,J} r[I][J] k[2I + 22 - k][2J + 22 - l].
+//
+// Forward: output blocks of 16 x 16 frame pixels.  For each kernel row a the
+// sum over b is a product with a stride-2 banded Toeplitz matrix,
+//   O += X_a(16 x 96) . U_a(96 x 16),  X_a[i][p] = x[2(I0+i) - 21 + a][2 J0 - 21 + p],
+//   U_a[p][j] = g[a][p - 2j]  (0 <= p - 2j < 44),
+// three v_mfma_f32_16x16x32_bf16 k-chunks per row (44 of 96 p-values of a
+// column are non-zero).  Rows a = r + 32 m share A fragments across block rows.
+//
+// Adjoint: output rows are split by parity q (k = 2i + q).  For each parity the
+// sum is a 22-tap correlation on the frame grid,
+//   s[2i+q][l] = sum_{alpha,J} k[2 alpha + q][2J + 22 - l] r[i + alpha + q - 11][J],
+// and for 16 consecutive latent columns the column sum is one Toeplitz product
+// within a single 32-wide k-chunk: U[p][j] = k[2 alpha + q][2p - j].  A fragment
+// of r rows (sigma + i) serves parity 0 with alpha = sigma - 16 beta and parity 1
+// with alpha - 1, so one LDS read feeds both output parities.
+//
+// Precision and data movement as for sr = 1 (em_mfma.hip): hi + lo bf16 split
+// operands, three products, FP32 accumulation; input tile in LDS as hi / lo
+// planes; Toeplitz fragments pre-built per frame in MFMA lane order.
+#include "em_device.h"
+#include "em_internal.h"
+#include "em_mfma_common.h"
+
+namespace em {
+
+constexpr int M2_KC = 44;        // box-extended kernel size for K = 43
+constexpr int M2_FROWS = 64;     // forward table rows (44 used, 2 classes of 32)
+constexpr int M2_FCH = 3;        // forward k-chunks per kernel row
+constexpr int M2_AROWS = 32;     // adjoint table rows per parity (22 used)
+constexpr int M2_FTILE = 64;     // forward: 64 x 64 frame pixels per workgroup
+constexpr int M2_ATILE = 128;    // adjoint: 128 x 128 latent pixels per workgroup
+
+template <int ROWS, int COLS, int PITCH, int NT>
+__device__ inline void stage_split_tile(const float* __restrict__ src, int H, int W, int r0,
+                                        int q0, unsigned short* sh_hi, unsigned short* sh_lo) {
+  constexpr int HALF = COLS / 2;
+  for (int e = threadIdx.x; e < ROWS * HALF; e += NT) {
+    const int row = e / HALF, cp = e - row * HALF;
+    const int gy = r0 + row, gx = q0 + 2 * cp;
+    float v0 = 0.f, v1 = 0.f;
+    if (gy >= 0 && gy < H) {
+      const float* rp = src + (int64_t)gy * W;
+      if (gx >= 0 && gx < W) v0 = rp[gx];
+      if (gx + 1 >= 0 && gx + 1 < W) v1 = rp[gx + 1];
+    }
+    unsigned short h0, l0, h1, l1;
+    split_bf16(v0, h0, l0);
+    split_bf16(v1, h1, l1);
+    const int o = row * PITCH + 2 * cp;
+    *reinterpret_cast<unsigned int*>(sh_hi + o) = (unsigned int)h0 | ((unsigned int)h1 << 16);
+    *reinterpret_cast<unsigned int*>(sh_lo + o) = (unsigned int)l0 | ((unsigned int)l1 << 16);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// forward, sr = 2
+// ---------------------------------------------------------------------------
+template <int NS_, int BR_, int BC_, int WR_, int WC_>
+struct M2F {
+  static constexpr int NS = NS_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int NW = WR * WC, NT = 64 * NW;
+  static constexpr int TH = 16 * BR * WR, TW = 16 * BC * WC;      // frame pixels
+  static constexpr int ROWS = 2 * TH + M2_KC - 2;                   // latent rows staged
+  static constexpr int COLS = 2 * TW + 64;                          // latent cols staged
+  static constexpr int PITCH = mf_pitch(COLS);
+};
+
+template <class C>
+__device__ inline void m2f_load_T(bf16x8 (&T)[2][M2_FCH][2], const bf16x8* __restrict__ tab_t,
+                                  int r) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int m = 0; m < 2; ++m)
+#pragma unroll
+    for (int h = 0; h < M2_FCH; ++h)
+#pragma unroll
+      for (int s = 0; s < (C::NS == 3 ? 2 : 1); ++s)
+        T[m][h][s] = tab_t[(((r + 32 * m) * M2_FCH + h) * 2 + s) * 64 + lane];
+}
+
+// one tap class a = r + 32 m (m < NM)
+template <class C, int NM>
+__device__ inline void m2f_class(int r, const unsigned short* sh_hi, const unsigned short* sh_lo,
+                                 const bf16x8 (&T)[2][M2_FCH][2], int row_base, int col_base,
+                                 f32x4 (&acc)[C::BR][C::BC]) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, g = lane >> 4;
+  constexpr int NRHO = C::BR + NM - 1;
+  constexpr int NK = C::BC + M2_FCH - 1;
+#pragma unroll
+  for (int rho = 0; rho < NRHO; ++rho) {
+    const int lrow = row_base + r + 32 * rho + 2 * i;
+    bf16x8 A[NK][2];
+#pragma unroll
+    for (int kap = 0; kap < NK; ++kap) {
+      const int o = lrow * C::PITCH + col_base + 32 * kap + 8 * g;
+      A[kap][0] = *reinterpret_cast<const bf16x8*>(sh_hi + o);
+      if (C::NS == 3) A[kap][1] = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+    }
+#pragma unroll
+    for (int s = 0; s < C::NS; ++s)
+#pragma unroll
+      for (int kap = 0; kap < NK; ++kap)
+#pragma unroll
+        for (int m = 0; m < NM; ++m) {
+          const int beta = rho - m;
+          if (beta < 0 || beta >= C::BR) continue;
+#pragma unroll
+          for (int h = 0; h < M2_FCH; ++h) {
+            const int gam = kap - h;
+            if (gam < 0 || gam >= C::BC) continue;
+            acc[beta][gam] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                A[kap][s == 1 ? 1 : 0], T[m][h][s == 2 ? 1 : 0], acc[beta][gam], 0, 0, 0);
+          }
+        }
+  }
+}
+
+template <class C>
+__device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int group) {
+  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ double red[C::NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w / C::WC, wc = w % C::WC;
+  const int tiles_x = (a.W + C::TW - 1) / C::TW;      // a.H, a.W: frame grid
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int I0 = ty * C::TH, J0 = tx * C::TW;
+  const int Hl = 2 * a.H, Wl = 2 * a.W;
+  stage_split_tile<C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, Hl, Wl, 2 * I0 - 21, 2 * J0 - 21,
+                                                      sh_hi, sh_lo);
+  __syncthreads();
+  const int row_base = wr * 32 * C::BR;    // latent rows of this wave's block row 0
+  const int col_base = wc * 32 * C::BC;    // latent cols
+  const int t0 = group * a.fpg;
+  const int t1 = min(a.n, t0 + a.fpg);
+  const int64_t N = (int64_t)a.H * a.W;
+  double llp = 0.0;
+  for (int t = t0; t < t1; ++t) {
+    __asm__ volatile("" ::: "memory");   // keep tile reads inside the frame loop
+    f32x4 acc[C::BR][C::BC];
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const bf16x8* tab_t =
+        reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * M2_FROWS * M2_FCH * 2 * 64;
+    bf16x8 Tc[2][M2_FCH][2], Tn[2][M2_FCH][2];
+    m2f_load_T<C>(Tc, tab_t, 0);
+    for (int r = 0; r < 32; ++r) {
+      if (r + 1 < 32) m2f_load_T<C>(Tn, tab_t, r + 1);
+      if (r < M2_KC - 32) m2f_class<C, 2>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+      else m2f_class<C, 1>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int h = 0; h < M2_FCH; ++h)
+#pragma unroll
+          for (int q = 0; q < 2; ++q) Tc[m][h][q] = Tn[m][h][q];
+    }
+    const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
+    const float* yt = a.y ? a.y + (int64_t)t * N : nullptr;
+    float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int q = 0; q < C::BC; ++q) {
+        const int J = J0 + wc * 16 * C::BC + 16 * q + (lane & 15);
+        const int Ib = I0 + wr * 16 * C::BR + 16 * b + 4 * (lane >> 4);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int I = Ib + v;
+          if (I < a.H && J < a.W) {
+            const int off = I * a.W + J;
+            const float m = acc[b][q][v];
+            if (ut == nullptr) {
+              ot[off] = m;
+            } else {
+              const float uu = ut[off];
+              if (ot) ot[off] = uu * m;
+              if (a.part != nullptr && uu > 0.f) {
+                const double d = (double)yt[off] - (double)m;
+                llp += (double)uu * d * d;
+              }
+            }
+          }
+        }
+      }
+  }
+  if (a.part != nullptr) {
+    const double s = block_sum<C::NT>(llp, red);
+    if (threadIdx.x == 0) a.part[(int64_t)group * a.ntiles + tile] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// adjoint, sr = 2
+// ---------------------------------------------------------------------------
+template <int NS_, int BR_, int BC_, int WR_, int WC_>
+struct M2A {
+  static constexpr int NS = NS_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int NW = WR * WC, NT = 64 * NW;
+  static constexpr int THL = 32 * BR * WR, TWL = 16 * BC * WC;     // latent pixels
+  // frame rows staged: THL/2 + 22 are read; the margin keeps every fragment
+  // address of the unrolled class loop inside the tile
+  static constexpr int ROWS = THL / 2 + 32;
+  static constexpr int COLS = TWL / 2 + 24;                         // frame cols staged
+  static constexpr int PITCH = mf_pitch(COLS);
+};
+
+// Toeplitz fragments of adjoint class r: T[q][m] for alpha = r - q + 16 m.
+template <class C>
+__device__ inline void m2a_load_T(bf16x8 (&T)[2][2][2], const bf16x8* __restrict__ tab_t, int r) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+      int al = r - q + 16 * m;
+      al = al < 0 ? M2_AROWS - 1 : al;    // (alpha = -1 is never used; row 31 is zero)
+#pragma unroll
+      for (int s = 0; s < (C::NS == 3 ? 2 : 1); ++s)
+        T[q][m][s] = tab_t[((q * M2_AROWS + al) * 2 + s) * 64 + lane];
+    }
+}
+
+// One class of the adjoint: fragment rows R + 16 rho + i (R compile-time, so the
+// validity of every (parity, tap) pair folds away).
+template <class C, int R>
+__device__ inline void m2a_class(const unsigned short* sh_hi, const unsigned short* sh_lo,
+                                 const bf16x8 (&T)[2][2][2], int row_base, int col_base,
+                                 f32x4 (&acc)[2][C::BR][C::BC]) {
+  const int lane = threadIdx.x & 63;
+  const int i = lane & 15, g = lane >> 4;
+#pragma unroll
+  for (int rho = 0; rho < C::BR + 1; ++rho) {
+    // skip fragment rows no (parity, tap) pair of this class uses
+    bool used = false;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int m = 0; m < 2; ++m) {
+        const int beta = rho - m, al = R - q + 16 * m;
+        used = used || (beta >= 0 && beta < C::BR && al >= 0 && al < 22);
+      }
+    if (!used) continue;
+    const int lrow = row_base + R + 16 * rho + i;
+    bf16x8 A[C::BC][2];
+#pragma unroll
+    for (int gam = 0; gam < C::BC; ++gam) {
+      const int o = lrow * C::PITCH + col_base + 8 * gam + 8 * g;
+      A[gam][0] = *reinterpret_cast<const bf16x8*>(sh_hi + o);
+      if (C::NS == 3) A[gam][1] = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+    }
+#pragma unroll
+    for (int s = 0; s < C::NS; ++s)
+#pragma unroll
+      for (int gam = 0; gam < C::BC; ++gam)
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+          for (int m = 0; m < 2; ++m) {
+            // alpha = R - q + 16 m serves block row beta = rho - m
+            const int beta = rho - m;
+            if (beta < 0 || beta >= C::BR) continue;
+            const int al = R - q + 16 * m;
+            if (al < 0 || al >= 22) continue;
+            acc[q][beta][gam] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                A[gam][s == 1 ? 1 : 0], T[q][m][s == 2 ? 1 : 0], acc[q][beta][gam], 0, 0, 0);
+          }
+  }
+}
+
+// Classes R .. 15 with the next class's Toeplitz fragments fetched early.
+template <class C, int R>
+__device__ inline void m2a_classes(const unsigned short* sh_hi, const unsigned short* sh_lo,
+                                   const bf16x8* __restrict__ tab_t, bf16x8 (&Tc)[2][2][2],
+                                   int row_base, int col_base, f32x4 (&acc)[2][C::BR][C::BC]) {
+  if constexpr (R < 16) {
+    bf16x8 Tn[2][2][2];
+    if constexpr (R + 1 < 16) m2a_load_T<C>(Tn, tab_t, R + 1);
+    m2a_class<C, R>(sh_hi, sh_lo, Tc, row_base, col_base, acc);
+    if constexpr (R + 1 < 16) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int m = 0; m < 2; ++m)
+#pragma unroll
+          for (int s = 0; s < 2; ++s) Tc[q][m][s] = Tn[q][m][s];
+      m2a_classes<C, R + 1>(sh_hi, sh_lo, tab_t, Tc, row_base, col_base, acc);
+    }
+  }
+}
+
+template <class C>
+__device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int group) {
+  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ double red[2 * C::NW];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wr = w / C::WC, wc = w % C::WC;
+  const int Hf = a.H / 2, Wf = a.W / 2;             // a.H, a.W: latent grid
+  const int tiles_x = (a.W + C::TWL - 1) / C::TWL;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int K0 = ty * C::THL, L0 = tx * C::TWL;     // both even
+  const int64_t Nf = (int64_t)Hf * Wf;
+  const int64_t Nl = (int64_t)a.H * a.W;
+  const int row_base = wr * 16 * C::BR;             // frame rows (relative to K0/2 - 11)
+  const int col_base = wc * 8 * C::BC;              // frame cols (relative to L0/2 - 11)
+
+  f32x4 acc[2][C::BR][C::BC];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int c2 = 0; c2 < C::BC; ++c2) acc[q][b][c2] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = group * a.fpg;
+  const int t1 = min(a.n, t0 + a.fpg);
+  for (int t = t0; t < t1; ++t) {
+    __syncthreads();
+    stage_split_tile<C::ROWS, C::COLS, C::PITCH, C::NT>(a.in + (int64_t)t * Nf, Hf, Wf,
+                                                        K0 / 2 - 11, L0 / 2 - 11, sh_hi, sh_lo);
+    __syncthreads();
+    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * 2 * M2_AROWS * 2 * 64;
+    // classes r = 0..15 (fragment rows r + 16 rho) cover every (parity, tap) once
+    bf16x8 Tc[2][2][2];
+    m2a_load_T<C>(Tc, tab_t, 0);
+    m2a_classes<C, 0>(sh_hi, sh_lo, tab_t, Tc, row_base, col_base, acc);
+  }
+
+  double dsq = 0.0, xsq = 0.0;
+  float* pl = a.fused ? nullptr : a.plane + (int64_t)group * Nl;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int c2 = 0; c2 < C::BC; ++c2) {
+        const int l = L0 + wc * 16 * C::BC + 16 * c2 + (lane & 15);
+        const int ib = wr * 16 * C::BR + 16 * b + 4 * (lane >> 4);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = K0 + 2 * (ib + v) + q;
+          if (k < a.H && l < a.W) {
+            const int off = k * a.W + l;
+            if (a.fused) {
+              const float xo = a.x[off];
+              const float xn = mf_update_value(xo, a.B[off], acc[q][b][c2][v]);
+              a.x[off] = xn;
+              const double d = (double)xn - (double)xo;
+              dsq += d * d;
+              xsq += (double)xo * (double)xo;
+            } else {
+              pl[off] = acc[q][b][c2][v];
+            }
+          }
+        }
+      }
+  if (a.fused && a.part != nullptr) {
+    const double s1 = block_sum<C::NT>(dsq, red);
+    __syncthreads();
+    const double s2 = block_sum<C::NT>(xsq, red + C::NW);
+    if (threadIdx.x == 0) {
+      a.part[2 * tile] = s1;
+      a.part[2 * tile + 1] = s2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// entry points
+// ---------------------------------------------------------------------------
+template <class C>
+__global__ __launch_bounds__(C::NT) void m2f_kernel(MfmaLaunch a) {
+  m2f_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void m2a_kernel(MfmaLaunch a) {
+  m2a_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void m2f_batched(const MfmaLaunch* __restrict__ descs,
+                                                     const int4* __restrict__ items, int n) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    const MfmaLaunch d = descs[w.x];
+    m2f_body<C>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void m2a_batched(const MfmaLaunch* __restrict__ descs,
+                                                     const int4* __restrict__ items, int n) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    const MfmaLaunch d = descs[w.x];
+    m2a_body<C>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
+
+// Toeplitz tables (one block per frame and table row):
+//  dir 0 (forward): [t][a < 64][h < 3][s][lane] = U_a[32h + 8(lane/16) + e][lane%16],
+//                   U_a[p][j] = g[a][p - 2j], g = k flipped (a >= 44: zero);
+//  dir 1 (adjoint): [t][q][alpha < 32][s][lane] = k[2 alpha + q][2p - j],
+//                   p = 8(lane/16) + e, j = lane%16 (alpha >= 22: zero).
+// k = 2x2-box extension of f zero-padded from K to 43.
+__global__ __launch_bounds__(384) void m2_table_kernel(const float* psf, int K, int dir,
+                                                       unsigned short* tab) {
+  const int t = blockIdx.x, row = blockIdx.y;
+  const int off = (43 - K) / 2;
+  const float* f = psf + (int64_t)t * K * K;
+  auto fp = [&](int a, int b) -> float {
+    const int ia = a - off, ib = b - off;
+    if (ia < 0 || ia >= K || ib < 0 || ib >= K) return 0.f;
+    return f[ia * K + ib];
+  };
+  auto kk = [&](int a, int b) -> float {   // 44 x 44 box-extended kernel
+    if (a < 0 || a >= M2_KC || b < 0 || b >= M2_KC) return 0.f;
+    return (fp(a - 1, b - 1) + fp(a - 1, b)) + (fp(a, b - 1) + fp(a, b));
+  };
+  const int idx = threadIdx.x;
+  if (dir == 0) {
+    // row = a in [0, 64); idx = (h, s, lane) = 3 x 2 x 64
+    if (idx >= M2_FCH * 2 * 64) return;
+    const int lane = idx & 63, s = (idx >> 6) & 1, h = idx >> 7;
+    const int j = lane & 15, gq = lane >> 4;
+    unsigned short* dst =
+        tab + ((((int64_t)t * M2_FROWS + row) * M2_FCH + h) * 2 + s) * 64 * 8 + lane * 8;
+    for (int e = 0; e < 8; ++e) {
+      const int p = 32 * h + 8 * gq + e;
+      const int b = p - 2 * j;
+      float gv = 0.f;
+      if (row < M2_KC && b >= 0 && b < M2_KC) gv = kk(M2_KC - 1 - row, M2_KC - 1 - b);
+      unsigned short hi, lo;
+      split_bf16(gv, hi, lo);
+      dst[e] = s == 0 ? hi : lo;
+    }
+  } else {
+    // row = q * 32 + alpha; idx = (s, lane) = 2 x 64
+    if (idx >= 2 * 64) return;
+    const int q = row / M2_AROWS, al = row % M2_AROWS;
+    const int lane = idx & 63, s = idx >> 6;
+    const int j = lane & 15, gq = lane >> 4;
+    unsigned short* dst = tab + ((((int64_t)t * 2 + q) * M2_AROWS + al) * 2 + s) * 64 * 8 + lane * 8;
+    for (int e = 0; e < 8; ++e) {
+      const int p = 8 * gq + e;
+      const int b = 2 * p - j;
+      float gv = 0.f;
+      if (al < 22 && b >= 0 && b < M2_KC) gv = kk(2 * al + q, b);
+      unsigned short hi, lo;
+      split_bf16(gv, hi, lo);
+      dst[e] = s == 0 ? hi : lo;
+    }
+  }
+}
+
+size_t mfma2_table_bytes(int n, int dir) {
+  return dir == 0 ? (size_t)n * M2_FROWS * M2_FCH * 2 * 64 * 8 * 2
+                  : (size_t)n * 2 * M2_AROWS * 2 * 64 * 8 * 2;
+}
+
+hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(m2_table_kernel, dim3(g.n, M2_FROWS), dim3(384), 0, s, psf, g.K, 0,
+                     static_cast<unsigned short*>(tab_fwd));
+  hipLaunchKernelGGL(m2_table_kernel, dim3(g.n, 2 * M2_AROWS), dim3(384), 0, s, psf, g.K, 1,
+                     static_cast<unsigned short*>(tab_adj));
+  return hipGetLastError();
+}
+
+int mfma2_fwd_tile() { return M2_FTILE; }
+int mfma2_adj_tile() { return M2_ATILE; }
+
+namespace {
+// forward variants (64 x 64 frame pixels): 0: 4 waves of 2x2 blocks; 1: 8 waves of 2x1;
+// 2: 8 waves of 1x2.  adjoint variants (128 x 128 latent): 0: 8 waves of 2x2 blocks
+// (per parity); 1: 4 waves of 4x2; 2: 4 waves of 2x4.
+template <int NS>
+hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
+                   const MfmaLaunch* d, const int4* it, int n, hipStream_t s) {
+  using F0 = M2F<NS, 2, 2, 2, 2>;
+  using F1 = M2F<NS, 2, 1, 2, 4>;
+  using F2 = M2F<NS, 1, 2, 4, 2>;
+  using A0 = M2A<NS, 2, 2, 2, 4>;
+  using A1 = M2A<NS, 4, 2, 1, 4>;
+  using A2 = M2A<NS, 2, 4, 2, 2>;
+  static_assert(F0::TH == M2_FTILE && F0::TW == M2_FTILE && F1::TH == M2_FTILE &&
+                F1::TW == M2_FTILE && F2::TH == M2_FTILE && F2::TW == M2_FTILE, "fwd tile");
+  static_assert(A0::THL == M2_ATILE && A0::TWL == M2_ATILE && A1::THL == M2_ATILE &&
+                A1::TWL == M2_ATILE && A2::THL == M2_ATILE && A2::TWL == M2_ATILE, "adj tile");
+#define EM_M2_LAUNCH(KER, CFG)                                                          \
+  do {                                                                                  \
+    if (batched)                                                                        \
+      hipLaunchKernelGGL(KER##_batched<CFG>, grid, dim3(CFG::NT), 0, s, d, it, n);      \
+    else                                                                                \
+      hipLaunchKernelGGL(KER##_kernel<CFG>, grid, dim3(CFG::NT), 0, s, a);              \
+  } while (0)
+  if (dir == 0) {
+    if (variant == 1) EM_M2_LAUNCH(m2f, F1);
+    else if (variant == 2) EM_M2_LAUNCH(m2f, F2);
+    else EM_M2_LAUNCH(m2f, F0);
+  } else {
+    if (variant == 1) EM_M2_LAUNCH(m2a, A1);
+    else if (variant == 2) EM_M2_LAUNCH(m2a, A2);
+    else EM_M2_LAUNCH(m2a, A0);
+  }
+#undef EM_M2_LAUNCH
+  return hipGetLastError();
+}
+}  // namespace
+
+hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int groups,
+                        const MfmaLaunch& a, hipStream_t s) {
+  dim3 grid(tiles, groups);
+  return g.precision == EM_BF16_SPLIT
+             ? launch2<3>(dir, variant, grid, false, a, nullptr, nullptr, 0, s)
+             : launch2<1>(dir, variant, grid, false, a, nullptr, nullptr, 0, s);
+}
+
+hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
+                                const int4* items, int n_items, int grid, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  MfmaLaunch dummy{};
+  return precision == EM_BF16_SPLIT
+             ? launch2<3>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s)
+             : launch2<1>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
+}
+
+}  // namespace em

@@ -288,7 +288,10 @@ int build_round(em_server* S) {
   hipError_t e = hipSuccess;
   for (auto& f : S->fams) {
     const int n = (int)f.fitems.size();
-    if (f.kind == 1) {
+    if (f.kind == 1 && f.sr == 2) {
+      e = launch_mfma2_batched(f.precision, 0, f.fvar, static_cast<const MfmaLaunch*>(f.d_fdesc),
+                               f.d_fitems, n, std::min(n, 512), S->stream);
+    } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 0, f.fvar,
                               static_cast<const MfmaLaunch*>(f.d_fdesc), f.d_fitems, n,
                               std::min(n, 512), S->stream);
@@ -301,7 +304,10 @@ int build_round(em_server* S) {
   for (auto& f : S->fams) {
     if (e != hipSuccess) break;
     const int n = (int)f.aitems.size();
-    if (f.kind == 1) {
+    if (f.kind == 1 && f.sr == 2) {
+      e = launch_mfma2_batched(f.precision, 1, f.avar, static_cast<const MfmaLaunch*>(f.d_adesc),
+                               f.d_aitems, n, std::min(n, 1024), S->stream);
+    } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 1, f.avar,
                               static_cast<const MfmaLaunch*>(f.d_adesc), f.d_aitems, n,
                               std::min(n, 512), S->stream);
@@ -570,8 +576,6 @@ int em_submit(em_server* S, const em_problem* p, const float* y_host, const floa
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
   if (g.precision == EM_FP16_SPLIT) return fail(EM_ENOTSUP, "precision not provided");
-  if (uses_mfma(g) && g.sr != 1)
-    return fail(EM_ENOTSUP, "matrix-core precisions are provided for sr = 1 only");
   if (g.weight_mode != EM_W_ADJOINT) return fail(EM_ENOTSUP, "weight mode not provided");
   size_t total, a, b, c2, d, e, wsb;
   job_layout(g, &total, &a, &b, &c2, &d, &e, &wsb);

@@ -102,20 +102,76 @@ def test_c3_recipe_split_multi_tile():
     assert err <= SPLIT_X_TOL and (xg >= 0).all()
 
 
-def test_split_deterministic_and_sr2_unsupported():
-    import torch
+def test_split_deterministic():
     em = _em()
     p = synth.make_problem("c2", H=140, W=150, n=3)
     x0 = synth.positive_start(p.latent_shape, 20.0, seed=6)
     a, ta = gpu_run(p.y, p.v, p.psf, 1, 4, x0=x0, precision=em.BF16_SPLIT)
     b, tb = gpu_run(p.y, p.v, p.psf, 1, 4, x0=x0, precision=em.BF16_SPLIT)
     assert np.array_equal(a, b) and np.array_equal(ta, tb)
-    q = synth.make_problem("c4", H=64, W=64, n=1)
-    prob = em.Problem.make(1, 32, 32, 43, sr=2, precision=em.BF16_SPLIT)
-    x = torch.empty((64, 64), dtype=torch.float32, device="cuda")
-    with pytest.raises(em.EMError) as ei:
-        em.Context(prob, to_dev(q.y), to_dev(q.v), to_dev(q.psf), x)
-    assert ei.value.code == em.ENOTSUP
+
+
+# ---------------------------------------------------------------------------
+# super-resolution (sr = 2, Eq. (3)) on the matrix cores
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("K,hf,wf,n", [(43, 75, 66, 2), (43, 64, 64, 1), (15, 40, 70, 3),
+                                       (43, 17, 130, 1), (43, 3, 2, 1), (43, 130, 97, 2)])
+def test_split_sr2_operators_elementwise_bound(K, hf, wf, n):
+    em = _em()
+    log(f"mfma sr=2 operators K={K} frame {hf}x{wf} n={n}")
+    rng = np.random.default_rng(K * 11 + hf)
+    psf = rng.uniform(0, 1, (n, K, K)).astype(np.float32)
+    psf /= psf.sum(axis=(1, 2), keepdims=True)
+    x = rng.gamma(0.5, 200.0, (2 * hf, 2 * wf)).astype(np.float32)
+    r = rng.normal(0, 1, (n, hf, wf)).astype(np.float32)
+    p = em.Problem.make(n, hf, wf, K, sr=2, precision=em.BF16_SPLIT)
+    m = em.forward_op(p, to_dev(psf), to_dev(x)).cpu().numpy()
+    s = em.adjoint_op(p, to_dev(psf), to_dev(r)).cpu().numpy()
+    for t in range(n):
+        mo = oracle.forward(psf[t], x, 2)
+        so = oracle.adjoint(psf[t], r[t], 2)
+        mb = oracle.forward(np.abs(psf[t]), np.abs(x), 2)
+        sb = oracle.adjoint(np.abs(psf[t]), np.abs(r[t]), 2)
+        assert (np.abs(m[t] - mo) <= OP_EPS * mb + 1e-30).all()
+        assert (np.abs(s[t] - so) <= OP_EPS * sb + 1e-30).all()
+        log(f"  t={t}: rel L2 fwd {rel_l2(m[t], mo):.2e} adj {rel_l2(s[t], so):.2e}")
+
+
+def test_c4_recipe_split_sr2_runs():
+    em = _em()
+    p = synth.make_problem("c4", H=192, W=134, n=3)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v, 2), 0.25), seed=9)
+    err, llerr, xg, trg = _run_both(p, 10, x0, em.BF16_SPLIT)
+    log(f"c4-sr2 bf16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= SPLIT_X_TOL and (xg >= 0).all()
+    assert (np.diff(trg) >= -1e-7 * np.abs(trg[1:])).all()
+    p2 = synth.make_problem("c4", H=300, W=260, n=2, seed=4401)
+    x02 = synth.positive_start(p2.latent_shape, max(oracle.flat_x0(p2.y, p2.v, 2), 0.25), seed=10)
+    err2, _, xg2, _ = _run_both(p2, 5, x02, em.BF16_SPLIT)
+    log(f"c4-sr2 multi-tile bf16-split: rel L2(x) {err2:.3e}")
+    assert err2 <= SPLIT_X_TOL
+
+
+def test_sr2_every_variant_matches_oracle():
+    import torch
+    em = _em()
+    p = synth.make_problem("c4", H=260, W=200, n=2, seed=4402)
+    x0 = synth.positive_start(p.latent_shape, 2.0, seed=13)
+    xo = oracle.run(p.y, p.v, p.psf, x0, 3, sr=2)
+    prob = em.Problem.make(2, 130, 100, 43, sr=2, precision=em.BF16_SPLIT)
+    nv = em._lib.em_variant_count()
+    for fv in range(nv):
+        for av in range(nv):
+            x = torch.empty((260, 200), dtype=torch.float32, device="cuda")
+            ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+            ctx.set_variants(fv, av)
+            ctx.iterate(3)
+            ctx.sync()
+            err = rel_l2(x.cpu().numpy(), xo)
+            ctx.close()
+            log(f"sr2 variant fwd={fv} adj={av}: rel L2 {err:.2e}")
+            assert err <= SPLIT_X_TOL
 
 
 def test_every_variant_and_autotune_match_oracle():

@@ -26,7 +26,7 @@ def _jobs():
     specs = [  # (recipe, latent H, W, n, sr, precision, iterations)
         ("c2", 96, 96, 3, 1, em.BF16_SPLIT, 7),
         ("c3", 160, 128, 5, 1, em.FP32, 5),
-        ("c4", 128, 96, 2, 2, em.FP32, 6),
+        ("c4", 128, 96, 2, 2, em.BF16_SPLIT, 6),
         ("c2", 200, 136, 2, 1, em.BF16_SPLIT, 9),
         ("c1", 64, 64, 4, 1, em.FP32, 12),
         ("c4", 64, 192, 3, 2, em.FP32, 4),
