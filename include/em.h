@@ -189,6 +189,14 @@ int em_set_variants(em_ctx* ctx, int32_t fwd_variant, int32_t adj_variant);
 int em_autotune(em_ctx* ctx, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_variant,
                 double* ms);
 
+/*
+ * Host-only self-check (no GPU needed): builds every launch descriptor the
+ * library would use for problem p (iteration, autotuning, stand-alone operators,
+ * serving plan; every kernel variant) and checks each against the grid it is
+ * launched on and the workspace sizes.  EM_OK, or EM_EINVAL with the reason.
+ */
+int em_check_plan(const em_problem* p);
+
 /* Wait for the job's stream; reports asynchronous device errors. */
 int em_sync(em_ctx* ctx);
 

@@ -679,6 +679,58 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
   return EM_OK;
 }
 
+int em_check_plan(const em_problem* p) {
+  Geometry g;
+  const char* why = nullptr;
+  if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
+  for (int serving = 0; serving < 2; ++serving) {
+    const Plan pl = serving ? make_serving_plan(g) : make_plan(g);
+    em_ctx c{};
+    c.g = g;
+    c.pl = pl;
+    c.lay = make_layout(g, pl);
+    c.ws = reinterpret_cast<char*>(static_cast<uintptr_t>(1) << 20);   // never dereferenced
+    em_bind_views(&c);
+    const char* what = serving ? "serving plan" : "plan";
+    for (int v = 0; v < (uses_mfma(g) ? mfma_variants() : 1); ++v) {
+      c.pl.fwd_variant = c.pl.adj_variant = v;
+      if (uses_mfma(g)) {
+        MfmaLaunch m;
+        fill_forward_mfma(&c, &m, true, true);
+        if (!mfma_desc_ok(g, 0, pl.fwd_tiles, pl.fwd_groups, m))
+          return fail(EM_EINVAL, "%s: forward descriptor does not match its grid", what);
+        fill_adjoint_mfma(&c, &m, nullptr);
+        if (!mfma_desc_ok(g, 1, pl.adj_tiles, pl.adj_groups, m))
+          return fail(EM_EINVAL, "%s: adjoint descriptor does not match its grid", what);
+        m.fpg = 1;   // stand-alone operator: one frame per group
+        if (!mfma_desc_ok(g, 1, pl.adj_tiles, g.n, m))
+          return fail(EM_EINVAL, "%s: per-frame adjoint descriptor does not match", what);
+      } else {
+        FwdLaunch f;
+        fill_forward_fp32(&c, &f, true, true);
+        if (!forward_desc_ok(g, pl.fwd_tiles, pl.fwd_groups, f))
+          return fail(EM_EINVAL, "%s: forward descriptor does not match its grid", what);
+        AdjLaunch a;
+        fill_adjoint_fp32(&c, &a, nullptr);
+        if (!adjoint_desc_ok(g, pl.adj_tiles, pl.adj_groups, a))
+          return fail(EM_EINVAL, "%s: adjoint descriptor does not match its grid", what);
+        a.fpg = 1;
+        if (!adjoint_desc_ok(g, pl.adj_tiles, g.n, a))
+          return fail(EM_EINVAL, "%s: per-frame adjoint descriptor does not match", what);
+      }
+    }
+    // workspace capacities for what the kernels write
+    const Layout& L = c.lay;
+    const size_t ll = (size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double);
+    const size_t rcb = (size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double);
+    if (L.part_rc - L.part_ll < ll || L.part_prep - L.part_rc < rcb)
+      return fail(EM_EINVAL, "%s: partial-sum buffers too small", what);
+    if (pl.adj_groups > 1 && L.tab - L.planes < (size_t)pl.adj_groups * g.Nl * sizeof(float))
+      return fail(EM_EINVAL, "%s: partial planes too small", what);
+  }
+  return EM_OK;
+}
+
 int em_variant_count(void) { return mfma_variants(); }
 
 int em_set_variants(em_ctx* c, int32_t fwd_variant, int32_t adj_variant) {
@@ -706,33 +758,21 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
   int rc = EM_OK;
   for (int dir = 0; dir < 2 && rc == EM_OK; ++dir) {
     for (int v = 0; v < nv && rc == EM_OK; ++v) {
-      MfmaLaunch m{};
-      m.n = c->g.n;
-      m.H = c->g.Hl;
-      m.W = c->g.Wl;
+      // descriptors of the iteration itself (grid sizes of the right grids)
+      MfmaLaunch m;
       int tiles, groups;
       if (dir == 0) {
         // the forward writes r, which every iteration recomputes before use
-        m.in = c->x;
-        m.tab = c->mtab_fwd;
-        m.u = c->u;
-        m.out = c->r;
-        m.fpg = c->pl.fwd_fpg;
-    m.ntiles = c->pl.fwd_tiles;
+        fill_forward_mfma(c, &m, true, false);
         tiles = c->pl.fwd_tiles;
         groups = c->pl.fwd_groups;
-        m.ntiles = tiles;
       } else {
         // the adjoint writes partial planes (never the iterate)
-        m.in = c->r;
-        m.tab = c->mtab_adj;
+        fill_adjoint_mfma(c, &m, nullptr);
         m.fused = 0;
         m.plane = c->pl.adj_groups > 1 ? c->planes : c->tune;
-        m.fpg = c->pl.adj_fpg;
-    m.ntiles = c->pl.adj_tiles;
         tiles = c->pl.adj_tiles;
         groups = c->pl.adj_groups;
-        m.ntiles = tiles;
       }
       for (int k = 0; k <= n_rep && rc == EM_OK; ++k) {
         if (k == 1) EM_HIP(hipEventRecord(e0, c->stream));

@@ -482,7 +482,20 @@ int fwd_tile_w(const Geometry&) { return 64; }
 int adj_tile_h(const Geometry& g) { return g.sr == 1 ? A1_R * A1_WV : A2_R * A2_WV; }
 int adj_tile_w(const Geometry& g) { return g.sr == 1 ? 64 : 128; }
 
+bool forward_desc_ok(const Geometry& g, int tiles, int groups, const FwdLaunch& a) {
+  return a.Hl == g.sr * a.Hf && a.Wl == g.sr * a.Wf &&
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.Hf, a.Wf, fwd_tile_h(g),
+                        fwd_tile_w(g));
+}
+
+bool adjoint_desc_ok(const Geometry& g, int tiles, int groups, const AdjLaunch& a) {
+  return a.Hl == g.sr * a.Hf && a.Wl == g.sr * a.Wf &&
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.Hl, a.Wl, adj_tile_h(g),
+                        adj_tile_w(g));
+}
+
 hipError_t launch_forward(const Geometry& g, const Plan& pl, const FwdLaunch& a, hipStream_t s) {
+  if (!forward_desc_ok(g, pl.fwd_tiles, pl.fwd_groups, a)) return hipErrorInvalidValue;
   dim3 grid(pl.fwd_tiles, pl.fwd_groups);
   if (g.sr == 1) {
     dim3 block(64 * F1_WV);
@@ -501,6 +514,7 @@ hipError_t launch_forward(const Geometry& g, const Plan& pl, const FwdLaunch& a,
 }
 
 hipError_t launch_adjoint(const Geometry& g, const Plan& pl, const AdjLaunch& a, hipStream_t s) {
+  if (!adjoint_desc_ok(g, pl.adj_tiles, pl.adj_groups, a)) return hipErrorInvalidValue;
   dim3 grid(pl.adj_tiles, pl.adj_groups);
   if (g.sr == 1) {
     dim3 block(64 * A1_WV);

@@ -148,6 +148,23 @@ int mfma_tile_h();
 int mfma_tile_w();
 size_t mfma_table_bytes(const Geometry& g, int dir);
 
+// Host-side check that a launch grid matches its descriptor: `tiles` tiles of
+// tile_h x tile_w cover an h x w grid exactly, and `groups` frame groups of fpg
+// frames cover n frames exactly.  Launchers refuse anything else, so a
+// descriptor built for the wrong grid is an error, never an out-of-range access.
+inline bool launch_grid_ok(int tiles, int groups, int ntiles, int n, int fpg, int h, int w,
+                           int tile_h, int tile_w) {
+  if (h < 1 || w < 1 || n < 1 || fpg < 1 || groups < 1 || tiles < 1) return false;
+  const int64_t expect = (int64_t)((w + tile_w - 1) / tile_w) * ((h + tile_h - 1) / tile_h);
+  return tiles == expect && ntiles == tiles && (int64_t)groups * fpg >= n &&
+         (int64_t)(groups - 1) * fpg < n;
+}
+
+bool forward_desc_ok(const Geometry& g, int tiles, int groups, const FwdLaunch& a);
+bool adjoint_desc_ok(const Geometry& g, int tiles, int groups, const AdjLaunch& a);
+bool mfma_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a);
+bool mfma2_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a);
+
 hipError_t launch_forward(const Geometry& g, const Plan& pl, const FwdLaunch& a, hipStream_t s);
 hipError_t launch_adjoint(const Geometry& g, const Plan& pl, const AdjLaunch& a, hipStream_t s);
 

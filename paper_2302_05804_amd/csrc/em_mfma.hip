@@ -475,9 +475,16 @@ hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, cons
                : launch_dir_batched<KT_SMALL, 1>(dir, variant, grid, descs, items, n_items, s);
 }
 
+bool mfma_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
+  if (g.sr == 2) return mfma2_desc_ok(g, dir, tiles, groups, a);
+  return a.H == g.Hl && a.W == g.Wl &&
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, MF_TILE, MF_TILE);
+}
+
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s) {
   if (g.sr == 2) return launch_mfma2(g, dir, variant, tiles, groups, a, s);
+  if (!mfma_desc_ok(g, dir, tiles, groups, a)) return hipErrorInvalidValue;
   dim3 grid(tiles, groups);
   const bool split = g.precision == EM_BF16_SPLIT;
   if (g.KT == KT_LARGE)

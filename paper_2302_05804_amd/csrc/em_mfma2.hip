@@ -520,8 +520,18 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
 }
 }  // namespace
 
+// forward descriptors carry the frame grid, adjoint descriptors the latent grid
+bool mfma2_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
+  return dir == 0
+      ? (a.H == g.Hf && a.W == g.Wf &&
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2_FTILE, M2_FTILE))
+      : (a.H == g.Hl && a.W == g.Wl && a.H % 2 == 0 && a.W % 2 == 0 &&
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2_ATILE, M2_ATILE));
+}
+
 hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int groups,
                         const MfmaLaunch& a, hipStream_t s) {
+  if (!mfma2_desc_ok(g, dir, tiles, groups, a)) return hipErrorInvalidValue;
   dim3 grid(tiles, groups);
   return g.precision == EM_BF16_SPLIT
              ? launch2<3>(dir, variant, grid, false, a, nullptr, nullptr, 0, s)

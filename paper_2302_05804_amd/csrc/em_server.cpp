@@ -241,21 +241,30 @@ int build_round(em_server* S) {
   for (Job* j : order) {
     Family& f = family_of(j->ctx);
     const em_ctx* c = j->ctx;
+    // every descriptor is checked against its grid on the host before upload
     if (f.kind == 1) {
       MfmaLaunch m;
       fill_forward_mfma(c, &m, true, false);
+      if (!mfma_desc_ok(c->g, 0, c->pl.fwd_tiles, c->pl.fwd_groups, m))
+        return fail(EM_EDEVICE, "inconsistent forward descriptor");
       add_items(f.fitems, (int)f.fwdmf.size(), c->pl.fwd_tiles, c->pl.fwd_groups);
       f.fwdmf.push_back(m);
       fill_adjoint_mfma(c, &m, nullptr);
+      if (!mfma_desc_ok(c->g, 1, c->pl.adj_tiles, 1, m))
+        return fail(EM_EDEVICE, "inconsistent adjoint descriptor");
       add_items(f.aitems, (int)f.adjmf.size(), c->pl.adj_tiles, 1);
       f.adjmf.push_back(m);
     } else {
       FwdLaunch fl;
       fill_forward_fp32(c, &fl, true, false);
+      if (!forward_desc_ok(c->g, c->pl.fwd_tiles, c->pl.fwd_groups, fl))
+        return fail(EM_EDEVICE, "inconsistent forward descriptor");
       add_items(f.fitems, (int)f.fwd32.size(), c->pl.fwd_tiles, c->pl.fwd_groups);
       f.fwd32.push_back(fl);
       AdjLaunch al;
       fill_adjoint_fp32(c, &al, nullptr);
+      if (!adjoint_desc_ok(c->g, c->pl.adj_tiles, 1, al))
+        return fail(EM_EDEVICE, "inconsistent adjoint descriptor");
       add_items(f.aitems, (int)f.adj32.size(), c->pl.adj_tiles, 1);
       f.adj32.push_back(al);
     }

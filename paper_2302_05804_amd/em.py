@@ -85,6 +85,7 @@ _sig = {
                                     ctypes.POINTER(ctypes.c_double)]),
     "em_server_stats": (ctypes.c_int, [_P, _P]),
     "em_variant_count": (ctypes.c_int, []),
+    "em_check_plan": (ctypes.c_int, [ctypes.POINTER(Problem)]),
     "em_set_variants": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
     "em_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), _P]),
@@ -105,6 +106,11 @@ def exported_symbols():
 
 def version() -> str:
     return _lib.em_version().decode()
+
+
+def check_plan(p: Problem) -> None:
+    """Host-only: every launch descriptor for p matches its grid (raises otherwise)."""
+    _check(_lib.em_check_plan(ctypes.byref(p)), "em_check_plan")
 
 
 def workspace_bytes(p: Problem) -> int:

@@ -208,3 +208,27 @@ def test_every_variant_and_autotune_match_oracle():
     ctx.sync()
     assert rel_l2(x.cpu().numpy(), xo) <= SPLIT_X_TOL
     ctx.close()
+
+
+def test_sr2_autotune_then_iterate_matches_oracle():
+    """Autotuning an sr = 2 job times its forward kernel on the frame grid and
+    its adjoint on the latent grid; the iterate is untouched and the tuned
+    iteration still matches the oracle."""
+    import torch
+    em = _em()
+    p = synth.make_problem("c4", H=256, W=192, n=3, seed=4403)
+    x0 = synth.positive_start(p.latent_shape, 2.0, seed=14)
+    xo = oracle.run(p.y, p.v, p.psf, x0, 3, sr=2)
+    prob = em.Problem.make(3, 128, 96, 43, sr=2, precision=em.BF16_SPLIT)
+    x = torch.empty((256, 192), dtype=torch.float32, device="cuda")
+    ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+    before = x.clone()
+    f, a, ms = ctx.autotune(2)
+    torch.cuda.synchronize()
+    assert torch.equal(before, x) and (ms > 0).all()
+    ctx.iterate(3)
+    ctx.sync()
+    err = rel_l2(x.cpu().numpy(), xo)
+    log(f"sr2 autotuned (fwd {f}, adj {a}): rel L2 {err:.2e}")
+    assert err <= SPLIT_X_TOL
+    ctx.close()
