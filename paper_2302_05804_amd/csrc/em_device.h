@@ -14,6 +14,15 @@ __host__ __device__ constexpr int lds_pitch(int need) {
   return (((need + 3) / 4) % 2 == 1) ? ((need + 3) / 4) * 4 : ((need + 3) / 4) * 4 + 4;
 }
 
+// Column owned by a lane in the FP32 kernels.  A ds_read_b128 serves lanes
+// {0-7, 16-23} (and {8-15, 24-31}, ...) together; mapping each such group to 16
+// consecutive columns makes their 16-byte reads of a transposed tile (one
+// column per LDS row, odd pitch/4) fall on distinct banks.  A bijection of
+// 0..63.
+__device__ inline int lane_column(int lane) {
+  return (lane & 7) | ((lane >> 4) << 3) | (((lane >> 3) & 1) << 5);
+}
+
 // Read-only view of a global buffer through the constant address space: loads
 // with wave-uniform addresses are then selected as scalar (s_load) loads, so
 // convolution taps arrive in SGPRs.  Only for data no kernel of the same launch

@@ -40,7 +40,7 @@ __device__ inline void fwd1_body(const FwdLaunch& a, const int tile, const int g
   __shared__ __align__(16) float xs[LW * P];
   __shared__ double red[WV];
 
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = lane_column(threadIdx.x & 63), w = threadIdx.x >> 6;
   const int tiles_x = (a.Wf + TW - 1) / TW;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int j0 = tx * TW, i0 = ty * TH;
@@ -133,7 +133,7 @@ __device__ inline void fwd2_body(const FwdLaunch& a, const int tile, const int g
   __shared__ __align__(16) float xs[2 * LWP * P];
   __shared__ double red[WV];
 
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = lane_column(threadIdx.x & 63), w = threadIdx.x >> 6;
   const int tiles_x = (a.Wf + TW - 1) / TW;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int J0 = tx * TW, I0 = ty * TH;
@@ -236,7 +236,7 @@ __device__ inline void adj1_body(const AdjLaunch& a, const int tile, const int g
   __shared__ __align__(16) float rs[LW * P];
   __shared__ double red[2 * WV];
 
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int lane = lane_column(threadIdx.x & 63), w = threadIdx.x >> 6;
   const int tiles_x = (a.Wl + TW - 1) / TW;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int l0 = tx * TW, k0 = ty * TH;
@@ -346,7 +346,7 @@ __device__ inline void adj2_body(const AdjLaunch& a, const int tile, const int g
   __shared__ __align__(16) float rs[LW * P];
   __shared__ double red[2 * NT / 64];
 
-  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int lane = lane_column(threadIdx.x & 63), wid = threadIdx.x >> 6;
   const int ph = wid & 1, w = wid >> 1;
   const int tiles_x = (a.Wl + TWL - 1) / TWL;
   const int tx = tile % tiles_x, ty = tile / tiles_x;

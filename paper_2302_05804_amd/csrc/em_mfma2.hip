@@ -70,7 +70,7 @@ struct M2F {
   static constexpr int TH = 16 * BR * WR, TW = 16 * BC * WC;      // frame pixels
   static constexpr int ROWS = 2 * TH + M2_KC - 2;                   // latent rows staged
   static constexpr int COLS = 2 * TW + 64;                          // latent cols staged
-  static constexpr int PITCH = mf_pitch(COLS);
+  static constexpr int PITCH = mf_pitch(COLS, 2);   // fragment rows are 2 apart
 };
 
 template <class C>

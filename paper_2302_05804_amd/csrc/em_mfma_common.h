@@ -8,10 +8,17 @@ namespace em {
 typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
 typedef __attribute__((ext_vector_type(4))) float f32x4;
 
-// Row pitch (bf16 elements) of an LDS plane holding `cols` columns: rows stay
-// 16-byte aligned and the pitch is an odd number of 16-byte chunks.
-__host__ __device__ constexpr int mf_pitch(int cols) {
-  return (((cols + 7) / 8) % 2 == 1) ? ((cols + 7) / 8) * 8 : ((cols + 7) / 8) * 8 + 8;
+// Row pitch (bf16 elements) of an LDS plane holding `cols` columns whose
+// 16-byte fragments are read by lanes i = 0..15 at rows base + row_stride * i
+// and by the next lane group one chunk to the right.  A ds_read_b128 serves
+// lanes {0-7, 16-23} (and the matching groups) together across 64 banks; the
+// sixteen 16-byte pieces are conflict-free when row_stride * pitch, counted in
+// 16-byte chunks, is 2 mod 4 (measured on gfx950: 22 chunks conflict-free, 21,
+// 23 and 25 chunks four extra cycles per read, 24 chunks twelve).
+__host__ __device__ constexpr int mf_pitch(int cols, int row_stride = 1) {
+  int chunks = (cols + 7) / 8;
+  while ((row_stride * chunks) % 4 != 2) ++chunks;
+  return chunks * 8;
 }
 
 __device__ inline unsigned short bf16_bits(__bf16 v) { return __builtin_bit_cast(unsigned short, v); }
