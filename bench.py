@@ -43,7 +43,13 @@ WORKLOADS = {
           "4-33 frames, sr 1 or 2, 43x43 Moffat PSFs, 50-200 iterations per job",
 }
 DTYPES = {"fp32": "f32", "bf16split": "bf16x3 (hi+lo split), f32 accumulate",
+          "fp16split": "f16 image (2^k tile scale) x f16 hi+lo PSF, f32 accumulate",
           "bf16": "bf16, f32 accumulate"}
+
+
+def prec_code(em, name):
+    return {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "fp16split": em.FP16_SPLIT,
+            "bf16": em.BF16}[name]
 
 
 def log(msg: str) -> None:
@@ -110,8 +116,7 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream):
     import torch
     y, v, f = tensors
     n, hf, wf = prob.y.shape
-    prec = {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "bf16": em.BF16}[prec_name]
-    p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec)
+    p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec_code(em, prec_name))
     x = torch.empty(p.latent_shape, dtype=torch.float32, device=y.device)
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
@@ -181,8 +186,7 @@ def sampled_check(em, prob, tensors, prec_names, npts=6, seed=77):
     out = {}
     x0d = torch.from_numpy(x0).to(y.device)
     for prec_name in prec_names:
-        prec = {"fp32": em.FP32, "bf16split": em.BF16_SPLIT, "bf16": em.BF16}[prec_name]
-        p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec)
+        p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec_code(em, prec_name))
         x = torch.empty((hl, wl), dtype=torch.float32, device=y.device)
         ctx = em.Context(p, y, v, f, x, x0=x0d)
         ctx.iterate(1)
@@ -316,7 +320,8 @@ def main() -> int:
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="c3", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="auto", choices=["auto", "fp32", "bf16split", "bf16"])
+    ap.add_argument("--precision", default="auto",
+                    choices=["auto", "fp32", "bf16split", "fp16split", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-check", action="store_true", help="skip the sampled oracle check")
     ap.add_argument("--cpu-crop", type=int, default=128)
@@ -372,7 +377,7 @@ def main() -> int:
     stream = torch.cuda.Stream(dev)
 
     if args.precision == "auto":
-        forms = ["bf16split", "fp32"]
+        forms = ["bf16split", "fp16split", "fp32"]
     else:
         forms = [args.precision]
     res = {}

@@ -68,8 +68,13 @@ extern "C" {
 /* arithmetic of the two convolutions (the update is always FP32, the
  * log-likelihood and convergence sums always FP64) */
 #define EM_FP32        0    /* FP32 products, FP32 accumulation               */
-#define EM_BF16_SPLIT  1    /* BF16 MFMA, hi+lo split operands, FP32 accum.   */
-#define EM_FP16_SPLIT  2    /* reserved                                       */
+#define EM_BF16_SPLIT  1    /* BF16 MFMA, image and PSF split into hi+lo,
+                               three products, FP32 accumulation             */
+#define EM_FP16_SPLIT  2    /* FP16 MFMA: image in binary16 with a power-of-two
+                               scale per staged tile, PSF split into binary16
+                               hi+lo with a power-of-two scale per frame, two
+                               products, FP32 accumulation, scales removed
+                               exactly in the epilogue                       */
 #define EM_BF16        3    /* plain BF16 MFMA (ablation; below 1e-3 accuracy) */
 
 /* placement of the inverse-variance weights */
@@ -86,7 +91,7 @@ typedef struct {
     int32_t frame_w;      /* exposure columns >= 1                           */
     int32_t psf_k;        /* odd, 1 <= K <= 43                               */
     int32_t sr;           /* super-resolution factor: 1 or 2 (Eq. (3))       */
-    int32_t precision;    /* EM_FP32 or EM_BF16_SPLIT                        */
+    int32_t precision;    /* EM_FP32, EM_BF16_SPLIT, EM_FP16_SPLIT, EM_BF16   */
     int32_t weight_mode;  /* EM_W_ADJOINT (EM_W_LITERAL: sr = 1 only)        */
 } em_problem;
 

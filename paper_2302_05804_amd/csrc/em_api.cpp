@@ -484,8 +484,6 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
-  if (g.precision == EM_FP16_SPLIT)
-    return fail(EM_ENOTSUP, "precision %d not provided", g.precision);
   if (g.weight_mode != EM_W_ADJOINT)
     return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
   const Plan pl = serving ? make_serving_plan(g) : make_plan(g);

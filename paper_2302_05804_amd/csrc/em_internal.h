@@ -76,7 +76,7 @@ struct Layout {
 
 // true when the convolutions of geometry g run on the matrix cores
 inline bool uses_mfma(const Geometry& g) {
-  return g.precision == EM_BF16_SPLIT || g.precision == EM_BF16;
+  return g.precision == EM_BF16_SPLIT || g.precision == EM_FP16_SPLIT || g.precision == EM_BF16;
 }
 
 bool make_geometry(const void* problem, Geometry* g, const char** why);

@@ -1,5 +1,5 @@
-// em_mfma.hip -- BF16 matrix-core (MFMA) form of the two convolutions of one
-// EM iteration (arXiv:2302.05804, Sec. 2, Eqs. (1)-(2)), sr = 1.
+// em_mfma.hip -- matrix-core (MFMA) forms of the two convolutions of one EM
+// iteration (arXiv:2302.05804, Sec. 2, Eqs. (1)-(2)), sr = 1.
 //
 // Both directions are the same 2-D correlation core
 //     out[k][l] = sum_{a,b} g[a][b] in[k - c + a][l - c + b]
@@ -12,21 +12,23 @@
 // v_mfma_f32_16x16x32_bf16 steps (p in [0,32) and [32,64)); 43 of the 64
 // p-values of a column of U_a are non-zero.
 //
-// Precision: operands are split into bf16 hi + lo parts (v = hi + lo, with
-// lo = bf16(v - hi)) and each product is formed as hi.hi + lo.hi + hi.lo with
-// FP32 accumulation in the matrix core (the lo.lo term, ~2^-16 relative, is
-// dropped).  NS = 1 keeps only hi.hi (plain bf16, for comparison).
+// Precision (template argument PREC, encodings in em_mfma_common.h): bf16 hi +
+// lo split of both operands with three products (EM_BF16_SPLIT), plain bf16
+// (EM_BF16), or a binary16 image operand with a per-tile power-of-two scale
+// times a binary16 hi + lo PSF with a per-frame scale, two products
+// (EM_FP16_SPLIT).  Accumulation is FP32 in the matrix core throughout.
 //
 // Data movement (per workgroup of 4 waves, 128 x 128 outputs, each wave 64 x 64
 // = 4 x 4 blocks of 16 x 16):
-//  * the input tile (128 + K - 1 rows, 176 columns) is stored in LDS as two
-//    bf16 planes (hi, lo), row-major, row pitch 368 bytes (an odd multiple of 16
-//    bytes, so 16-byte fragment reads of consecutive rows spread over banks);
+//  * the input tile (128 + K - 1 rows, 176 columns) is stored in LDS as one
+//    16-bit plane per image part (hi, lo for the bf16 split), row-major, with
+//    the bank-conflict-free pitch of mf_pitch;
 //  * taps are grouped in classes a = r + 16 m: the A fragment of rows
 //    r + 16 rho + i then serves block rows beta = rho - m for every m of the
 //    class, so one LDS read feeds up to 3 row blocks (and 2 column blocks);
 //  * the Toeplitz fragments U_a (hi, lo) are pre-built per frame in the lane
-//    order of the MFMA B operand and read from global memory (L2-resident).
+//    order of the MFMA B operand and read from global memory (L2-resident);
+//    scaled encodings keep the frame's scale exponents after the fragments.
 #include "em_device.h"
 #include "em_internal.h"
 #include "em_mfma_common.h"
@@ -37,9 +39,12 @@ constexpr int MF_TILE = 128;   // every sr = 1 variant covers 128 x 128 outputs
 
 // Tile configuration: each wave owns BR x BC blocks of 16 x 16 outputs, the
 // workgroup WR x WC waves.
-template <int KT_, int NS_, int BR_, int BC_, int WR_, int WC_, int PFA_, int PFT_>
+template <int KT_, int PREC_, int BR_, int BC_, int WR_, int WC_, int PFA_, int PFT_>
 struct MfCfg {
-  static constexpr int KT = KT_, NS = NS_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  using P = Prec<PREC_>;
+  using frag = typename P::frag;
+  static constexpr int KT = KT_, PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int NS = P::NP, NA = P::NA, NB = P::NB;
   // PFA: load the A fragments of the next fragment row before the products of
   // the current one; PFT: fetch the next tap class's Toeplitz fragments early.
   static constexpr int PFA = PFA_, PFT = PFT_;
@@ -52,54 +57,32 @@ struct MfCfg {
   static constexpr int KTP = 16 * MMAX;         // table rows (zero beyond KT)
 };
 
-// Stage an input tile (FP32 image, rows [r0, r0 + ROWS), cols [q0, q0 + COLS),
-// zero outside [0,H) x [0,W)) into the hi / lo LDS planes.
-template <class C>
-__device__ inline void stage_tile(const float* __restrict__ src, int H, int W, int r0, int q0,
-                                  unsigned short* sh_hi, unsigned short* sh_lo) {
-  constexpr int HALF = C::COLS / 2;
-  for (int e = threadIdx.x; e < C::ROWS * HALF; e += C::NT) {
-    const int row = e / HALF, cp = e - row * HALF;
-    const int gy = r0 + row, gx = q0 + 2 * cp;
-    float v0 = 0.f, v1 = 0.f;
-    if (gy >= 0 && gy < H) {
-      const float* rp = src + (int64_t)gy * W;
-      if (gx >= 0 && gx < W) v0 = rp[gx];
-      if (gx + 1 >= 0 && gx + 1 < W) v1 = rp[gx + 1];
-    }
-    unsigned short h0, l0, h1, l1;
-    split_bf16(v0, h0, l0);
-    split_bf16(v1, h1, l1);
-    const int o = row * C::PITCH + 2 * cp;
-    *reinterpret_cast<unsigned int*>(sh_hi + o) = (unsigned int)h0 | ((unsigned int)h1 << 16);
-    *reinterpret_cast<unsigned int*>(sh_lo + o) = (unsigned int)l0 | ((unsigned int)l1 << 16);
-  }
-}
-
 // Toeplitz fragments of tap class r (rows a = r + 16 m, m < MMAX), both k-halves,
 // hi and (split) lo parts.
 template <class C>
-__device__ inline void load_T(bf16x8 (&T)[C::MMAX][2][2], const bf16x8* __restrict__ tab_t, int r) {
+__device__ inline void load_T(typename C::frag (&T)[C::MMAX][2][C::NB],
+                              const typename C::frag* __restrict__ tab_t, int r) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int m = 0; m < C::MMAX; ++m)
 #pragma unroll
     for (int h = 0; h < 2; ++h)
 #pragma unroll
-      for (int s = 0; s < (C::NS == 3 ? 2 : 1); ++s)
+      for (int s = 0; s < C::NB; ++s)
         T[m][h][s] = tab_t[(((r + 16 * m) * 2 + h) * 2 + s) * 64 + lane];
 }
 
-// A fragments (hi, lo) of fragment row rho for every column position kappa.
+// A fragments (every image part) of fragment row rho for every column
+// position kappa.
 template <class C>
-__device__ inline void load_A(bf16x8 (&A)[C::BC + 2][2], const unsigned short* sh_hi,
-                              const unsigned short* sh_lo, int lrow, int col_base) {
+__device__ inline void load_A(typename C::frag (&A)[C::BC + 2][C::NA], const unsigned short (*sh)[C::ROWS * C::PITCH],
+                              int lrow, int col_base) {
   const int g = (threadIdx.x & 63) >> 4;
 #pragma unroll
   for (int kap = 0; kap < C::BC + 2; ++kap) {
     const int o = lrow * C::PITCH + col_base + 16 * kap + 8 * g;
-    A[kap][0] = *reinterpret_cast<const bf16x8*>(sh_hi + o);
-    if (C::NS == 3) A[kap][1] = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+#pragma unroll
+    for (int p = 0; p < C::NA; ++p) A[kap][p] = *reinterpret_cast<const typename C::frag*>(&sh[p][o]);
   }
 }
 
@@ -108,20 +91,20 @@ __device__ inline void load_A(bf16x8 (&A)[C::BC + 2][2], const unsigned short* s
 // are loaded before the products of the current one are issued, and products
 // are ordered by split term so that consecutive MFMAs write different blocks.
 template <class C, int NM>
-__device__ inline void mfma_class(int r, const unsigned short* sh_hi, const unsigned short* sh_lo,
-                                  const bf16x8 (&T)[C::MMAX][2][2], int row_base, int col_base,
-                                  f32x4 (&acc)[C::BR][C::BC]) {
+__device__ inline void mfma_class(int r, const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                  const typename C::frag (&T)[C::MMAX][2][C::NB], int row_base,
+                                  int col_base, f32x4 (&acc)[C::BR][C::BC]) {
   const int i = threadIdx.x & 15;
   constexpr int NRHO = C::BR + NM - 1;
-  bf16x8 A[C::PFA ? 2 : 1][C::BC + 2][2];
-  if (C::PFA) load_A<C>(A[0], sh_hi, sh_lo, row_base + r + i, col_base);
+  typename C::frag A[C::PFA ? 2 : 1][C::BC + 2][C::NA];
+  if (C::PFA) load_A<C>(A[0], sh, row_base + r + i, col_base);
 #pragma unroll
   for (int rho = 0; rho < NRHO; ++rho) {
     if (C::PFA) {
       if (rho + 1 < NRHO)
-        load_A<C>(A[(rho + 1) & 1], sh_hi, sh_lo, row_base + r + 16 * (rho + 1) + i, col_base);
+        load_A<C>(A[(rho + 1) & 1], sh, row_base + r + 16 * (rho + 1) + i, col_base);
     } else {
-      load_A<C>(A[0], sh_hi, sh_lo, row_base + r + 16 * rho + i, col_base);
+      load_A<C>(A[0], sh, row_base + r + 16 * rho + i, col_base);
     }
     const int cur = C::PFA ? (rho & 1) : 0;
 #pragma unroll
@@ -136,10 +119,8 @@ __device__ inline void mfma_class(int r, const unsigned short* sh_hi, const unsi
           for (int h = 0; h < 2; ++h) {
             const int gam = kap - 2 * h;
             if (gam < 0 || gam >= C::BC) continue;
-            const bf16x8& a_op = A[cur][kap][s == 1 ? 1 : 0];
-            const bf16x8& b_op = T[m][h][s == 2 ? 1 : 0];
-            acc[beta][gam] =
-                __builtin_amdgcn_mfma_f32_16x16x32_bf16(a_op, b_op, acc[beta][gam], 0, 0, 0);
+            acc[beta][gam] = C::P::mma(A[cur][kap][C::P::pa(s)], T[m][h][C::P::pb(s)],
+                                       acc[beta][gam]);
           }
         }
       }
@@ -150,68 +131,77 @@ __device__ inline void mfma_class(int r, const unsigned short* sh_hi, const unsi
 // All kernel rows of one frame; the Toeplitz fragments of the next class are
 // fetched while the current class runs.
 template <class C>
-__device__ inline void mfma_frame(const unsigned short* sh_hi, const unsigned short* sh_lo,
-                                  const bf16x8* __restrict__ tab_t, int row_base, int col_base,
-                                  f32x4 (&acc)[C::BR][C::BC]) {
+__device__ inline void mfma_frame(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                  const typename C::frag* __restrict__ tab_t, int row_base,
+                                  int col_base, f32x4 (&acc)[C::BR][C::BC]) {
   // classes with MMAX members first, then MMAX-1 (KT = 43: r <= 10 -> 3, r >= 11 -> 2;
   // KT = 15: r <= 14 -> 1)
   constexpr int RFULL = C::KT - 16 * (C::MMAX - 1);
   constexpr int RLAST = (C::MMAX == 1) ? C::KT : 16;
-  bf16x8 Tc[C::MMAX][2][2];
+  typename C::frag Tc[C::MMAX][2][C::NB];
   if (C::PFT) {
-    bf16x8 Tn[C::MMAX][2][2];
+    typename C::frag Tn[C::MMAX][2][C::NB];
     load_T<C>(Tc, tab_t, 0);
     int r = 0;
     for (; r < RFULL; ++r) {
       if (r + 1 < RLAST) load_T<C>(Tn, tab_t, r + 1);
-      mfma_class<C, C::MMAX>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+      mfma_class<C, C::MMAX>(r, sh, Tc, row_base, col_base, acc);
 #pragma unroll
       for (int m = 0; m < C::MMAX; ++m)
 #pragma unroll
         for (int h = 0; h < 2; ++h)
 #pragma unroll
-          for (int q = 0; q < 2; ++q) Tc[m][h][q] = Tn[m][h][q];
+          for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = Tn[m][h][q];
     }
     if constexpr (C::MMAX > 1) {
       for (; r < RLAST; ++r) {
         if (r + 1 < RLAST) load_T<C>(Tn, tab_t, r + 1);
-        mfma_class<C, C::MMAX - 1>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+        mfma_class<C, C::MMAX - 1>(r, sh, Tc, row_base, col_base, acc);
 #pragma unroll
         for (int m = 0; m < C::MMAX; ++m)
 #pragma unroll
           for (int h = 0; h < 2; ++h)
 #pragma unroll
-            for (int q = 0; q < 2; ++q) Tc[m][h][q] = Tn[m][h][q];
+            for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = Tn[m][h][q];
       }
     }
   } else {
     int r = 0;
     for (; r < RFULL; ++r) {
       load_T<C>(Tc, tab_t, r);
-      mfma_class<C, C::MMAX>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+      mfma_class<C, C::MMAX>(r, sh, Tc, row_base, col_base, acc);
     }
     if constexpr (C::MMAX > 1) {
       for (; r < RLAST; ++r) {
         load_T<C>(Tc, tab_t, r);
-        mfma_class<C, C::MMAX - 1>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+        mfma_class<C, C::MMAX - 1>(r, sh, Tc, row_base, col_base, acc);
       }
     }
   }
+}
+
+// Scale exponents of a frame's Toeplitz table (scaled encodings): n ints after
+// the fragments of all frames.
+template <class C>
+__device__ inline const int* table_exponents(const MfmaLaunch& a) {
+  return reinterpret_cast<const int*>(static_cast<const char*>(a.tab) +
+                                      (size_t)a.n * C::KTP * 4 * 64 * 16);
 }
 
 // Forward: r_t = u_t * (f_t * x) for the frames of this group, x tile staged once.
 template <class C>
 __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const int group) {
   constexpr int c = (C::KT - 1) / 2;
-  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
-  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[C::NW];
+  __shared__ float redf[C::NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int k0 = ty * C::TH, l0 = tx * C::TW;
-  stage_tile<C>(a.in, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
+  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, a.H, a.W, k0 - c,
+                                                                        l0 - c, sh, redf);
   __syncthreads();
 
   const int t0 = group * a.fpg;
@@ -228,8 +218,11 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
     for (int b = 0; b < C::BR; ++b)
 #pragma unroll
       for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
-    mfma_frame<C>(sh_hi, sh_lo, tab_t, row_base, col_base, acc);
+    const typename C::frag* tab_t =
+        reinterpret_cast<const typename C::frag*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
+    mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
+    // exact removal of the image and PSF scales (scaled encodings)
+    const int unscale = C::P::SCALED ? -(sx + table_exponents<C>(a)[t]) : 0;
     // epilogue: per-frame base pointers (wave-uniform) + 32-bit in-frame offsets
     const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
     const float* yt = a.y ? a.y + (int64_t)t * N : nullptr;
@@ -245,7 +238,7 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
           const int k = kb + v;
           if (k < a.H && l < a.W) {
             const int off = k * a.W + l;
-            const float m = acc[b][q][v];
+            const float m = C::P::SCALED ? ldexpf(acc[b][q][v], unscale) : acc[b][q][v];
             if (ut == nullptr) {
               ot[off] = m;
             } else {
@@ -272,9 +265,9 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
 template <class C>
 __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const int group) {
   constexpr int c = (C::KT - 1) / 2;
-  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
-  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[2 * C::NW];
+  __shared__ float redf[C::NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;
@@ -292,10 +285,31 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
   const int t1 = min(a.n, t0 + a.fpg);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
-    stage_tile<C>(a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh_hi, sh_lo);
+    const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
+        a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh, redf);
     __syncthreads();
-    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
-    mfma_frame<C>(sh_hi, sh_lo, tab_t, row_base, col_base, acc);
+    const typename C::frag* tab_t =
+        reinterpret_cast<const typename C::frag*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
+    if constexpr (C::P::SCALED) {
+      // each frame has its own scales: sum it in its own accumulators, then
+      // add it to the total unscaled (ldexp is exact)
+      f32x4 accf[C::BR][C::BC];
+#pragma unroll
+      for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+        for (int q = 0; q < C::BC; ++q) accf[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+      mfma_frame<C>(sh, tab_t, row_base, col_base, accf);
+      const int unscale = -(sr_t + table_exponents<C>(a)[t]);
+#pragma unroll
+      for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+        for (int q = 0; q < C::BC; ++q)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[b][q][v] += ldexpf(accf[b][q][v], unscale);
+    } else {
+      (void)sr_t;
+      mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
+    }
   }
 
   double dsq = 0.0, xsq = 0.0;
@@ -369,14 +383,30 @@ __global__ __launch_bounds__(C::NT) void mfma_adj_batched(const MfmaLaunch* __re
 }
 
 // Toeplitz fragment tables, one block per (frame, kernel row a): entry
-// [t][a][h][s][lane] holds the 8 bf16 values U_a[32h + 8(lane/16) + e][lane%16],
+// [t][a][h][s][lane] holds the 8 16-bit values U_a[32h + 8(lane/16) + e][lane%16],
 // e = 0..7, of part s (0 = hi, 1 = lo) of g = flip(f) (dir 0, forward) or
-// g = f (dir 1, adjoint), f zero-padded from K to KT.
-__global__ __launch_bounds__(256) void mfma_table_kernel(const float* psf, int K, int KT, int KTP,
-                                                         int dir, unsigned short* tab) {
+// g = f (dir 1, adjoint), f zero-padded from K to KT.  Scaled encodings
+// multiply g by 2^e_t (e_t = f16_scale_exp of max |f_t|) and store e_t as the
+// t-th of n ints after the fragments of all n frames.
+template <int PREC>
+__global__ __launch_bounds__(256) void mfma_table_kernel(const float* psf, int n, int K, int KT,
+                                                         int KTP, int dir, unsigned short* tab) {
+  __shared__ float redf[4];
   const int t = blockIdx.x, a = blockIdx.y;   // a in [0, KTP); rows a >= KT are zero
   const int off = (KT - K) / 2;
   const float* f = psf + (int64_t)t * K * K;
+  int ex = 0;
+  if constexpr (Prec<PREC>::SCALED) {
+    float mx = 0.f;
+    for (int i = threadIdx.x; i < K * K; i += 256) mx = fmaxf(mx, fabsf(f[i]));
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = fmaxf(fmaxf(redf[0], redf[1]), fmaxf(redf[2], redf[3]));
+    ex = f16_scale_exp(mx);
+    if (a == 0 && threadIdx.x == 0)
+      reinterpret_cast<int*>(tab + (size_t)n * KTP * 4 * 64 * 8)[t] = ex;
+  }
   const int idx = threadIdx.x;          // (h, s, lane) = 2 x 2 x 64
   const int lane = idx & 63, s = (idx >> 6) & 1, h = idx >> 7;
   const int j = lane & 15, gq = lane >> 4;
@@ -392,9 +422,7 @@ __global__ __launch_bounds__(256) void mfma_table_kernel(const float* psf, int K
       const int ia = fa - off, ib = fb - off;
       if (ia >= 0 && ia < K && ib >= 0 && ib < K) gv = f[ia * K + ib];
     }
-    unsigned short hi, lo;
-    split_bf16(gv, hi, lo);
-    dst[e] = s == 0 ? hi : lo;
+    dst[e] = table_part<PREC>(Prec<PREC>::SCALED ? ldexpf(gv, ex) : gv, s);
   }
 }
 
@@ -405,10 +433,15 @@ hipError_t launch_mfma_tables(const Geometry& g, const float* psf, void* tab_fwd
   if (g.sr == 2) return launch_mfma2_tables(g, psf, tab_fwd, tab_adj, s);
   const int KTP = mfma_table_rows(g.KT);
   dim3 grid(g.n, KTP);
-  hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, KTP, 0,
-                     static_cast<unsigned short*>(tab_fwd));
-  hipLaunchKernelGGL(mfma_table_kernel, grid, dim3(256), 0, s, psf, g.K, g.KT, KTP, 1,
-                     static_cast<unsigned short*>(tab_adj));
+  for (int dir = 0; dir < 2; ++dir) {
+    unsigned short* t = static_cast<unsigned short*>(dir == 0 ? tab_fwd : tab_adj);
+    if (g.precision == EM_FP16_SPLIT)
+      hipLaunchKernelGGL(mfma_table_kernel<EM_FP16_SPLIT>, grid, dim3(256), 0, s, psf, g.n, g.K,
+                         g.KT, KTP, dir, t);
+    else
+      hipLaunchKernelGGL(mfma_table_kernel<EM_BF16_SPLIT>, grid, dim3(256), 0, s, psf, g.n, g.K,
+                         g.KT, KTP, dir, t);
+  }
   return hipGetLastError();
 }
 
@@ -417,17 +450,19 @@ int mfma_tile_w() { return MF_TILE; }
 
 size_t mfma_table_bytes(const Geometry& g, int dir) {
   if (g.sr == 2) return mfma2_table_bytes(g.n, dir);
-  return (size_t)g.n * mfma_table_rows(g.KT) * 4 * 64 * 8 * sizeof(uint16_t);
+  // fragments, then one scale exponent per frame
+  return (size_t)g.n * mfma_table_rows(g.KT) * 4 * 64 * 8 * sizeof(uint16_t) +
+         (size_t)g.n * sizeof(int);
 }
 int mfma_variants() { return 3; }
 
 namespace {
 // variant v: 0 = 4 waves of 4x4 blocks; 1 = 8 waves of 4x2 blocks; 2 = 8 waves of 2x4 blocks
-template <int KT, int NS>
+template <int KT, int PREC>
 hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipStream_t s) {
-  using C0 = MfCfg<KT, NS, 4, 4, 2, 2, 1, 1>;
-  using C1 = MfCfg<KT, NS, 4, 2, 2, 4, 0, 1>;
-  using C2 = MfCfg<KT, NS, 2, 4, 4, 2, 0, 1>;
+  using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, 1>;
+  using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, 1>;
+  using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, 1>;
   static_assert(C0::TH == MF_TILE && C0::TW == MF_TILE, "tile");
   static_assert(C1::TH == MF_TILE && C1::TW == MF_TILE, "tile");
   static_assert(C2::TH == MF_TILE && C2::TW == MF_TILE, "tile");
@@ -445,12 +480,12 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
 }  // namespace
 
 namespace {
-template <int KT, int NS>
+template <int KT, int PREC>
 hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* d, const int4* it,
                               int n, hipStream_t s) {
-  using C0 = MfCfg<KT, NS, 4, 4, 2, 2, 1, 1>;
-  using C1 = MfCfg<KT, NS, 4, 2, 2, 4, 0, 1>;
-  using C2 = MfCfg<KT, NS, 2, 4, 4, 2, 0, 1>;
+  using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, 1>;
+  using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, 1>;
+  using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, 1>;
   if (dir == 0) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
@@ -467,12 +502,20 @@ hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* 
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
                                const int4* items, int n_items, int grid, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const bool split = precision == EM_BF16_SPLIT;
-  if (KT == KT_LARGE)
-    return split ? launch_dir_batched<KT_LARGE, 3>(dir, variant, grid, descs, items, n_items, s)
-                 : launch_dir_batched<KT_LARGE, 1>(dir, variant, grid, descs, items, n_items, s);
-  return split ? launch_dir_batched<KT_SMALL, 3>(dir, variant, grid, descs, items, n_items, s)
-               : launch_dir_batched<KT_SMALL, 1>(dir, variant, grid, descs, items, n_items, s);
+#define EM_MF_DISPATCH(KTV)                                                                  \
+  switch (precision) {                                                                       \
+    case EM_BF16_SPLIT:                                                                      \
+      return launch_dir_batched<KTV, EM_BF16_SPLIT>(dir, variant, grid, descs, items, n_items, s); \
+    case EM_FP16_SPLIT:                                                                      \
+      return launch_dir_batched<KTV, EM_FP16_SPLIT>(dir, variant, grid, descs, items, n_items, s); \
+    case EM_BF16:                                                                            \
+      return launch_dir_batched<KTV, EM_BF16>(dir, variant, grid, descs, items, n_items, s); \
+    default:                                                                                 \
+      return hipErrorInvalidValue;                                                           \
+  }
+  if (KT == KT_LARGE) { EM_MF_DISPATCH(KT_LARGE) }
+  EM_MF_DISPATCH(KT_SMALL)
+#undef EM_MF_DISPATCH
 }
 
 bool mfma_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
@@ -486,12 +529,16 @@ hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int g
   if (g.sr == 2) return launch_mfma2(g, dir, variant, tiles, groups, a, s);
   if (!mfma_desc_ok(g, dir, tiles, groups, a)) return hipErrorInvalidValue;
   dim3 grid(tiles, groups);
-  const bool split = g.precision == EM_BF16_SPLIT;
-  if (g.KT == KT_LARGE)
-    return split ? launch_dir<KT_LARGE, 3>(dir, variant, grid, a, s)
-                 : launch_dir<KT_LARGE, 1>(dir, variant, grid, a, s);
-  return split ? launch_dir<KT_SMALL, 3>(dir, variant, grid, a, s)
-               : launch_dir<KT_SMALL, 1>(dir, variant, grid, a, s);
+#define EM_MF_DISPATCH(KTV)                                                  \
+  switch (g.precision) {                                                     \
+    case EM_BF16_SPLIT: return launch_dir<KTV, EM_BF16_SPLIT>(dir, variant, grid, a, s); \
+    case EM_FP16_SPLIT: return launch_dir<KTV, EM_FP16_SPLIT>(dir, variant, grid, a, s); \
+    case EM_BF16: return launch_dir<KTV, EM_BF16>(dir, variant, grid, a, s);             \
+    default: return hipErrorInvalidValue;                                    \
+  }
+  if (g.KT == KT_LARGE) { EM_MF_DISPATCH(KT_LARGE) }
+  EM_MF_DISPATCH(KT_SMALL)
+#undef EM_MF_DISPATCH
 }
 
 }  // namespace em

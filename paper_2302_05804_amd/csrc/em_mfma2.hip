@@ -1,5 +1,5 @@
-// em_mfma2.hip -- BF16 matrix-core (MFMA) form of the two convolutions of one
-// EM iteration with super-resolution factor 2 (arXiv:2302.05804, Sec. 2,
+// em_mfma2.hip -- matrix-core (MFMA) forms of the two convolutions of one EM
+// iteration with super-resolution factor 2 (arXiv:2302.05804, Sec. 2,
 // Eq. (3) and Eq. (2)).
 //
 // With k = h * 1_{2x2} (the (K+1) x (K+1) kernel of the 2x2 box sum of
@@ -22,9 +22,10 @@
 // of r rows (sigma + i) serves parity 0 with alpha = sigma - 16 beta and parity 1
 // with alpha - 1, so one LDS read feeds both output parities.
 //
-// Precision and data movement as for sr = 1 (em_mfma.hip): hi + lo bf16 split
-// operands, three products, FP32 accumulation; input tile in LDS as hi / lo
-// planes; Toeplitz fragments pre-built per frame in MFMA lane order.
+// Precision encodings and data movement as for sr = 1 (em_mfma.hip): operand
+// encodings of em_mfma_common.h, FP32 accumulation; input tile in LDS, one
+// plane per image part; Toeplitz fragments pre-built per frame in MFMA lane
+// order, followed by the frames' scale exponents for scaled encodings.
 #include "em_device.h"
 #include "em_internal.h"
 #include "em_mfma_common.h"
@@ -37,35 +38,24 @@ constexpr int M2_FCH = 3;        // forward k-chunks per kernel row
 constexpr int M2_AROWS = 32;     // adjoint table rows per parity (22 used)
 constexpr int M2_FTILE = 64;     // forward: 64 x 64 frame pixels per workgroup
 constexpr int M2_ATILE = 128;    // adjoint: 128 x 128 latent pixels per workgroup
+// bytes of one frame's fragment tables (16-byte fragments, 64 lanes)
+constexpr size_t M2_FWD_FRAME_BYTES = (size_t)M2_FROWS * M2_FCH * 2 * 64 * 16;
+constexpr size_t M2_ADJ_FRAME_BYTES = (size_t)2 * M2_AROWS * 2 * 64 * 16;
 
-template <int ROWS, int COLS, int PITCH, int NT>
-__device__ inline void stage_split_tile(const float* __restrict__ src, int H, int W, int r0,
-                                        int q0, unsigned short* sh_hi, unsigned short* sh_lo) {
-  constexpr int HALF = COLS / 2;
-  for (int e = threadIdx.x; e < ROWS * HALF; e += NT) {
-    const int row = e / HALF, cp = e - row * HALF;
-    const int gy = r0 + row, gx = q0 + 2 * cp;
-    float v0 = 0.f, v1 = 0.f;
-    if (gy >= 0 && gy < H) {
-      const float* rp = src + (int64_t)gy * W;
-      if (gx >= 0 && gx < W) v0 = rp[gx];
-      if (gx + 1 >= 0 && gx + 1 < W) v1 = rp[gx + 1];
-    }
-    unsigned short h0, l0, h1, l1;
-    split_bf16(v0, h0, l0);
-    split_bf16(v1, h1, l1);
-    const int o = row * PITCH + 2 * cp;
-    *reinterpret_cast<unsigned int*>(sh_hi + o) = (unsigned int)h0 | ((unsigned int)h1 << 16);
-    *reinterpret_cast<unsigned int*>(sh_lo + o) = (unsigned int)l0 | ((unsigned int)l1 << 16);
-  }
+// Scale exponents of the frames (scaled encodings): n ints after the fragments.
+__device__ inline const int* m2_table_exponents(const MfmaLaunch& a, size_t frame_bytes) {
+  return reinterpret_cast<const int*>(static_cast<const char*>(a.tab) + (size_t)a.n * frame_bytes);
 }
 
 // ---------------------------------------------------------------------------
 // forward, sr = 2
 // ---------------------------------------------------------------------------
-template <int NS_, int BR_, int BC_, int WR_, int WC_>
+template <int PREC_, int BR_, int BC_, int WR_, int WC_>
 struct M2F {
-  static constexpr int NS = NS_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  using P = Prec<PREC_>;
+  using frag = typename P::frag;
+  static constexpr int PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int NS = P::NP, NA = P::NA, NB = P::NB;
   static constexpr int NW = WR * WC, NT = 64 * NW;
   static constexpr int TH = 16 * BR * WR, TW = 16 * BC * WC;      // frame pixels
   static constexpr int ROWS = 2 * TH + M2_KC - 2;                   // latent rows staged
@@ -74,23 +64,23 @@ struct M2F {
 };
 
 template <class C>
-__device__ inline void m2f_load_T(bf16x8 (&T)[2][M2_FCH][2], const bf16x8* __restrict__ tab_t,
-                                  int r) {
+__device__ inline void m2f_load_T(typename C::frag (&T)[2][M2_FCH][C::NB],
+                                  const typename C::frag* __restrict__ tab_t, int r) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int m = 0; m < 2; ++m)
 #pragma unroll
     for (int h = 0; h < M2_FCH; ++h)
 #pragma unroll
-      for (int s = 0; s < (C::NS == 3 ? 2 : 1); ++s)
+      for (int s = 0; s < C::NB; ++s)
         T[m][h][s] = tab_t[(((r + 32 * m) * M2_FCH + h) * 2 + s) * 64 + lane];
 }
 
 // one tap class a = r + 32 m (m < NM)
 template <class C, int NM>
-__device__ inline void m2f_class(int r, const unsigned short* sh_hi, const unsigned short* sh_lo,
-                                 const bf16x8 (&T)[2][M2_FCH][2], int row_base, int col_base,
-                                 f32x4 (&acc)[C::BR][C::BC]) {
+__device__ inline void m2f_class(int r, const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                 const typename C::frag (&T)[2][M2_FCH][C::NB], int row_base,
+                                 int col_base, f32x4 (&acc)[C::BR][C::BC]) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, g = lane >> 4;
   constexpr int NRHO = C::BR + NM - 1;
@@ -98,12 +88,13 @@ __device__ inline void m2f_class(int r, const unsigned short* sh_hi, const unsig
 #pragma unroll
   for (int rho = 0; rho < NRHO; ++rho) {
     const int lrow = row_base + r + 32 * rho + 2 * i;
-    bf16x8 A[NK][2];
+    typename C::frag A[NK][C::NA];
 #pragma unroll
     for (int kap = 0; kap < NK; ++kap) {
       const int o = lrow * C::PITCH + col_base + 32 * kap + 8 * g;
-      A[kap][0] = *reinterpret_cast<const bf16x8*>(sh_hi + o);
-      if (C::NS == 3) A[kap][1] = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+#pragma unroll
+      for (int p = 0; p < C::NA; ++p)
+        A[kap][p] = *reinterpret_cast<const typename C::frag*>(&sh[p][o]);
     }
 #pragma unroll
     for (int s = 0; s < C::NS; ++s)
@@ -117,8 +108,8 @@ __device__ inline void m2f_class(int r, const unsigned short* sh_hi, const unsig
           for (int h = 0; h < M2_FCH; ++h) {
             const int gam = kap - h;
             if (gam < 0 || gam >= C::BC) continue;
-            acc[beta][gam] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                A[kap][s == 1 ? 1 : 0], T[m][h][s == 2 ? 1 : 0], acc[beta][gam], 0, 0, 0);
+            acc[beta][gam] =
+                C::P::mma(A[kap][C::P::pa(s)], T[m][h][C::P::pb(s)], acc[beta][gam]);
           }
         }
   }
@@ -126,17 +117,17 @@ __device__ inline void m2f_class(int r, const unsigned short* sh_hi, const unsig
 
 template <class C>
 __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int group) {
-  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
-  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[C::NW];
+  __shared__ float redf[C::NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w / C::WC, wc = w % C::WC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;      // a.H, a.W: frame grid
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int I0 = ty * C::TH, J0 = tx * C::TW;
   const int Hl = 2 * a.H, Wl = 2 * a.W;
-  stage_split_tile<C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, Hl, Wl, 2 * I0 - 21, 2 * J0 - 21,
-                                                      sh_hi, sh_lo);
+  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
+      a.in, Hl, Wl, 2 * I0 - 21, 2 * J0 - 21, sh, redf);
   __syncthreads();
   const int row_base = wr * 32 * C::BR;    // latent rows of this wave's block row 0
   const int col_base = wc * 32 * C::BC;    // latent cols
@@ -151,21 +142,23 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
     for (int b = 0; b < C::BR; ++b)
 #pragma unroll
       for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const bf16x8* tab_t =
-        reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * M2_FROWS * M2_FCH * 2 * 64;
-    bf16x8 Tc[2][M2_FCH][2], Tn[2][M2_FCH][2];
+    const typename C::frag* tab_t = reinterpret_cast<const typename C::frag*>(a.tab) +
+                                    (int64_t)t * M2_FROWS * M2_FCH * 2 * 64;
+    typename C::frag Tc[2][M2_FCH][C::NB], Tn[2][M2_FCH][C::NB];
     m2f_load_T<C>(Tc, tab_t, 0);
     for (int r = 0; r < 32; ++r) {
       if (r + 1 < 32) m2f_load_T<C>(Tn, tab_t, r + 1);
-      if (r < M2_KC - 32) m2f_class<C, 2>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
-      else m2f_class<C, 1>(r, sh_hi, sh_lo, Tc, row_base, col_base, acc);
+      if (r < M2_KC - 32) m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
+      else m2f_class<C, 1>(r, sh, Tc, row_base, col_base, acc);
 #pragma unroll
       for (int m = 0; m < 2; ++m)
 #pragma unroll
         for (int h = 0; h < M2_FCH; ++h)
 #pragma unroll
-          for (int q = 0; q < 2; ++q) Tc[m][h][q] = Tn[m][h][q];
+          for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = Tn[m][h][q];
     }
+    const int unscale =
+        C::P::SCALED ? -(sx + m2_table_exponents(a, M2_FWD_FRAME_BYTES)[t]) : 0;
     const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
     const float* yt = a.y ? a.y + (int64_t)t * N : nullptr;
     float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
@@ -180,7 +173,7 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
           const int I = Ib + v;
           if (I < a.H && J < a.W) {
             const int off = I * a.W + J;
-            const float m = acc[b][q][v];
+            const float m = C::P::SCALED ? ldexpf(acc[b][q][v], unscale) : acc[b][q][v];
             if (ut == nullptr) {
               ot[off] = m;
             } else {
@@ -204,9 +197,12 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
 // ---------------------------------------------------------------------------
 // adjoint, sr = 2
 // ---------------------------------------------------------------------------
-template <int NS_, int BR_, int BC_, int WR_, int WC_>
+template <int PREC_, int BR_, int BC_, int WR_, int WC_>
 struct M2A {
-  static constexpr int NS = NS_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  using P = Prec<PREC_>;
+  using frag = typename P::frag;
+  static constexpr int PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int NS = P::NP, NA = P::NA, NB = P::NB;
   static constexpr int NW = WR * WC, NT = 64 * NW;
   static constexpr int THL = 32 * BR * WR, TWL = 16 * BC * WC;     // latent pixels
   // frame rows staged: THL/2 + 22 are read; the margin keeps every fragment
@@ -218,7 +214,8 @@ struct M2A {
 
 // Toeplitz fragments of adjoint class r: T[q][m] for alpha = r - q + 16 m.
 template <class C>
-__device__ inline void m2a_load_T(bf16x8 (&T)[2][2][2], const bf16x8* __restrict__ tab_t, int r) {
+__device__ inline void m2a_load_T(typename C::frag (&T)[2][2][C::NB],
+                                  const typename C::frag* __restrict__ tab_t, int r) {
   const int lane = threadIdx.x & 63;
 #pragma unroll
   for (int q = 0; q < 2; ++q)
@@ -227,7 +224,7 @@ __device__ inline void m2a_load_T(bf16x8 (&T)[2][2][2], const bf16x8* __restrict
       int al = r - q + 16 * m;
       al = al < 0 ? M2_AROWS - 1 : al;    // (alpha = -1 is never used; row 31 is zero)
 #pragma unroll
-      for (int s = 0; s < (C::NS == 3 ? 2 : 1); ++s)
+      for (int s = 0; s < C::NB; ++s)
         T[q][m][s] = tab_t[((q * M2_AROWS + al) * 2 + s) * 64 + lane];
     }
 }
@@ -235,9 +232,9 @@ __device__ inline void m2a_load_T(bf16x8 (&T)[2][2][2], const bf16x8* __restrict
 // One class of the adjoint: fragment rows R + 16 rho + i (R compile-time, so the
 // validity of every (parity, tap) pair folds away).
 template <class C, int R>
-__device__ inline void m2a_class(const unsigned short* sh_hi, const unsigned short* sh_lo,
-                                 const bf16x8 (&T)[2][2][2], int row_base, int col_base,
-                                 f32x4 (&acc)[2][C::BR][C::BC]) {
+__device__ inline void m2a_class(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                 const typename C::frag (&T)[2][2][C::NB], int row_base,
+                                 int col_base, f32x4 (&acc)[2][C::BR][C::BC]) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, g = lane >> 4;
 #pragma unroll
@@ -253,12 +250,13 @@ __device__ inline void m2a_class(const unsigned short* sh_hi, const unsigned sho
       }
     if (!used) continue;
     const int lrow = row_base + R + 16 * rho + i;
-    bf16x8 A[C::BC][2];
+    typename C::frag A[C::BC][C::NA];
 #pragma unroll
     for (int gam = 0; gam < C::BC; ++gam) {
       const int o = lrow * C::PITCH + col_base + 8 * gam + 8 * g;
-      A[gam][0] = *reinterpret_cast<const bf16x8*>(sh_hi + o);
-      if (C::NS == 3) A[gam][1] = *reinterpret_cast<const bf16x8*>(sh_lo + o);
+#pragma unroll
+      for (int p = 0; p < C::NA; ++p)
+        A[gam][p] = *reinterpret_cast<const typename C::frag*>(&sh[p][o]);
     }
 #pragma unroll
     for (int s = 0; s < C::NS; ++s)
@@ -273,38 +271,39 @@ __device__ inline void m2a_class(const unsigned short* sh_hi, const unsigned sho
             if (beta < 0 || beta >= C::BR) continue;
             const int al = R - q + 16 * m;
             if (al < 0 || al >= 22) continue;
-            acc[q][beta][gam] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
-                A[gam][s == 1 ? 1 : 0], T[q][m][s == 2 ? 1 : 0], acc[q][beta][gam], 0, 0, 0);
+            acc[q][beta][gam] =
+                C::P::mma(A[gam][C::P::pa(s)], T[q][m][C::P::pb(s)], acc[q][beta][gam]);
           }
   }
 }
 
 // Classes R .. 15 with the next class's Toeplitz fragments fetched early.
 template <class C, int R>
-__device__ inline void m2a_classes(const unsigned short* sh_hi, const unsigned short* sh_lo,
-                                   const bf16x8* __restrict__ tab_t, bf16x8 (&Tc)[2][2][2],
-                                   int row_base, int col_base, f32x4 (&acc)[2][C::BR][C::BC]) {
+__device__ inline void m2a_classes(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                   const typename C::frag* __restrict__ tab_t,
+                                   typename C::frag (&Tc)[2][2][C::NB], int row_base,
+                                   int col_base, f32x4 (&acc)[2][C::BR][C::BC]) {
   if constexpr (R < 16) {
-    bf16x8 Tn[2][2][2];
+    typename C::frag Tn[2][2][C::NB];
     if constexpr (R + 1 < 16) m2a_load_T<C>(Tn, tab_t, R + 1);
-    m2a_class<C, R>(sh_hi, sh_lo, Tc, row_base, col_base, acc);
+    m2a_class<C, R>(sh, Tc, row_base, col_base, acc);
     if constexpr (R + 1 < 16) {
 #pragma unroll
       for (int q = 0; q < 2; ++q)
 #pragma unroll
         for (int m = 0; m < 2; ++m)
 #pragma unroll
-          for (int s = 0; s < 2; ++s) Tc[q][m][s] = Tn[q][m][s];
-      m2a_classes<C, R + 1>(sh_hi, sh_lo, tab_t, Tc, row_base, col_base, acc);
+          for (int s = 0; s < C::NB; ++s) Tc[q][m][s] = Tn[q][m][s];
+      m2a_classes<C, R + 1>(sh, tab_t, Tc, row_base, col_base, acc);
     }
   }
 }
 
 template <class C>
 __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int group) {
-  __shared__ __align__(16) unsigned short sh_hi[C::ROWS * C::PITCH];
-  __shared__ __align__(16) unsigned short sh_lo[C::ROWS * C::PITCH];
+  __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[2 * C::NW];
+  __shared__ float redf[C::NW];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w / C::WC, wc = w % C::WC;
   const int Hf = a.H / 2, Wf = a.W / 2;             // a.H, a.W: latent grid
@@ -328,14 +327,37 @@ __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int g
   const int t1 = min(a.n, t0 + a.fpg);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
-    stage_split_tile<C::ROWS, C::COLS, C::PITCH, C::NT>(a.in + (int64_t)t * Nf, Hf, Wf,
-                                                        K0 / 2 - 11, L0 / 2 - 11, sh_hi, sh_lo);
+    const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
+        a.in + (int64_t)t * Nf, Hf, Wf, K0 / 2 - 11, L0 / 2 - 11, sh, redf);
     __syncthreads();
-    const bf16x8* tab_t = reinterpret_cast<const bf16x8*>(a.tab) + (int64_t)t * 2 * M2_AROWS * 2 * 64;
+    const typename C::frag* tab_t =
+        reinterpret_cast<const typename C::frag*>(a.tab) + (int64_t)t * 2 * M2_AROWS * 2 * 64;
     // classes r = 0..15 (fragment rows r + 16 rho) cover every (parity, tap) once
-    bf16x8 Tc[2][2][2];
+    typename C::frag Tc[2][2][C::NB];
     m2a_load_T<C>(Tc, tab_t, 0);
-    m2a_classes<C, 0>(sh_hi, sh_lo, tab_t, Tc, row_base, col_base, acc);
+    if constexpr (C::P::SCALED) {
+      // per-frame accumulators, added to the total with both scales removed
+      f32x4 accf[2][C::BR][C::BC];
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+          for (int c2 = 0; c2 < C::BC; ++c2) accf[q][b][c2] = f32x4{0.f, 0.f, 0.f, 0.f};
+      m2a_classes<C, 0>(sh, tab_t, Tc, row_base, col_base, accf);
+      const int unscale = -(sr_t + m2_table_exponents(a, M2_ADJ_FRAME_BYTES)[t]);
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+#pragma unroll
+        for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+          for (int c2 = 0; c2 < C::BC; ++c2)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[q][b][c2][v] += ldexpf(accf[q][b][c2][v], unscale);
+    } else {
+      (void)sr_t;
+      m2a_classes<C, 0>(sh, tab_t, Tc, row_base, col_base, acc);
+    }
   }
 
   double dsq = 0.0, xsq = 0.0;
@@ -414,9 +436,13 @@ __global__ __launch_bounds__(C::NT) void m2a_batched(const MfmaLaunch* __restric
 //                   U_a[p][j] = g[a][p - 2j], g = k flipped (a >= 44: zero);
 //  dir 1 (adjoint): [t][q][alpha < 32][s][lane] = k[2 alpha + q][2p - j],
 //                   p = 8(lane/16) + e, j = lane%16 (alpha >= 22: zero).
-// k = 2x2-box extension of f zero-padded from K to 43.
-__global__ __launch_bounds__(384) void m2_table_kernel(const float* psf, int K, int dir,
+// k = 2x2-box extension of f zero-padded from K to 43.  Scaled encodings
+// multiply k by 2^e_t (e_t = f16_scale_exp of max |k_t|) and store e_t as the
+// t-th of n ints after the fragments of all n frames.
+template <int PREC>
+__global__ __launch_bounds__(384) void m2_table_kernel(const float* psf, int n, int K, int dir,
                                                        unsigned short* tab) {
+  __shared__ float redf[6];
   const int t = blockIdx.x, row = blockIdx.y;
   const int off = (43 - K) / 2;
   const float* f = psf + (int64_t)t * K * K;
@@ -429,6 +455,22 @@ __global__ __launch_bounds__(384) void m2_table_kernel(const float* psf, int K, 
     if (a < 0 || a >= M2_KC || b < 0 || b >= M2_KC) return 0.f;
     return (fp(a - 1, b - 1) + fp(a - 1, b)) + (fp(a, b - 1) + fp(a, b));
   };
+  int ex = 0;
+  if constexpr (Prec<PREC>::SCALED) {
+    float mx = 0.f;
+    for (int i = threadIdx.x; i < M2_KC * M2_KC; i += 384)
+      mx = fmaxf(mx, fabsf(kk(i / M2_KC, i % M2_KC)));
+    mx = wave_max(mx);
+    if ((threadIdx.x & 63) == 0) redf[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    mx = redf[0];
+    for (int i = 1; i < 6; ++i) mx = fmaxf(mx, redf[i]);
+    ex = f16_scale_exp(mx);
+    if (row == 0 && threadIdx.x == 0) {
+      const size_t fb = dir == 0 ? M2_FWD_FRAME_BYTES : M2_ADJ_FRAME_BYTES;
+      reinterpret_cast<int*>(reinterpret_cast<char*>(tab) + (size_t)n * fb)[t] = ex;
+    }
+  }
   const int idx = threadIdx.x;
   if (dir == 0) {
     // row = a in [0, 64); idx = (h, s, lane) = 3 x 2 x 64
@@ -442,9 +484,7 @@ __global__ __launch_bounds__(384) void m2_table_kernel(const float* psf, int K, 
       const int b = p - 2 * j;
       float gv = 0.f;
       if (row < M2_KC && b >= 0 && b < M2_KC) gv = kk(M2_KC - 1 - row, M2_KC - 1 - b);
-      unsigned short hi, lo;
-      split_bf16(gv, hi, lo);
-      dst[e] = s == 0 ? hi : lo;
+      dst[e] = table_part<PREC>(Prec<PREC>::SCALED ? ldexpf(gv, ex) : gv, s);
     }
   } else {
     // row = q * 32 + alpha; idx = (s, lane) = 2 x 64
@@ -458,23 +498,23 @@ __global__ __launch_bounds__(384) void m2_table_kernel(const float* psf, int K, 
       const int b = 2 * p - j;
       float gv = 0.f;
       if (al < 22 && b >= 0 && b < M2_KC) gv = kk(2 * al + q, b);
-      unsigned short hi, lo;
-      split_bf16(gv, hi, lo);
-      dst[e] = s == 0 ? hi : lo;
+      dst[e] = table_part<PREC>(Prec<PREC>::SCALED ? ldexpf(gv, ex) : gv, s);
     }
   }
 }
 
 size_t mfma2_table_bytes(int n, int dir) {
-  return dir == 0 ? (size_t)n * M2_FROWS * M2_FCH * 2 * 64 * 8 * 2
-                  : (size_t)n * 2 * M2_AROWS * 2 * 64 * 8 * 2;
+  // fragments, then one scale exponent per frame
+  return (size_t)n * (dir == 0 ? M2_FWD_FRAME_BYTES : M2_ADJ_FRAME_BYTES) + (size_t)n * sizeof(int);
 }
 
 hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                                hipStream_t s) {
-  hipLaunchKernelGGL(m2_table_kernel, dim3(g.n, M2_FROWS), dim3(384), 0, s, psf, g.K, 0,
+  auto ker = g.precision == EM_FP16_SPLIT ? m2_table_kernel<EM_FP16_SPLIT>
+                                          : m2_table_kernel<EM_BF16_SPLIT>;
+  hipLaunchKernelGGL(ker, dim3(g.n, M2_FROWS), dim3(384), 0, s, psf, g.n, g.K, 0,
                      static_cast<unsigned short*>(tab_fwd));
-  hipLaunchKernelGGL(m2_table_kernel, dim3(g.n, 2 * M2_AROWS), dim3(384), 0, s, psf, g.K, 1,
+  hipLaunchKernelGGL(ker, dim3(g.n, 2 * M2_AROWS), dim3(384), 0, s, psf, g.n, g.K, 1,
                      static_cast<unsigned short*>(tab_adj));
   return hipGetLastError();
 }
@@ -486,15 +526,15 @@ namespace {
 // forward variants (64 x 64 frame pixels): 0: 4 waves of 2x2 blocks; 1: 8 waves of 2x1;
 // 2: 8 waves of 1x2.  adjoint variants (128 x 128 latent): 0: 8 waves of 2x2 blocks
 // (per parity); 1: 4 waves of 4x2; 2: 4 waves of 2x4.
-template <int NS>
+template <int PREC>
 hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
                    const MfmaLaunch* d, const int4* it, int n, hipStream_t s) {
-  using F0 = M2F<NS, 2, 2, 2, 2>;
-  using F1 = M2F<NS, 2, 1, 2, 4>;
-  using F2 = M2F<NS, 1, 2, 4, 2>;
-  using A0 = M2A<NS, 2, 2, 2, 4>;
-  using A1 = M2A<NS, 4, 2, 1, 4>;
-  using A2 = M2A<NS, 2, 4, 2, 2>;
+  using F0 = M2F<PREC, 2, 2, 2, 2>;
+  using F1 = M2F<PREC, 2, 1, 2, 4>;
+  using F2 = M2F<PREC, 1, 2, 4, 2>;
+  using A0 = M2A<PREC, 2, 2, 2, 4>;
+  using A1 = M2A<PREC, 4, 2, 1, 4>;
+  using A2 = M2A<PREC, 2, 4, 2, 2>;
   static_assert(F0::TH == M2_FTILE && F0::TW == M2_FTILE && F1::TH == M2_FTILE &&
                 F1::TW == M2_FTILE && F2::TH == M2_FTILE && F2::TW == M2_FTILE, "fwd tile");
   static_assert(A0::THL == M2_ATILE && A0::TWL == M2_ATILE && A1::THL == M2_ATILE &&
@@ -533,18 +573,24 @@ hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int 
                         const MfmaLaunch& a, hipStream_t s) {
   if (!mfma2_desc_ok(g, dir, tiles, groups, a)) return hipErrorInvalidValue;
   dim3 grid(tiles, groups);
-  return g.precision == EM_BF16_SPLIT
-             ? launch2<3>(dir, variant, grid, false, a, nullptr, nullptr, 0, s)
-             : launch2<1>(dir, variant, grid, false, a, nullptr, nullptr, 0, s);
+  switch (g.precision) {
+    case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, grid, false, a, nullptr, nullptr, 0, s);
+    case EM_FP16_SPLIT: return launch2<EM_FP16_SPLIT>(dir, variant, grid, false, a, nullptr, nullptr, 0, s);
+    case EM_BF16: return launch2<EM_BF16>(dir, variant, grid, false, a, nullptr, nullptr, 0, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
                                 const int4* items, int n_items, int grid, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
   MfmaLaunch dummy{};
-  return precision == EM_BF16_SPLIT
-             ? launch2<3>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s)
-             : launch2<1>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
+  switch (precision) {
+    case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
+    case EM_FP16_SPLIT: return launch2<EM_FP16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
+    case EM_BF16: return launch2<EM_BF16>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace em

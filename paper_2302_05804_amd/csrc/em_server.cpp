@@ -584,7 +584,6 @@ int em_submit(em_server* S, const em_problem* p, const float* y_host, const floa
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
-  if (g.precision == EM_FP16_SPLIT) return fail(EM_ENOTSUP, "precision not provided");
   if (g.weight_mode != EM_W_ADJOINT) return fail(EM_ENOTSUP, "weight mode not provided");
   size_t total, a, b, c2, d, e, wsb;
   job_layout(g, &total, &a, &b, &c2, &d, &e, &wsb);

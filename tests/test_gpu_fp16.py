@@ -1,0 +1,199 @@
+"""Parity of the FP16 matrix-core form (EM_FP16_SPLIT) with the FP64 oracle.
+
+Encoding: the image operand is rounded to binary16 after an exact power-of-two
+scale chosen per staged tile (largest magnitude in [2^14, 2^15)); the PSF is
+split into binary16 hi + lo after a power-of-two scale per frame; the two
+products accumulate in FP32 and the epilogue removes both scales exactly.
+
+Error model of one output o = sum_k g_k v_k: rounding each v_k to 11
+significant bits moves it by at most 2^-11 |v_k| (values down to 2^-29 of the
+tile maximum are normal binary16 numbers); the hi + lo PSF is exact to about
+2^-22; products of binary16 numbers are exact in FP32 and the FP32 sums add a
+few 2^-24.  The operator tests therefore bound |o_gpu - o| by
+6e-4 * sum_k |g_k||v_k| element by element (the oracle on absolute values).
+Whole EM runs must stay within rel L2 1e-3 of the oracle's iterate, the bar of
+the mixed-precision forms.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2302_05804_amd import synth
+from tests.gpu_common import gpu_run, log, rel_l2, to_dev
+
+pytestmark = pytest.mark.gpu
+
+OP16_EPS = 6e-4
+X_TOL = 1e-3
+
+
+def _em():
+    from paper_2302_05804_amd import em
+    return em
+
+
+def _ops(em, sr, psf, x, r):
+    n, K = psf.shape[0], psf.shape[1]
+    hf, wf = r.shape[1], r.shape[2]
+    p = em.Problem.make(n, hf, wf, K, sr=sr, precision=em.FP16_SPLIT)
+    m = em.forward_op(p, to_dev(psf), to_dev(x)).cpu().numpy()
+    s = em.adjoint_op(p, to_dev(psf), to_dev(r)).cpu().numpy()
+    return m, s
+
+
+@pytest.mark.parametrize("sr,K,hf,wf,n", [(1, 43, 150, 131, 2), (1, 15, 70, 260, 3),
+                                          (1, 7, 33, 40, 2), (1, 43, 5, 3, 1),
+                                          (1, 43, 129, 257, 1), (2, 43, 75, 66, 2),
+                                          (2, 15, 40, 70, 3), (2, 43, 3, 2, 1),
+                                          (2, 43, 130, 97, 2)])
+def test_fp16_operators_elementwise_bound(sr, K, hf, wf, n):
+    em = _em()
+    log(f"fp16 operators sr={sr} K={K} frame {hf}x{wf} n={n}")
+    rng = np.random.default_rng(K * 13 + hf + sr)
+    psf = rng.uniform(0, 1, (n, K, K)).astype(np.float32)
+    psf /= psf.sum(axis=(1, 2), keepdims=True)
+    x = rng.gamma(0.5, 200.0, (sr * hf, sr * wf)).astype(np.float32)
+    r = rng.normal(0, 1, (n, hf, wf)).astype(np.float32)
+    m, s = _ops(em, sr, psf, x, r)
+    for t in range(n):
+        mo = oracle.forward(psf[t], x, sr)
+        so = oracle.adjoint(psf[t], r[t], sr)
+        mb = oracle.forward(np.abs(psf[t]), np.abs(x), sr)
+        sb = oracle.adjoint(np.abs(psf[t]), np.abs(r[t]), sr)
+        assert (np.abs(m[t] - mo) <= OP16_EPS * mb + 1e-30).all()
+        assert (np.abs(s[t] - so) <= OP16_EPS * sb + 1e-30).all()
+        log(f"  t={t}: rel L2 fwd {rel_l2(m[t], mo):.2e} adj {rel_l2(s[t], so):.2e}")
+
+
+@pytest.mark.parametrize("sr", [1, 2])
+def test_fp16_scales_cover_any_magnitude(sr):
+    """Values far outside the binary16 range (1e-30 .. 1e9 in one image, PSFs
+    scaled by 1e12) stay within the same elementwise bound, and scaling an input
+    by a power of two scales the output by exactly that power (the encoding's
+    scales are powers of two chosen from the data)."""
+    em = _em()
+    rng = np.random.default_rng(40 + sr)
+    n, K, hf, wf = 2, 43, 90, 110
+    psf = rng.uniform(0, 1, (n, K, K)).astype(np.float32)
+    psf *= (1e12 / psf.sum(axis=(1, 2), keepdims=True)).astype(np.float32)
+    g = rng.gamma(0.5, 1.0, (sr * hf, sr * wf))
+    x = (g * 1e9).astype(np.float32)                      # binary16 overflows at 65504
+    x[: sr * hf // 2] = (g[: sr * hf // 2] * 1e-30).astype(np.float32)   # and underflows here
+    r = (rng.normal(0, 1, (n, hf, wf)) * 1e-20).astype(np.float32)
+    m, s = _ops(em, sr, psf, x, r)
+    for t in range(n):
+        mo = oracle.forward(psf[t], x, sr)
+        so = oracle.adjoint(psf[t], r[t], sr)
+        mb = oracle.forward(np.abs(psf[t]), np.abs(x), sr)
+        sb = oracle.adjoint(np.abs(psf[t]), np.abs(r[t]), sr)
+        # an absolute floor for values below 2^-29 of their tile's maximum
+        fm = 2.0 ** -38 * np.abs(x).max() * np.abs(psf[t]).sum()
+        fs = 2.0 ** -38 * np.abs(r[t]).max() * np.abs(psf[t]).sum()
+        assert np.isfinite(m[t]).all() and np.isfinite(s[t]).all()
+        assert (np.abs(m[t] - mo) <= OP16_EPS * mb + fm).all()
+        assert (np.abs(s[t] - so) <= OP16_EPS * sb + fs).all()
+        log(f"  sr={sr} t={t}: rel L2 fwd {rel_l2(m[t], mo):.2e} adj {rel_l2(s[t], so):.2e}")
+    m2, s2 = _ops(em, sr, psf * np.float32(2.0 ** 7), x * np.float32(2.0 ** -13),
+                  r * np.float32(2.0 ** 20))
+    assert np.array_equal(m2, m * np.float32(2.0 ** -6))
+    assert np.array_equal(s2, s * np.float32(2.0 ** 27))
+
+
+def _run(p, n_iter, x0):
+    em = _em()
+    xg, trg = gpu_run(p.y, p.v, p.psf, p.sr, n_iter, x0=x0, precision=em.FP16_SPLIT)
+    xo, tro, _ = oracle.run(p.y, p.v, p.psf, x0, n_iter, p.sr, trace=True)
+    err = rel_l2(xg, xo)
+    llerr = float(np.abs(trg - tro).max() / np.abs(tro).max())
+    return err, llerr, xg, trg
+
+
+def test_fp16_c1_full_run():
+    p = synth.make_problem("c1")
+    x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v), np.float32)
+    err, llerr, xg, trg = _run(p, p.n_iter, x0)
+    log(f"c1 fp16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= X_TOL and (xg >= 0).all()
+
+
+def test_fp16_hundred_iterations():
+    p = synth.make_problem("c2", H=128, W=128, n=4, seed=101)
+    x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v), np.float32)
+    err, llerr, xg, _ = _run(p, 100, x0)
+    log(f"100 iterations fp16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= X_TOL and llerr <= X_TOL and (xg >= 0).all()
+
+
+def test_fp16_c3_recipe_multi_tile_ragged():
+    p = synth.make_problem("c3", H=300, W=260, n=4)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v), 1.0), seed=8)
+    err, llerr, xg, _ = _run(p, 6, x0)
+    log(f"c3-tiles fp16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= X_TOL and (xg >= 0).all()
+
+
+def test_fp16_c4_recipe_sr2():
+    p = synth.make_problem("c4", H=192, W=134, n=3)
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(p.y, p.v, 2), 0.25), seed=9)
+    err, llerr, xg, _ = _run(p, 10, x0)
+    log(f"c4-sr2 fp16-split: rel L2(x) {err:.3e}, loglik rel err {llerr:.3e}")
+    assert err <= X_TOL and (xg >= 0).all()
+
+
+@pytest.mark.parametrize("sr", [1, 2])
+def test_fp16_every_variant_matches_oracle(sr):
+    import torch
+    em = _em()
+    p = synth.make_problem("c3" if sr == 1 else "c4", H=260, W=200, n=3, seed=4403)
+    x0 = synth.positive_start(p.latent_shape, 2.0, seed=14)
+    xo = oracle.run(p.y, p.v, p.psf, x0, 3, sr=sr)
+    prob = em.Problem.make(3, 260 // sr, 200 // sr, 43, sr=sr, precision=em.FP16_SPLIT)
+    nv = em._lib.em_variant_count()
+    outs = []
+    for fv in range(nv):
+        for av in range(nv):
+            x = torch.empty(p.latent_shape, dtype=torch.float32, device="cuda")
+            ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+            ctx.set_variants(fv, av)
+            ctx.iterate(3)
+            ctx.sync()
+            xg = x.cpu().numpy()
+            ctx.close()
+            err = rel_l2(xg, xo)
+            log(f"fp16 sr={sr} variant fwd={fv} adj={av}: rel L2 {err:.2e}")
+            assert err <= X_TOL
+            outs.append(xg)
+    # autotune picks valid variants and leaves the iterate alone
+    x = torch.empty(p.latent_shape, dtype=torch.float32, device="cuda")
+    ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
+    before = x.clone()
+    fv, av, ms = ctx.autotune(1)
+    torch.cuda.synchronize()
+    assert torch.equal(before, x) and 0 <= fv < nv and 0 <= av < nv and (ms > 0).all()
+    ctx.iterate(3)
+    ctx.sync()
+    assert np.array_equal(x.cpu().numpy(), outs[fv * nv + av])
+    ctx.close()
+
+
+def test_fp16_deterministic_and_graph_replays():
+    import torch
+    em = _em()
+    p = synth.make_problem("c2", H=192, W=160, n=3, seed=31)
+    prob = em.Problem.make(3, 192, 160, 43, precision=em.FP16_SPLIT)
+    x0 = synth.positive_start(p.latent_shape, 20.0, seed=32)
+    xe = torch.empty(p.latent_shape, dtype=torch.float32, device="cuda")
+    xg = torch.empty_like(xe)
+    eager = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), xe, x0=to_dev(x0))
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        graphed = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), xg, x0=to_dev(x0),
+                             stream=side)
+    for k in range(4):
+        eager.iterate(1)
+        graphed.iterate(1)
+        torch.cuda.synchronize()
+        assert torch.equal(xe, xg), f"replay {k}"
+        _ = (xe * 2).sum().item()
+    eager.close()
+    graphed.close()

@@ -192,7 +192,7 @@ def test_invalid_inputs_are_rejected():
         init(ws=torch.empty(1024, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == em.ENOMEM
     with pytest.raises(em.EMError) as ei:
-        init(prob=em.Problem.make(2, 32, 32, 15, precision=em.FP16_SPLIT))
+        init(prob=em.Problem.make(2, 32, 32, 15, weight_mode=em.W_LITERAL))
     assert ei.value.code == em.ENOTSUP
     # masked pixels with NaN exposures are fine and never read as numbers
     y2 = p.y.copy()

@@ -30,6 +30,8 @@ def _jobs():
         ("c2", 200, 136, 2, 1, em.BF16_SPLIT, 9),
         ("c1", 64, 64, 4, 1, em.FP32, 12),
         ("c4", 64, 192, 3, 2, em.FP32, 4),
+        ("c3", 128, 160, 3, 1, em.FP16_SPLIT, 6),
+        ("c4", 96, 128, 2, 2, em.FP16_SPLIT, 5),
     ]
     out = []
     for k, (rec, H, W, n, sr, prec, it) in enumerate(specs):
