@@ -33,6 +33,8 @@
 #include "em_internal.h"
 #include "em_mfma_common.h"
 
+#include <type_traits>
+
 namespace em {
 
 constexpr int MF_TILE = 128;   // every sr = 1 variant covers 128 x 128 outputs
@@ -46,7 +48,9 @@ struct MfCfg {
   static constexpr int KT = KT_, PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
   static constexpr int NS = P::NP, NA = P::NA, NB = P::NB;
   // PFA: load the A fragments of the next fragment row before the products of
-  // the current one; PFT: fetch the next tap class's Toeplitz fragments early.
+  // the current one.  PFT = 1: each wave fetches the next tap class's Toeplitz
+  // fragments into registers early; PFT = 2: the workgroup stages them once in
+  // LDS with direct global-to-LDS loads (two buffers, one barrier per class).
   static constexpr int PFA = PFA_, PFT = PFT_;
   static constexpr int NW = WR * WC, NT = 64 * NW;
   static constexpr int TH = 16 * BR * WR, TW = 16 * BC * WC;
@@ -55,7 +59,18 @@ struct MfCfg {
   static constexpr int PITCH = mf_pitch(COLS);
   static constexpr int MMAX = (KT + 15) / 16;   // members of the largest tap class
   static constexpr int KTP = 16 * MMAX;         // table rows (zero beyond KT)
+  static constexpr int NTF = MMAX * 2 * NB;     // Toeplitz fragments of one class
+  static constexpr int RFULL = KT - 16 * (MMAX - 1);     // classes with MMAX members
+  static constexpr int RLAST = (MMAX == 1) ? KT : 16;    // number of classes
 };
+
+// LDS staging buffers of the Toeplitz fragments (PFT = 2): two classes, NTF
+// fragments of 64 lanes each.
+template <class C>
+using TBuf = typename C::frag[2][C::NTF][64];
+// what the kernel bodies allocate (a token when the fragments are not staged)
+template <class C>
+using TBufDecl = std::conditional_t<C::PFT == 2, TBuf<C>, int[4]>;
 
 // Toeplitz fragments of tap class r (rows a = r + 16 m, m < MMAX), both k-halves,
 // hi and (split) lo parts.
@@ -180,6 +195,71 @@ __device__ inline void mfma_frame(const unsigned short (*sh)[C::ROWS * C::PITCH]
   }
 }
 
+// PFT = 2: start copying the Toeplitz fragments of class r of one frame's
+// table into an LDS buffer: buffer fragment f = (m, h, s) of the class; the
+// waves of the workgroup share the fragments round robin, each lane moving its
+// own 16 bytes (global_load_lds_dwordx4: destination = wave-uniform base + 16
+// bytes per lane, the fragment's lane order).
+template <class C>
+__device__ inline void issue_T(const typename C::frag* __restrict__ tab_t, int r, void* dst_v) {
+  typename C::frag* dst = static_cast<typename C::frag*>(dst_v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int f = w; f < C::NTF; f += C::NW) {
+    const int s = f % C::NB, h = (f / C::NB) % 2, m = f / (2 * C::NB);
+    const typename C::frag* src = tab_t + (((r + 16 * m) * 2 + h) * 2 + s) * 64 + lane;
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src),
+                                     (__attribute__((address_space(3))) void*)(dst + f * 64), 16,
+                                     0, 0);
+  }
+}
+
+// One tap class with the Toeplitz fragments staged in LDS: start the copy of
+// the next class (the first class of tab_next after the last one, if any) into
+// the other buffer, read this class's fragments from LDS, issue its products,
+// then wait for this wave's copies and meet the other waves at a barrier, after
+// which the next buffer is complete and this one free.
+template <class C, int NM>
+__device__ inline void mfma_class_lds(int r, const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                      const typename C::frag* __restrict__ tab_t,
+                                      const typename C::frag* __restrict__ tab_next,
+                                      TBuf<C>& tl, int& step, int row_base, int col_base,
+                                      f32x4 (&acc)[C::BR][C::BC]) {
+  const int lane = threadIdx.x & 63;
+  const int cur = step & 1;
+  if (r + 1 < C::RLAST) issue_T<C>(tab_t, r + 1, (void*)&tl[cur ^ 1][0][0]);
+  else if (tab_next != nullptr) issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+  typename C::frag Tc[C::MMAX][2][C::NB];
+#pragma unroll
+  for (int m = 0; m < C::MMAX; ++m)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = tl[cur][(m * 2 + h) * C::NB + q][lane];
+  mfma_class<C, NM>(r, sh, Tc, row_base, col_base, acc);
+  frags_landed();
+  ++step;
+}
+
+// All classes of one frame with the Toeplitz fragments staged in LDS.  On entry
+// the fragments of class 0 are in buffer step & 1 (a barrier after their copy
+// has been passed).
+template <class C>
+__device__ inline void mfma_frame_lds(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                      const typename C::frag* __restrict__ tab_t,
+                                      const typename C::frag* __restrict__ tab_next,
+                                      TBuf<C>& tl, int& step, int row_base, int col_base,
+                                      f32x4 (&acc)[C::BR][C::BC]) {
+  int r = 0;
+#pragma unroll 1
+  for (; r < C::RFULL; ++r)
+    mfma_class_lds<C, C::MMAX>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+  if constexpr (C::MMAX > 1) {
+#pragma unroll 1
+    for (; r < C::RLAST; ++r)
+      mfma_class_lds<C, C::MMAX - 1>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+  }
+}
+
 // Scale exponents of a frame's Toeplitz table (scaled encodings): n ints after
 // the fragments of all frames.
 template <class C>
@@ -200,12 +280,18 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
   const int tiles_x = (a.W + C::TW - 1) / C::TW;
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int k0 = ty * C::TH, l0 = tx * C::TW;
-  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, a.H, a.W, k0 - c,
-                                                                        l0 - c, sh, redf);
-  __syncthreads();
-
   const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
+  const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
+  constexpr int64_t TSTRIDE = (int64_t)C::KTP * 4 * 64;   // fragments per frame
+  __shared__ __align__(16) TBufDecl<C> tl;
+  int step = 0;
+  if constexpr (C::PFT == 2) issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
+  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, a.H, a.W, k0 - c,
+                                                                        l0 - c, sh, redf);
+  if constexpr (C::PFT == 2) frags_landed();
+  else __syncthreads();
+
   const int64_t N = (int64_t)a.H * a.W;
   double llp = 0.0;
   for (int t = t0; t < t1; ++t) {
@@ -218,40 +304,20 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
     for (int b = 0; b < C::BR; ++b)
 #pragma unroll
       for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const typename C::frag* tab_t =
-        reinterpret_cast<const typename C::frag*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
-    mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
+    const typename C::frag* tab_t = tab + t * TSTRIDE;
+    if constexpr (C::PFT == 2)
+      mfma_frame_lds<C>(sh, tab_t, t + 1 < t1 ? tab_t + TSTRIDE : nullptr, tl, step, row_base,
+                        col_base, acc);
+    else
+      mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
     // exact removal of the image and PSF scales (scaled encodings)
     const int unscale = C::P::SCALED ? -(sx + table_exponents<C>(a)[t]) : 0;
     // epilogue: per-frame base pointers (wave-uniform) + 32-bit in-frame offsets
     const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
-    const float* yt = a.y ? a.y + (int64_t)t * N : nullptr;
+    const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;
     float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
-#pragma unroll
-    for (int b = 0; b < C::BR; ++b)
-#pragma unroll
-      for (int q = 0; q < C::BC; ++q) {
-        const int l = l0 + col_base + 16 * q + (lane & 15);
-        const int kb = k0 + row_base + 16 * b + 4 * (lane >> 4);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int k = kb + v;
-          if (k < a.H && l < a.W) {
-            const int off = k * a.W + l;
-            const float m = C::P::SCALED ? ldexpf(acc[b][q][v], unscale) : acc[b][q][v];
-            if (ut == nullptr) {
-              ot[off] = m;
-            } else {
-              const float uu = ut[off];
-              if (ot) ot[off] = uu * m;
-              if (a.part != nullptr && uu > 0.f) {
-                const double d = (double)yt[off] - (double)m;
-                llp += (double)uu * d * d;
-              }
-            }
-          }
-        }
-      }
+    llp += forward_epilogue<C::BR, C::BC>(acc, unscale, BlockPos{k0 + row_base, l0 + col_base, 1},
+                                          a.H, a.W, ut, yt, ot);
   }
   if (a.part != nullptr) {
     const double s = block_sum<C::NT>(llp, red);
@@ -283,13 +349,19 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
 
   const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
+  const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
+  constexpr int64_t TSTRIDE = (int64_t)C::KTP * 4 * 64;   // fragments per frame
+  __shared__ __align__(16) TBufDecl<C> tl;
+  int step = 0;
+  if constexpr (C::PFT == 2) issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
     const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
         a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh, redf);
-    __syncthreads();
-    const typename C::frag* tab_t =
-        reinterpret_cast<const typename C::frag*>(a.tab) + (int64_t)t * C::KTP * 4 * 64;
+    if constexpr (C::PFT == 2) frags_landed();
+    else __syncthreads();
+    const typename C::frag* tab_t = tab + t * TSTRIDE;
+    const typename C::frag* tab_next = t + 1 < t1 ? tab_t + TSTRIDE : nullptr;
     if constexpr (C::P::SCALED) {
       // each frame has its own scales: sum it in its own accumulators, then
       // add it to the total unscaled (ldexp is exact)
@@ -298,7 +370,10 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
       for (int b = 0; b < C::BR; ++b)
 #pragma unroll
         for (int q = 0; q < C::BC; ++q) accf[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-      mfma_frame<C>(sh, tab_t, row_base, col_base, accf);
+      if constexpr (C::PFT == 2)
+        mfma_frame_lds<C>(sh, tab_t, tab_next, tl, step, row_base, col_base, accf);
+      else
+        mfma_frame<C>(sh, tab_t, row_base, col_base, accf);
       const int unscale = -(sr_t + table_exponents<C>(a)[t]);
 #pragma unroll
       for (int b = 0; b < C::BR; ++b)
@@ -308,36 +383,17 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
           for (int v = 0; v < 4; ++v) acc[b][q][v] += ldexpf(accf[b][q][v], unscale);
     } else {
       (void)sr_t;
-      mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
+      if constexpr (C::PFT == 2)
+        mfma_frame_lds<C>(sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+      else
+        mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
     }
   }
 
   double dsq = 0.0, xsq = 0.0;
-  float* pl = a.fused ? nullptr : a.plane + (int64_t)group * N;
-#pragma unroll
-  for (int b = 0; b < C::BR; ++b)
-#pragma unroll
-    for (int q = 0; q < C::BC; ++q) {
-      const int l = l0 + col_base + 16 * q + (lane & 15);
-      const int kb = k0 + row_base + 16 * b + 4 * (lane >> 4);
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = kb + v;
-        if (k < a.H && l < a.W) {
-          const int off = k * a.W + l;
-          if (a.fused) {
-            const float xo = a.x[off];
-            const float xn = mf_update_value(xo, a.B[off], acc[b][q][v]);
-            a.x[off] = xn;
-            const double d = (double)xn - (double)xo;
-            dsq += d * d;
-            xsq += (double)xo * (double)xo;
-          } else {
-            pl[off] = acc[b][q][v];
-          }
-        }
-      }
-    }
+  adjoint_epilogue<C::BR, C::BC>(acc, BlockPos{k0 + row_base, l0 + col_base, 1}, a.H, a.W,
+                                 a.fused, a.x, a.B,
+                                 a.fused ? nullptr : a.plane + (int64_t)group * N, dsq, xsq);
   if (a.fused && a.part != nullptr) {
     const double s1 = block_sum<C::NT>(dsq, red);
     __syncthreads();
@@ -460,9 +516,12 @@ namespace {
 // variant v: 0 = 4 waves of 4x4 blocks; 1 = 8 waves of 4x2 blocks; 2 = 8 waves of 2x4 blocks
 template <int KT, int PREC>
 hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipStream_t s) {
-  using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, 1>;
-  using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, 1>;
-  using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, 1>;
+  // Toeplitz fragments: staged in LDS for the one-plane binary16 image (LDS
+  // traffic is low there), register prefetch for the two-plane bf16 split
+  constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
+  using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, PFT>;
+  using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, PFT>;
+  using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, PFT>;
   static_assert(C0::TH == MF_TILE && C0::TW == MF_TILE, "tile");
   static_assert(C1::TH == MF_TILE && C1::TW == MF_TILE, "tile");
   static_assert(C2::TH == MF_TILE && C2::TW == MF_TILE, "tile");
@@ -483,9 +542,12 @@ namespace {
 template <int KT, int PREC>
 hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* d, const int4* it,
                               int n, hipStream_t s) {
-  using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, 1>;
-  using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, 1>;
-  using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, 1>;
+  // Toeplitz fragments: staged in LDS for the one-plane binary16 image (LDS
+  // traffic is low there), register prefetch for the two-plane bf16 split
+  constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
+  using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, PFT>;
+  using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, PFT>;
+  using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, PFT>;
   if (dir == 0) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);

@@ -30,6 +30,8 @@
 #include "em_internal.h"
 #include "em_mfma_common.h"
 
+#include <type_traits>
+
 namespace em {
 
 constexpr int M2_KC = 44;        // box-extended kernel size for K = 43
@@ -50,12 +52,16 @@ __device__ inline const int* m2_table_exponents(const MfmaLaunch& a, size_t fram
 // ---------------------------------------------------------------------------
 // forward, sr = 2
 // ---------------------------------------------------------------------------
-template <int PREC_, int BR_, int BC_, int WR_, int WC_>
+// PFT = 1: each wave prefetches the next class's Toeplitz fragments into
+// registers; PFT = 2: the workgroup stages them in LDS (two buffers, one
+// barrier per class), as for sr = 1.
+template <int PREC_, int BR_, int BC_, int WR_, int WC_, int PFT_>
 struct M2F {
   using P = Prec<PREC_>;
   using frag = typename P::frag;
-  static constexpr int PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_, PFT = PFT_;
   static constexpr int NS = P::NP, NA = P::NA, NB = P::NB;
+  static constexpr int NTF = 2 * M2_FCH * NB;   // Toeplitz fragments of one class
   static constexpr int NW = WR * WC, NT = 64 * NW;
   static constexpr int TH = 16 * BR * WR, TW = 16 * BC * WC;      // frame pixels
   static constexpr int ROWS = 2 * TH + M2_KC - 2;                   // latent rows staged
@@ -115,6 +121,54 @@ __device__ inline void m2f_class(int r, const unsigned short (*sh)[C::ROWS * C::
   }
 }
 
+// LDS buffers of the Toeplitz fragments (PFT = 2) and what the bodies allocate.
+template <class C>
+using M2TBuf = typename C::frag[2][C::NTF][64];
+template <class C>
+using M2TBufDecl = std::conditional_t<C::PFT == 2, M2TBuf<C>, int[4]>;
+
+// Forward class r: buffer fragment f = (m, h, s) is table fragment
+// ((r + 32 m) FCH + h) 2 + s.
+template <class C>
+__device__ inline void m2f_issue_T(const typename C::frag* __restrict__ tab_t, int r, void* dst) {
+  stage_frags<C::NTF, C::NW>(
+      tab_t,
+      [r](int f) {
+        const int s = f % C::NB, h = (f / C::NB) % M2_FCH, m = f / (C::NB * M2_FCH);
+        return ((r + 32 * m) * M2_FCH + h) * 2 + s;
+      },
+      dst);
+}
+
+// All 32 forward classes of one frame with LDS-staged fragments (on entry class
+// 0 is in buffer step & 1); the last class starts the copy of the next frame's
+// class 0 when tab_next is given.
+template <class C>
+__device__ inline void m2f_frame_lds(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                     const typename C::frag* __restrict__ tab_t,
+                                     const typename C::frag* __restrict__ tab_next,
+                                     M2TBuf<C>& tl, int& step, int row_base, int col_base,
+                                     f32x4 (&acc)[C::BR][C::BC]) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll 1
+  for (int r = 0; r < 32; ++r) {
+    const int cur = step & 1;
+    if (r + 1 < 32) m2f_issue_T<C>(tab_t, r + 1, (void*)&tl[cur ^ 1][0][0]);
+    else if (tab_next != nullptr) m2f_issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+    typename C::frag Tc[2][M2_FCH][C::NB];
+#pragma unroll
+    for (int m = 0; m < 2; ++m)
+#pragma unroll
+      for (int h = 0; h < M2_FCH; ++h)
+#pragma unroll
+        for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = tl[cur][(m * M2_FCH + h) * C::NB + q][lane];
+    if (r < M2_KC - 32) m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
+    else m2f_class<C, 1>(r, sh, Tc, row_base, col_base, acc);
+    frags_landed();
+    ++step;
+  }
+}
+
 template <class C>
 __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int group) {
   __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
@@ -126,13 +180,19 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int I0 = ty * C::TH, J0 = tx * C::TW;
   const int Hl = 2 * a.H, Wl = 2 * a.W;
-  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
-      a.in, Hl, Wl, 2 * I0 - 21, 2 * J0 - 21, sh, redf);
-  __syncthreads();
-  const int row_base = wr * 32 * C::BR;    // latent rows of this wave's block row 0
-  const int col_base = wc * 32 * C::BC;    // latent cols
   const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
+  const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
+  constexpr int64_t TSTRIDE = (int64_t)M2_FROWS * M2_FCH * 2 * 64;   // fragments per frame
+  __shared__ __align__(16) M2TBufDecl<C> tl;
+  int step = 0;
+  if constexpr (C::PFT == 2) m2f_issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
+  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
+      a.in, Hl, Wl, 2 * I0 - 21, 2 * J0 - 21, sh, redf);
+  if constexpr (C::PFT == 2) frags_landed();
+  else __syncthreads();
+  const int row_base = wr * 32 * C::BR;    // latent rows of this wave's block row 0
+  const int col_base = wc * 32 * C::BC;    // latent cols
   const int64_t N = (int64_t)a.H * a.W;
   double llp = 0.0;
   for (int t = t0; t < t1; ++t) {
@@ -142,51 +202,32 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
     for (int b = 0; b < C::BR; ++b)
 #pragma unroll
       for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
-    const typename C::frag* tab_t = reinterpret_cast<const typename C::frag*>(a.tab) +
-                                    (int64_t)t * M2_FROWS * M2_FCH * 2 * 64;
-    typename C::frag Tc[2][M2_FCH][C::NB], Tn[2][M2_FCH][C::NB];
-    m2f_load_T<C>(Tc, tab_t, 0);
-    for (int r = 0; r < 32; ++r) {
-      if (r + 1 < 32) m2f_load_T<C>(Tn, tab_t, r + 1);
-      if (r < M2_KC - 32) m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
-      else m2f_class<C, 1>(r, sh, Tc, row_base, col_base, acc);
+    const typename C::frag* tab_t = tab + t * TSTRIDE;
+    if constexpr (C::PFT == 2) {
+      m2f_frame_lds<C>(sh, tab_t, t + 1 < t1 ? tab_t + TSTRIDE : nullptr, tl, step, row_base,
+                       col_base, acc);
+    } else {
+      typename C::frag Tc[2][M2_FCH][C::NB], Tn[2][M2_FCH][C::NB];
+      m2f_load_T<C>(Tc, tab_t, 0);
+      for (int r = 0; r < 32; ++r) {
+        if (r + 1 < 32) m2f_load_T<C>(Tn, tab_t, r + 1);
+        if (r < M2_KC - 32) m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
+        else m2f_class<C, 1>(r, sh, Tc, row_base, col_base, acc);
 #pragma unroll
-      for (int m = 0; m < 2; ++m)
+        for (int m = 0; m < 2; ++m)
 #pragma unroll
-        for (int h = 0; h < M2_FCH; ++h)
+          for (int h = 0; h < M2_FCH; ++h)
 #pragma unroll
-          for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = Tn[m][h][q];
+            for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = Tn[m][h][q];
+      }
     }
     const int unscale =
         C::P::SCALED ? -(sx + m2_table_exponents(a, M2_FWD_FRAME_BYTES)[t]) : 0;
     const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
-    const float* yt = a.y ? a.y + (int64_t)t * N : nullptr;
+    const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;
     float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
-#pragma unroll
-    for (int b = 0; b < C::BR; ++b)
-#pragma unroll
-      for (int q = 0; q < C::BC; ++q) {
-        const int J = J0 + wc * 16 * C::BC + 16 * q + (lane & 15);
-        const int Ib = I0 + wr * 16 * C::BR + 16 * b + 4 * (lane >> 4);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int I = Ib + v;
-          if (I < a.H && J < a.W) {
-            const int off = I * a.W + J;
-            const float m = C::P::SCALED ? ldexpf(acc[b][q][v], unscale) : acc[b][q][v];
-            if (ut == nullptr) {
-              ot[off] = m;
-            } else {
-              const float uu = ut[off];
-              if (ot) ot[off] = uu * m;
-              if (a.part != nullptr && uu > 0.f) {
-                const double d = (double)yt[off] - (double)m;
-                llp += (double)uu * d * d;
-              }
-            }
-          }
-        }
-      }
+    llp += forward_epilogue<C::BR, C::BC>(
+        acc, unscale, BlockPos{I0 + wr * 16 * C::BR, J0 + wc * 16 * C::BC, 1}, a.H, a.W, ut, yt, ot);
   }
   if (a.part != nullptr) {
     const double s = block_sum<C::NT>(llp, red);
@@ -197,12 +238,13 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
 // ---------------------------------------------------------------------------
 // adjoint, sr = 2
 // ---------------------------------------------------------------------------
-template <int PREC_, int BR_, int BC_, int WR_, int WC_>
+template <int PREC_, int BR_, int BC_, int WR_, int WC_, int PFT_>
 struct M2A {
   using P = Prec<PREC_>;
   using frag = typename P::frag;
-  static constexpr int PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int PREC = PREC_, BR = BR_, BC = BC_, WR = WR_, WC = WC_, PFT = PFT_;
   static constexpr int NS = P::NP, NA = P::NA, NB = P::NB;
+  static constexpr int NTF = 2 * 2 * NB;        // Toeplitz fragments of one class
   static constexpr int NW = WR * WC, NT = 64 * NW;
   static constexpr int THL = 32 * BR * WR, TWL = 16 * BC * WC;     // latent pixels
   // frame rows staged: THL/2 + 22 are read; the margin keeps every fragment
@@ -299,6 +341,48 @@ __device__ inline void m2a_classes(const unsigned short (*sh)[C::ROWS * C::PITCH
   }
 }
 
+// Adjoint class r: buffer fragment f = (q, m, s) is table fragment
+// (q AROWS + alpha) 2 + s with alpha = r - q + 16 m (alpha = -1 -> the zero row).
+template <class C>
+__device__ inline void m2a_issue_T(const typename C::frag* __restrict__ tab_t, int r, void* dst) {
+  stage_frags<C::NTF, C::NW>(
+      tab_t,
+      [r](int f) {
+        const int s = f % C::NB, m = (f / C::NB) % 2, q = f / (2 * C::NB);
+        int al = r - q + 16 * m;
+        al = al < 0 ? M2_AROWS - 1 : al;
+        return (q * M2_AROWS + al) * 2 + s;
+      },
+      dst);
+}
+
+// Adjoint classes R .. 15 with LDS-staged fragments (class R in buffer
+// step & 1 on entry).
+template <class C, int R>
+__device__ inline void m2a_classes_lds(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                       const typename C::frag* __restrict__ tab_t,
+                                       const typename C::frag* __restrict__ tab_next,
+                                       M2TBuf<C>& tl, int& step, int row_base, int col_base,
+                                       f32x4 (&acc)[2][C::BR][C::BC]) {
+  if constexpr (R < 16) {
+    const int lane = threadIdx.x & 63;
+    const int cur = step & 1;
+    if constexpr (R + 1 < 16) m2a_issue_T<C>(tab_t, R + 1, (void*)&tl[cur ^ 1][0][0]);
+    else if (tab_next != nullptr) m2a_issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+    typename C::frag Tc[2][2][C::NB];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int s = 0; s < C::NB; ++s) Tc[q][m][s] = tl[cur][(q * 2 + m) * C::NB + s][lane];
+    m2a_class<C, R>(sh, Tc, row_base, col_base, acc);
+    frags_landed();
+    ++step;
+    m2a_classes_lds<C, R + 1>(sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+  }
+}
+
 template <class C>
 __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int group) {
   __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
@@ -325,16 +409,22 @@ __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int g
 
   const int t0 = group * a.fpg;
   const int t1 = min(a.n, t0 + a.fpg);
+  const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
+  constexpr int64_t TSTRIDE = (int64_t)2 * M2_AROWS * 2 * 64;   // fragments per frame
+  __shared__ __align__(16) M2TBufDecl<C> tl;
+  int step = 0;
+  if constexpr (C::PFT == 2) m2a_issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
     const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
         a.in + (int64_t)t * Nf, Hf, Wf, K0 / 2 - 11, L0 / 2 - 11, sh, redf);
-    __syncthreads();
-    const typename C::frag* tab_t =
-        reinterpret_cast<const typename C::frag*>(a.tab) + (int64_t)t * 2 * M2_AROWS * 2 * 64;
+    if constexpr (C::PFT == 2) frags_landed();
+    else __syncthreads();
+    const typename C::frag* tab_t = tab + t * TSTRIDE;
+    const typename C::frag* tab_next = t + 1 < t1 ? tab_t + TSTRIDE : nullptr;
     // classes r = 0..15 (fragment rows r + 16 rho) cover every (parity, tap) once
     typename C::frag Tc[2][2][C::NB];
-    m2a_load_T<C>(Tc, tab_t, 0);
+    if constexpr (C::PFT != 2) m2a_load_T<C>(Tc, tab_t, 0);
     if constexpr (C::P::SCALED) {
       // per-frame accumulators, added to the total with both scales removed
       f32x4 accf[2][C::BR][C::BC];
@@ -344,7 +434,10 @@ __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int g
         for (int b = 0; b < C::BR; ++b)
 #pragma unroll
           for (int c2 = 0; c2 < C::BC; ++c2) accf[q][b][c2] = f32x4{0.f, 0.f, 0.f, 0.f};
-      m2a_classes<C, 0>(sh, tab_t, Tc, row_base, col_base, accf);
+      if constexpr (C::PFT == 2)
+        m2a_classes_lds<C, 0>(sh, tab_t, tab_next, tl, step, row_base, col_base, accf);
+      else
+        m2a_classes<C, 0>(sh, tab_t, Tc, row_base, col_base, accf);
       const int unscale = -(sr_t + m2_table_exponents(a, M2_ADJ_FRAME_BYTES)[t]);
 #pragma unroll
       for (int q = 0; q < 2; ++q)
@@ -356,38 +449,21 @@ __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int g
             for (int v = 0; v < 4; ++v) acc[q][b][c2][v] += ldexpf(accf[q][b][c2][v], unscale);
     } else {
       (void)sr_t;
-      m2a_classes<C, 0>(sh, tab_t, Tc, row_base, col_base, acc);
+      if constexpr (C::PFT == 2)
+        m2a_classes_lds<C, 0>(sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+      else
+        m2a_classes<C, 0>(sh, tab_t, Tc, row_base, col_base, acc);
     }
   }
 
   double dsq = 0.0, xsq = 0.0;
   float* pl = a.fused ? nullptr : a.plane + (int64_t)group * Nl;
+  // output rows of parity q: K0 + 2 (16 b + 4 (lane / 16) + v) + q
 #pragma unroll
   for (int q = 0; q < 2; ++q)
-#pragma unroll
-    for (int b = 0; b < C::BR; ++b)
-#pragma unroll
-      for (int c2 = 0; c2 < C::BC; ++c2) {
-        const int l = L0 + wc * 16 * C::BC + 16 * c2 + (lane & 15);
-        const int ib = wr * 16 * C::BR + 16 * b + 4 * (lane >> 4);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const int k = K0 + 2 * (ib + v) + q;
-          if (k < a.H && l < a.W) {
-            const int off = k * a.W + l;
-            if (a.fused) {
-              const float xo = a.x[off];
-              const float xn = mf_update_value(xo, a.B[off], acc[q][b][c2][v]);
-              a.x[off] = xn;
-              const double d = (double)xn - (double)xo;
-              dsq += d * d;
-              xsq += (double)xo * (double)xo;
-            } else {
-              pl[off] = acc[q][b][c2][v];
-            }
-          }
-        }
-      }
+    adjoint_epilogue<C::BR, C::BC>(acc[q],
+                                   BlockPos{K0 + 2 * wr * 16 * C::BR + q, L0 + wc * 16 * C::BC, 2},
+                                   a.H, a.W, a.fused, a.x, a.B, pl, dsq, xsq);
   if (a.fused && a.part != nullptr) {
     const double s1 = block_sum<C::NT>(dsq, red);
     __syncthreads();
@@ -529,12 +605,14 @@ namespace {
 template <int PREC>
 hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
                    const MfmaLaunch* d, const int4* it, int n, hipStream_t s) {
-  using F0 = M2F<PREC, 2, 2, 2, 2>;
-  using F1 = M2F<PREC, 2, 1, 2, 4>;
-  using F2 = M2F<PREC, 1, 2, 4, 2>;
-  using A0 = M2A<PREC, 2, 2, 2, 4>;
-  using A1 = M2A<PREC, 4, 2, 1, 4>;
-  using A2 = M2A<PREC, 2, 4, 2, 2>;
+  // Toeplitz fragments staged in LDS for the one-plane binary16 image
+  constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
+  using F0 = M2F<PREC, 2, 2, 2, 2, PFT>;
+  using F1 = M2F<PREC, 2, 1, 2, 4, PFT>;
+  using F2 = M2F<PREC, 1, 2, 4, 2, PFT>;
+  using A0 = M2A<PREC, 2, 2, 2, 4, PFT>;
+  using A1 = M2A<PREC, 4, 2, 1, 4, PFT>;
+  using A2 = M2A<PREC, 2, 4, 2, 2, PFT>;
   static_assert(F0::TH == M2_FTILE && F0::TW == M2_FTILE && F1::TH == M2_FTILE &&
                 F1::TW == M2_FTILE && F2::TH == M2_FTILE && F2::TW == M2_FTILE, "fwd tile");
   static_assert(A0::THL == M2_ATILE && A0::TWL == M2_ATILE && A1::THL == M2_ATILE &&

@@ -115,6 +115,30 @@ __device__ inline unsigned short table_part(float gv, int s) {
   return s == 0 ? hi : lo;
 }
 
+// Start copying NTF Toeplitz fragments (64 lanes x 16 bytes each) of one
+// frame's table into an LDS buffer: buffer fragment f comes from table
+// fragment idx(f).  The NW waves of the workgroup share the fragments round
+// robin; each lane moves its own 16 bytes with global_load_lds_dwordx4, whose
+// destination is the wave-uniform base plus 16 bytes per lane (the fragment's
+// lane order).  Completion: s_waitcnt in each wave, then a barrier.
+template <int NTF, int NW, class Frag, class Idx>
+__device__ inline void stage_frags(const Frag* __restrict__ tab_t, Idx idx, void* dst_v) {
+  Frag* dst = static_cast<Frag*>(dst_v);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int f = w; f < NTF; f += NW) {
+    const Frag* src = tab_t + idx(f) * 64 + lane;
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src),
+                                     (__attribute__((address_space(3))) void*)(dst + f * 64), 16,
+                                     0, 0);
+  }
+}
+
+// Wait for this wave's fragment copies, then for every wave of the workgroup.
+__device__ inline void frags_landed() {
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+}
+
 __device__ inline float wave_max(float v) {
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
@@ -196,6 +220,130 @@ __device__ inline float mf_update_value(float xo, float Bv, float Dn) {
   if (Dn == 0.f) return xo;
   const float q = fmaxf(Bv, 0.f) / Dn;
   return xo * q;
+}
+
+// Output position of accumulator element (b, q, v) of a wave whose block
+// (0, 0) starts at row kb, column lb; rows of the blocks are rs apart (2 for the
+// parity-split outputs of the sr = 2 adjoint).
+struct BlockPos {
+  int kb, lb, rs;
+  __device__ int row(int b, int v) const {
+    return kb + rs * (16 * b + 4 * ((threadIdx.x & 63) >> 4) + v);
+  }
+  __device__ int col(int q) const { return lb + 16 * q + (threadIdx.x & 15); }
+};
+
+// Forward epilogue of one frame: out = u * m (m = F_t x, unscaled by 2^unscale)
+// or out = m when u is NULL, plus the FP64 partial of u (y - m)^2 when y is
+// given (WITH_Y).  Every load is issued before any store (addresses clamped
+// into the image; clamped values are never used), so one wait covers them all.
+template <int BR, int BC, bool WITH_Y>
+__device__ inline double forward_epilogue_w(const f32x4 (&acc)[BR][BC], int unscale,
+                                            const BlockPos& P, int H, int W,
+                                            const float* __restrict__ ut,
+                                            const float* __restrict__ yt,
+                                            float* __restrict__ ot) {
+  float uu[BR][BC][4], yy[BR][BC][4];
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int off = min(P.row(b, v), H - 1) * W + min(P.col(q), W - 1);
+        uu[b][q][v] = ut[off];
+        if constexpr (WITH_Y) yy[b][q][v] = yt[off];
+      }
+  double llp = 0.0;
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = P.row(b, v), l = P.col(q);
+        if (k < H && l < W) {
+          const float m = ldexpf(acc[b][q][v], unscale);
+          const float u = uu[b][q][v];
+          if (ot) ot[k * W + l] = u * m;
+          if constexpr (WITH_Y) {
+            if (u > 0.f) {
+              const double d = (double)yy[b][q][v] - (double)m;
+              llp += (double)u * d * d;
+            }
+          }
+        }
+      }
+  return llp;
+}
+
+template <int BR, int BC>
+__device__ inline double forward_epilogue(const f32x4 (&acc)[BR][BC], int unscale,
+                                          const BlockPos& P, int H, int W,
+                                          const float* __restrict__ ut,
+                                          const float* __restrict__ yt, float* __restrict__ ot) {
+  if (ut == nullptr) {
+#pragma unroll
+    for (int b = 0; b < BR; ++b)
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = P.row(b, v), l = P.col(q);
+          if (k < H && l < W) ot[k * W + l] = ldexpf(acc[b][q][v], unscale);
+        }
+    return 0.0;
+  }
+  return yt ? forward_epilogue_w<BR, BC, true>(acc, unscale, P, H, W, ut, yt, ot)
+            : forward_epilogue_w<BR, BC, false>(acc, unscale, P, H, W, ut, yt, ot);
+}
+
+// Adjoint epilogue: Dn = acc.  Fused update of Eq. (2) (x <- x max(B,0)/Dn,
+// FP64 partials of |x_new - x|^2 and |x|^2) or a store into the partial plane.
+// Loads first, as in forward_epilogue.
+template <int BR, int BC>
+__device__ inline void adjoint_epilogue(const f32x4 (&acc)[BR][BC], const BlockPos& P, int H,
+                                        int W, bool fused, float* __restrict__ x,
+                                        const float* __restrict__ B, float* __restrict__ plane,
+                                        double& dsq, double& xsq) {
+  if (!fused) {
+#pragma unroll
+    for (int b = 0; b < BR; ++b)
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = P.row(b, v), l = P.col(q);
+          if (k < H && l < W) plane[k * W + l] = acc[b][q][v];
+        }
+    return;
+  }
+  float xo[BR][BC][4], bv[BR][BC][4];
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int off = min(P.row(b, v), H - 1) * W + min(P.col(q), W - 1);
+        xo[b][q][v] = x[off];
+        bv[b][q][v] = B[off];
+      }
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = P.row(b, v), l = P.col(q);
+        if (k < H && l < W) {
+          const float xn = mf_update_value(xo[b][q][v], bv[b][q][v], acc[b][q][v]);
+          x[k * W + l] = xn;
+          const double d = (double)xn - (double)xo[b][q][v];
+          dsq += d * d;
+          xsq += (double)xo[b][q][v] * (double)xo[b][q][v];
+        }
+      }
 }
 
 }  // namespace em
