@@ -7,14 +7,15 @@ weighting, adjoint correlation, sum over frames and the multiplicative update.
 Inputs are synthetic, seeded, and resident in HBM before timing starts.
 
 Default: the HSC-shaped workload (33 frames of 4096^2, 43x43 PSFs) timed in
-the BF16 hi+lo split matrix-core form (the reported value) and in plain FP32
-on the same data, with sampled full-size pixels checked against the FP64
-oracle.  --workload c5 runs the serving stream instead.
+the FP16 split matrix-core form (binary16 image with a power-of-two tile scale
+times a binary16 hi+lo PSF; the reported value), in the BF16 hi+lo split form
+and in plain FP32 on the same data, with sampled full-size pixels of every form
+checked against the FP64 oracle.  --workload c5 runs the serving stream instead.
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c3]
-                    [--precision auto|fp32|bf16split|bf16] [--no-cpu-baseline]
+                    [--precision auto|fp32|fp16split|bf16split|bf16] [--no-cpu-baseline]
 """
 from __future__ import annotations
 
@@ -230,7 +231,7 @@ def serving_bench(args):
     fpix_iters = [j.n * j.frame_side ** 2 * j.n_iter for j in jobs]
 
     def problem(j, mixed):
-        prec = em.BF16_SPLIT if mixed else em.FP32
+        prec = prec_code(em, args.serve_precision) if mixed else em.FP32
         return em.Problem.make(j.n, j.frame_side, j.frame_side, 43, sr=j.sr, precision=prec)
 
     budget = int(args.serve_budget_gib * (1 << 30))
@@ -302,7 +303,7 @@ def serving_bench(args):
             "arrival_rate_jobs_per_s": round(rate, 3),
             "p50_latency_ms": round(float(p50) * 1e3, 1),
             "p99_latency_ms": round(float(p99) * 1e3, 1),
-            "mixed_precision": "bf16 hi+lo split (matrix cores) for every job",
+            "mixed_precision": f"{args.serve_precision} (matrix cores) for every job",
             "fp32_one_at_a_time": {
                 "capacity_jobs_per_s": round(base_cap, 3),
                 "frame_mpix_per_s": round(total_fpix / sum(svc) / 1e6, 1),
@@ -329,6 +330,8 @@ def main() -> int:
     ap.add_argument("--jobs", type=int, default=200, help="c5: jobs in the stream")
     ap.add_argument("--slots", type=int, default=16, help="c5: server slots")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="c5: HBM budget")
+    ap.add_argument("--serve-precision", default="fp16split", choices=["fp16split", "bf16split"],
+                    help="c5: matrix-core form of the served jobs")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -364,7 +367,7 @@ def main() -> int:
     if args.workload == "c5":
         r = serving_bench(args)
         out.update({"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
-                    "dtype": DTYPES["bf16split"],
+                    "dtype": DTYPES[args.serve_precision],
                     "config": {"workload": WORKLOADS["c5"], "serving": r["serving"]}})
         print(json.dumps(out), flush=True)
         return 0
@@ -377,7 +380,7 @@ def main() -> int:
     stream = torch.cuda.Stream(dev)
 
     if args.precision == "auto":
-        forms = ["bf16split", "fp16split", "fp32"]
+        forms = ["fp16split", "bf16split", "fp32"]
     else:
         forms = [args.precision]
     res = {}

@@ -152,7 +152,10 @@ Plan make_serving_plan(const Geometry& g) {
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
   if (uses_mfma(g)) {
-    pl.fwd_variant = g.sr == 1 ? 1 : 0;
+    // the variants em_autotune picks on the large workloads (33 x 4096^2 sr = 1,
+    // 16 x 2048^2 sr = 2) for each encoding
+    const bool f16 = g.precision == EM_FP16_SPLIT;
+    pl.fwd_variant = g.sr == 1 ? (f16 ? 1 : 0) : (f16 ? 2 : 0);
     pl.adj_variant = g.sr == 1 ? 2 : 0;
   }
   return pl;
