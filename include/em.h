@@ -220,6 +220,27 @@ int em_forward_op(const em_problem* p, const float* psf, const float* x, float* 
 int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* s,
                   void* workspace, size_t ws_bytes, void* stream);
 
+/*
+ * Up-sampled exposures for the super-resolution run the paper describes after
+ * Eq. (4) (arXiv:2302.05804, Sec. 2): the super-resolved PSFs h and up-sampled
+ * exposures y^D take the place of f and y in the update of Eq. (2), with no
+ * down-sampling operator; the job is then an ordinary sr = 1 problem on the
+ * fine grid (frame_h = factor * the exposures' rows, PSFs h).  The paper does
+ * not say how y is up-sampled; each frame pixel is replicated into a
+ * factor x factor block of fine pixels that share its flux:
+ *     y_up[t][f i + p][f j + q] = y[t][i][j] / f^2,
+ *     v_up[t][f i + p][f j + q] = v[t][i][j] / f^4   (variance of y / f^2),
+ * binary32 quotients, so masked pixels (v = +inf) stay masked.
+ *   y, v: device n x frame_h x frame_w (caller-owned, read only);
+ *   y_up, v_up: device n x (factor frame_h) x (factor frame_w), written.
+ * factor: 2, 3 or 4.  EM_EINVAL for NULL pointers, buffers that do not fit in
+ * their device allocation, non-positive sizes or another factor (a buffer
+ * carved out of a larger allocation is checked against that allocation).  Asynchronous on `stream` (hipStream_t as void*,
+ * NULL = default stream); allocates nothing.
+ */
+int em_upsample(int32_t n_frames, int32_t frame_h, int32_t frame_w, int32_t factor,
+                const float* y, const float* v, float* y_up, float* v_up, void* stream);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of deconvolution jobs on one GPU.
  *

@@ -15,7 +15,9 @@ arXiv:2302.05804, Sec. 2):
 * ``loglik``   -- the Gaussian log-likelihood implied by Eq. (1);
 * ``run``      -- k iterations of the multiplicative update of Eq. (2);
 * ``step_at``  -- one iteration evaluated only at chosen latent pixels;
-* ``flat_x0``  -- the flat strictly-positive starting guess.
+* ``flat_x0``  -- the flat strictly-positive starting guess;
+* ``upsample`` -- the up-sampled exposures of the super-resolution run the
+  paper describes after Eq. (4) (fine grid, super-resolved PSFs, no D).
 
 The readings taken where the paper is silent (weight placement, clamp of a
 negative numerator, 0/0 guards, boundary, downsampling kernel) are listed in
@@ -78,6 +80,8 @@ def _load():
     lib.em_oracle_loglik.argtypes = [I, I, I, I, I, P, P, P, P, P]
     lib.em_oracle_run.restype = I
     lib.em_oracle_run.argtypes = [I, I, I, I, I, I, P, P, P, P, I, P, P]
+    lib.em_oracle_upsample.restype = I
+    lib.em_oracle_upsample.argtypes = [I, I, I, I, P, P, P, P]
     lib.em_oracle_step_at.restype = I
     lib.em_oracle_step_at.argtypes = [I, I, I, I, I, P, P, P, P, I, P, P, P, P, P]
     _lib = lib
@@ -144,6 +148,21 @@ def weights(y, v):
     yh = np.empty(y.shape, np.float64)
     bad = lib.em_oracle_weights(y.size, _p(y), _p(v), _p(u), _p(yh))
     return u, yh, int(bad)
+
+
+def upsample(y, v, factor: int = 2):
+    """(y^D, v^D): each frame pixel replicated into a D x D block, y / D^2 and
+    v / D^4 (binary32), the exposures of the super-resolution run of Sec. 2
+    (text after Eq. (4))."""
+    lib = _load()
+    y = _f32(y)
+    v = _f32(v)
+    n, hf, wf = y.shape
+    yd = np.empty((n, factor * hf, factor * wf), np.float32)
+    vd = np.empty_like(yd)
+    if lib.em_oracle_upsample(n, hf, wf, factor, _p(y), _p(v), _p(yd), _p(vd)) != 0:
+        raise ValueError("factor must be 2, 3 or 4")
+    return yd, vd
 
 
 def flat_x0(y, v, sr: int = 1) -> float:

@@ -34,6 +34,8 @@
  *  - Flat initial guess: mu = sum u y / sum u over all frames and pixels,
  *    x0 = max(mu, 1e-3) / sr^2.
  *  - Frames are summed in the order t = 0 .. n-1.
+ *  - The super-resolution run the paper describes after Eq. (4) (exposures
+ *    up-sampled to the fine grid, no D): em_oracle_upsample below.
  */
 #include <math.h>
 #include <stdint.h>
@@ -278,6 +280,34 @@ static void emo_update(long nl, const double* B, const double* Dn, double* x,
 /* ---------------------------------------------------------------------------
  * Public entry points (called through ctypes from the test-suite).
  * ------------------------------------------------------------------------- */
+
+/* ---------------------------------------------------------------------------
+ * Up-sampled exposures of the super-resolution run the paper describes after
+ * Eq. (4): the super-resolved PSFs h and up-sampled exposures y^D are used in
+ * the update of Eq. (2) in place of f and y (no operator D).  The paper does
+ * not say how y is up-sampled; the reading taken here replicates each frame
+ * pixel into a D x D block of fine pixels that share its flux:
+ *     y^D[t][D i + p][D j + q] = y[t][i][j] / D^2,
+ *     v^D[t][D i + p][D j + q] = v[t][i][j] / D^4     (the variance of y / D^2),
+ * with both quotients formed in binary32 (y and v are binary32 data).  A
+ * masked pixel (v = +inf) stays masked.  Returns -1 for D outside [2, 4].
+ * ------------------------------------------------------------------------- */
+int em_oracle_upsample(int n, int Hf, int Wf, int D, const float* y, const float* v, float* yD,
+                       float* vD)
+{
+    if (D < 2 || D > 4) return -1;
+    const int Hu = D * Hf, Wu = D * Wf;
+    const float d2 = (float)(D * D), d4 = (float)(D * D * D * D);
+    for (int t = 0; t < n; ++t)
+        for (int I = 0; I < Hu; ++I)
+            for (int J = 0; J < Wu; ++J) {
+                const long src = ((long)t * Hf + I / D) * Wf + J / D;
+                const long dst = ((long)t * Hu + I) * Wu + J;
+                yD[dst] = y[src] / d2;
+                vD[dst] = v[src] / d4;
+            }
+    return 0;
+}
 
 /* Flat initial guess (see header comment).  Returns -1 on invalid input. */
 double em_oracle_flat_x0(int n, int Hf, int Wf, int sr, const float* y, const float* v)

@@ -934,4 +934,22 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
   return EM_OK;
 }
 
+int em_upsample(int32_t n_frames, int32_t frame_h, int32_t frame_w, int32_t factor,
+                const float* y, const float* v, float* y_up, float* v_up, void* stream) {
+  if (n_frames < 1 || frame_h < 1 || frame_w < 1) return fail(EM_EINVAL, "sizes must be >= 1");
+  if (factor < 2 || factor > 4) return fail(EM_EINVAL, "factor must be 2, 3 or 4");
+  const int64_t nf = (int64_t)n_frames * frame_h * frame_w;
+  const int64_t nu = nf * factor * factor;
+  if ((int64_t)factor * frame_h * factor * frame_w >= ((int64_t)1 << 31))
+    return fail(EM_EINVAL, "up-sampled frame of 2^31 pixels or more");
+  int rc;
+  if ((rc = check_device_range(y, (size_t)nf * sizeof(float), "y"))) return rc;
+  if ((rc = check_device_range(v, (size_t)nf * sizeof(float), "v"))) return rc;
+  if ((rc = check_device_range(y_up, (size_t)nu * sizeof(float), "y_up"))) return rc;
+  if ((rc = check_device_range(v_up, (size_t)nu * sizeof(float), "v_up"))) return rc;
+  EM_HIP(launch_upsample(y, v, n_frames, frame_h, frame_w, factor, y_up, v_up,
+                         static_cast<hipStream_t>(stream)));
+  return EM_OK;
+}
+
 }  // extern "C"

@@ -6,6 +6,8 @@
 // These are HBM-bound passes: grid-stride loops with coalesced accesses.
 #include <math.h>
 
+#include <algorithm>
+
 #include "em_device.h"
 #include "em_internal.h"
 
@@ -283,6 +285,35 @@ __global__ __launch_bounds__(EW_NT) void copy_kernel(const float* src, float* ds
   const int64_t stride = (int64_t)gridDim.x * EW_NT;
   for (int64_t p = (int64_t)blockIdx.x * EW_NT + threadIdx.x; p < count; p += stride)
     dst[p] = src[p];
+}
+
+// Flux-sharing replication of frame pixels into factor x factor blocks (the
+// up-sampled exposures of the super-resolution run after Eq. (4)); one thread
+// per fine pixel, grid-stride.
+__global__ __launch_bounds__(256) void upsample_kernel(const float* __restrict__ y,
+                                                       const float* __restrict__ v, int64_t count,
+                                                       int Hf, int Wf, int f, float* __restrict__ yu,
+                                                       float* __restrict__ vu) {
+  const int Hu = f * Hf, Wu = f * Wf;
+  const float d2 = (float)(f * f), d4 = (float)(f * f * f * f);
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256) {
+    const int64_t t = i / ((int64_t)Hu * Wu);
+    const int64_t rem = i - t * Hu * Wu;
+    const int I = (int)(rem / Wu), J = (int)(rem - (int64_t)I * Wu);
+    const int64_t src = (t * Hf + I / f) * Wf + J / f;
+    yu[i] = y[src] / d2;
+    vu[i] = v[src] / d4;
+  }
+}
+
+hipError_t launch_upsample(const float* y, const float* v, int n, int Hf, int Wf, int f,
+                           float* yu, float* vu, hipStream_t s) {
+  const int64_t count = (int64_t)n * f * Hf * f * Wf;
+  const int blocks = (int)std::min<int64_t>(8192, (count + 255) / 256);
+  hipLaunchKernelGGL(upsample_kernel, dim3(blocks), dim3(256), 0, s, y, v, count, Hf, Wf, f, yu,
+                     vu);
+  return hipGetLastError();
 }
 
 hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t s) {

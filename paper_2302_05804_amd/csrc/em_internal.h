@@ -199,6 +199,8 @@ hipError_t launch_finalize_loglik(const double* part_ll, int n_ll, double* scala
                                   hipStream_t s);
 hipError_t launch_reset_counters(int* counters, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t s);
+hipError_t launch_upsample(const float* y, const float* v, int n, int Hf, int Wf, int f,
+                           float* yu, float* vu, hipStream_t s);
 
 }  // namespace em
 

@@ -92,6 +92,8 @@ _sig = {
     "em_destroy": (ctypes.c_int, [_P]),
     "em_forward_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "em_adjoint_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "em_upsample": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                   _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -274,6 +276,21 @@ def adjoint_op(p: Problem, psf, r, s=None, workspace=None, stream=None):
                               _dev_ptr(s, "s", p.n_frames * hl * wl),
                               _dev_ptr(ws, "workspace"), ws.numel(), sp), "em_adjoint_op")
     return s
+
+
+def upsample(y, v, factor: int = 2, stream=None):
+    """(y_up, v_up): the up-sampled exposures of the super-resolution run the
+    paper describes after Eq. (4) (each pixel replicated into a factor x factor
+    block, y / factor^2, v / factor^4); new device tensors."""
+    torch = _torch()
+    n, hf, wf = y.shape
+    yu = torch.empty((n, factor * hf, factor * wf), dtype=torch.float32, device=y.device)
+    vu = torch.empty_like(yu)
+    sp, _ = _stream_ptr(stream)
+    _check(_lib.em_upsample(int(n), int(hf), int(wf), int(factor), _dev_ptr(y, "y", n * hf * wf),
+                            _dev_ptr(v, "v", n * hf * wf), _dev_ptr(yu, "y_up"),
+                            _dev_ptr(vu, "v_up"), sp), "em_upsample")
+    return yu, vu
 
 
 def job_bytes(p: Problem) -> int:

@@ -413,3 +413,68 @@ def test_invalid_inputs_rejected():
     yb[0, 0, 0] = np.nan
     with pytest.raises(ValueError):
         oracle.run(yb, v, psf, x0, 1)
+
+
+# ---------------------------------------------------------------------------
+# The super-resolution run the paper describes after Eq. (4): exposures
+# up-sampled to the fine grid (reading: flux-sharing replication), plain EM
+# with the super-resolved PSFs, no D.
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("D", [2, 3, 4])
+def test_upsample_is_flux_sharing_replication(D):
+    rng = RNG(40 + D)
+    y = rng.normal(10, 30, (3, 5, 7)).astype(np.float32)
+    v = rng.uniform(1, 50, (3, 5, 7)).astype(np.float32)
+    v[1, 2, 3] = np.inf
+    y[1, 2, 3] = np.nan
+    yd, vd = oracle.upsample(y, v, D)
+    rep = lambda a: np.repeat(np.repeat(a, D, axis=1), D, axis=2)
+    assert np.array_equal(yd, rep(y) / np.float32(D * D), equal_nan=True)
+    assert np.array_equal(vd, rep(v) / np.float32(D ** 4))
+    assert np.isinf(vd[1, 2 * D:3 * D, 3 * D:4 * D]).all()
+    # the D x D block sums give the frame back (exactly for powers of two)
+    ok = np.isfinite(y)
+    bs = yd.astype(np.float64).reshape(3, 5, D, 7, D).sum(axis=(2, 4))
+    np.testing.assert_allclose(bs[ok], y[ok], rtol=0 if D in (2, 4) else 1e-6, atol=0)
+    with pytest.raises(ValueError):
+        oracle.upsample(y, v, 5)
+
+
+def test_upsampled_delta_psf_gives_scaled_weighted_mean():
+    """With a delta PSF on the fine grid one update gives, in every fine pixel,
+    the inverse-variance-weighted mean of the frames divided by D^2."""
+    D, n, H, W = 2, 4, 6, 5
+    rng = RNG(44)
+    y = rng.normal(20, 30, (n, H, W)).astype(np.float32)
+    v = rng.uniform(5, 50, (n, H, W)).astype(np.float32)
+    mk = rng.uniform(size=(n, H, W)) < 0.2
+    y[mk] = np.nan
+    v[mk] = np.inf
+    yd, vd = oracle.upsample(y, v, D)
+    h = np.ones((n, 1, 1), np.float32)
+    x0 = positive((D * H, D * W), 45)
+    u = np.where(mk, 0.0, 1.0 / v.astype(np.float64))
+    su = u.sum(0)
+    with np.errstate(invalid="ignore", divide="ignore"):
+        mean = (u * np.where(mk, 0.0, y.astype(np.float64))).sum(0) / su
+    coarse = np.where(su > 0, np.maximum(mean, 0.0) / (D * D), np.nan)
+    fine = np.repeat(np.repeat(coarse, D, 0), D, 1)
+    fine = np.where(np.isnan(fine), x0.astype(np.float64), fine)
+    x1 = oracle.run(yd, vd, h, x0, 1)
+    np.testing.assert_allclose(x1, fine, rtol=1e-12, atol=1e-300)
+
+
+def test_upsampled_run_ignores_variance_factor():
+    """The D^4 factor of v^D scales every weight by the same constant, which
+    leaves the iterates unchanged (P9); only the value of l moves."""
+    D = 2
+    y, v, _, _ = small_problem(8, 6, 3, 3, seed=46, mask=0.1)
+    hd = RNG(47).uniform(0.05, 1.0, (3, 7, 7)).astype(np.float32)
+    hd /= hd.sum(axis=(1, 2), keepdims=True)
+    yd, vd = oracle.upsample(y, v, D)
+    vr = np.repeat(np.repeat(v, D, axis=1), D, axis=2)
+    x0 = positive((16, 12), 48)
+    a = oracle.run(yd, vd, hd, x0, 6)
+    b = oracle.run(yd, vr, hd, x0, 6)
+    np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-12 * np.abs(a).max())
