@@ -17,7 +17,9 @@ arXiv:2302.05804, Sec. 2):
 * ``step_at``  -- one iteration evaluated only at chosen latent pixels;
 * ``flat_x0``  -- the flat strictly-positive starting guess;
 * ``upsample`` -- the up-sampled exposures of the super-resolution run the
-  paper describes after Eq. (4) (fine grid, super-resolved PSFs, no D).
+  paper describes after Eq. (4) (fine grid, super-resolved PSFs, no D);
+* ``psf_gauss`` / ``psf_objective`` / ``psf_gradient`` / ``psf_start`` /
+  ``psf_fit`` -- the super-resolved PSFs of Eq. (4), fitted by projected Adam.
 
 The readings taken where the paper is silent (weight placement, clamp of a
 negative numerator, 0/0 guards, boundary, downsampling kernel) are listed in
@@ -82,6 +84,17 @@ def _load():
     lib.em_oracle_run.argtypes = [I, I, I, I, I, I, P, P, P, P, I, P, P]
     lib.em_oracle_upsample.restype = I
     lib.em_oracle_upsample.argtypes = [I, I, I, I, P, P, P, P]
+    D = ctypes.c_double
+    lib.em_oracle_psf_gauss.restype = I
+    lib.em_oracle_psf_gauss.argtypes = [D, P]
+    lib.em_oracle_psf_objective.restype = I
+    lib.em_oracle_psf_objective.argtypes = [I, I, I, D, D, P, P, P, P]
+    lib.em_oracle_psf_gradient.restype = I
+    lib.em_oracle_psf_gradient.argtypes = [I, I, I, D, D, P, P, P]
+    lib.em_oracle_psf_start.restype = I
+    lib.em_oracle_psf_start.argtypes = [I, I, I, P, P]
+    lib.em_oracle_psf_fit.restype = I
+    lib.em_oracle_psf_fit.argtypes = [I, I, I, I, D, D, I, D, D, D, D, D, P, P, P, P]
     lib.em_oracle_step_at.restype = I
     lib.em_oracle_step_at.argtypes = [I, I, I, I, I, P, P, P, P, I, P, P, P, P, P]
     _lib = lib
@@ -252,3 +265,86 @@ def step_at(y, v, psf, x0, rows, cols, sr: int = 1):
     if rc:
         raise ValueError(f"oracle step_at failed ({rc})")
     return B, Dn, x1
+
+
+# ---------------------------------------------------------------------------
+# Super-resolved PSFs, Eq. (4) (readings in the header of em_oracle.c)
+# ---------------------------------------------------------------------------
+
+PSF_DEFAULTS = dict(lam=1e-2, steps=2000, lr=1e-2, decay=1e-2, beta1=0.9, beta2=0.999, eps=1e-7)
+
+
+def psf_gauss(sigma: float) -> np.ndarray:
+    """g of Eq. (4): isotropic Gaussian, std sigma fine pixels, radius ceil(4 sigma), unit sum."""
+    g = np.zeros(67 * 67)
+    k = _load().em_oracle_psf_gauss(float(sigma), _p(g))
+    if k < 0:
+        raise ValueError("sigma must be in [0, 8]")
+    return g[:k * k].reshape(k, k)
+
+
+def _psf_args(f, kh, factor):
+    f = _f32(f)
+    if f.ndim != 2 or f.shape[0] != f.shape[1] or f.shape[0] % 2 == 0 or kh % 2 == 0:
+        raise ValueError("f must be Kf x Kf with odd Kf; Kh odd")
+    return f, f.shape[0]
+
+
+def psf_objective(f, h, factor: int = 2, sigma=None, lam: float = PSF_DEFAULTS["lam"]):
+    """(objective of Eq. (4) at h, model D(h * g) on f's stamp) for one frame."""
+    h = _f64(h)
+    f, kf = _psf_args(f, h.shape[0], factor)
+    sigma = float(factor if sigma is None else sigma)
+    m = np.empty((kf, kf))
+    out = ctypes.c_double()
+    if _load().em_oracle_psf_objective(kf, h.shape[0], factor, sigma, float(lam), _p(f), _p(h),
+                                       _p(m), ctypes.byref(out)):
+        raise ValueError("bad Eq. (4) arguments")
+    return out.value, m
+
+
+def psf_gradient(f, h, factor: int = 2, sigma=None, lam: float = PSF_DEFAULTS["lam"]):
+    """Gradient of the objective of Eq. (4) with respect to h (Kh x Kh)."""
+    h = _f64(h)
+    f, kf = _psf_args(f, h.shape[0], factor)
+    sigma = float(factor if sigma is None else sigma)
+    g = np.empty_like(h)
+    if _load().em_oracle_psf_gradient(kf, h.shape[0], factor, sigma, float(lam), _p(f), _p(h), _p(g)):
+        raise ValueError("bad Eq. (4) arguments")
+    return g
+
+
+def psf_start(f, kh: int, factor: int = 2) -> np.ndarray:
+    """Adam's starting h: f replicated into factor x factor blocks / factor^2, >= 0, cropped."""
+    f, kf = _psf_args(f, kh, factor)
+    h = np.empty((kh, kh))
+    if _load().em_oracle_psf_start(kf, kh, factor, _p(f), _p(h)):
+        raise ValueError("bad Eq. (4) arguments")
+    return h
+
+
+def psf_fit(f, kh: int = 43, factor: int = 2, sigma=None, h0=None, **kw):
+    """Fit h_t of Eq. (4) for every frame of f (n x Kf x Kf) by projected Adam.
+
+    Keywords: lam, steps, lr (relative to max f_t), decay, beta1, beta2, eps
+    (defaults in PSF_DEFAULTS).  Returns (h n x Kh x Kh float64, objective n).
+    """
+    o = dict(PSF_DEFAULTS)
+    o.update(kw)
+    f = _f32(f)
+    if f.ndim == 2:
+        f = f[None]
+    n, kf = f.shape[0], f.shape[1]
+    if f.shape[2] != kf or kf % 2 == 0 or kh % 2 == 0:
+        raise ValueError("f must be n x Kf x Kf with odd Kf; Kh odd")
+    sigma = float(factor if sigma is None else sigma)
+    h = np.empty((n, kh, kh))
+    obj = np.empty(n)
+    h0a = None if h0 is None else _f32(h0).reshape(n, kh, kh).copy()
+    rc = _load().em_oracle_psf_fit(n, kf, kh, factor, sigma, float(o["lam"]), int(o["steps"]),
+                                   float(o["lr"]), float(o["decay"]), float(o["beta1"]),
+                                   float(o["beta2"]), float(o["eps"]), _p(f),
+                                   None if h0a is None else _p(h0a), _p(h), _p(obj))
+    if rc:
+        raise ValueError("bad Eq. (4) arguments")
+    return h, obj

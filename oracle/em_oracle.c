@@ -36,6 +36,8 @@
  *  - Frames are summed in the order t = 0 .. n-1.
  *  - The super-resolution run the paper describes after Eq. (4) (exposures
  *    up-sampled to the fine grid, no D): em_oracle_upsample below.
+ *  - The super-resolved PSFs of Eq. (4), fitted by projected Adam:
+ *    em_oracle_psf_* at the end of this file, with their own readings.
  */
 #include <math.h>
 #include <stdint.h>
@@ -450,5 +452,249 @@ int em_oracle_step_at(int n, int Hf, int Wf, int K, int sr,
         B_out[pt] = Bv; Dn_out[pt] = Dv; x1_out[pt] = xn;
     }
     free(xd); free(fd);
+    return 0;
+}
+
+/* ===========================================================================
+ * Super-resolved PSFs, Eq. (4): for each frame t,
+ *     h_t = argmin_{h >= 0}  sum_{I,J} ([D(h * g)]_{IJ} - f_t[I][J])^2
+ *                            + lambda * sum (grad h)^2,
+ * solved with Adam (Kingma & Ba, 2015, Algorithm 1), the solver the paper
+ * names.  Readings of the points the paper leaves open:
+ *  - Grids.  f is Kf x Kf on the frame grid (odd Kf, centre cf); h is Kh x Kh
+ *    on the fine grid (odd Kh, centre ch).  The data term runs over the D*Kf x
+ *    D*Kf fine stamp that D sums, block by block, onto f's stamp (coarse pixel
+ *    I covers fine rows D*I .. D*I+D-1, as the operator D of Eq. (3)).  h is
+ *    placed with its centre on fine pixel (D*cf, D*cf): a point source at
+ *    fine pixel (D*I, D*J) seen through h and D lands on coarse pixel (I, J),
+ *    the phase of D in Eq. (3).  h * g is a true convolution; the part of it
+ *    outside the fine stamp is not seen by the data term.
+ *  - g is an isotropic Gaussian whose standard deviation is sigma fine pixels
+ *    (the paper's width Delta; sigma = D by default), sampled at pixel
+ *    centres on a (2r+1)^2 stamp with r = ceil(4 sigma), and normalised to
+ *    unit sum.  sigma = 0 makes g the unit impulse.
+ *  - grad h: forward differences of h extended by zeros beyond its stamp, so
+ *    the penalty is lambda times the sum of (h[i+1][j]-h[i][j])^2 and
+ *    (h[i][j+1]-h[i][j])^2 over every pair of 4-neighbours with at least one
+ *    pixel on the stamp.
+ *  - h >= 0: each Adam step is followed by the projection max(h, 0).
+ *  - Step size: lr_k = lr * max(f_t) * decay^((k-1)/(S-1)) at step k of S
+ *    (an exponential schedule; a constant step leaves Adam circling the
+ *    minimiser at its own scale).  max(f_t) makes lr relative to the PSF's
+ *    scale.  beta1, beta2, eps as passed (0.9, 0.999, 1e-7 by default).
+ *  - Start: f replicated into D x D blocks of fine pixels sharing its value
+ *    (f/D^2, negative values set to 0), cropped to Kh x Kh about the anchor
+ *    (zero where the crop leaves the stamp), unless h0 is given.
+ * Everything below is evaluated from these definitions pixel by pixel.
+ * ========================================================================= */
+
+/* g of the header above; returns its side Kg (<= 2*33+1) and fills g[Kg*Kg]. */
+int em_oracle_psf_gauss(double sigma, double* g)
+{
+    if (!(sigma >= 0.0) || sigma > 8.0) return -1;
+    if (sigma == 0.0) { g[0] = 1.0; return 1; }
+    const int r = (int)ceil(4.0 * sigma), Kg = 2 * r + 1;
+    double s = 0.0;
+    for (int i = 0; i < Kg; ++i)
+        for (int j = 0; j < Kg; ++j) {
+            const double di = i - r, dj = j - r;
+            g[i * Kg + j] = exp(-(di * di + dj * dj) / (2.0 * sigma * sigma));
+            s += g[i * Kg + j];
+        }
+    for (int i = 0; i < Kg * Kg; ++i) g[i] /= s;
+    return Kg;
+}
+
+typedef struct {
+    int Kf, Kh, D, Kg, S, anchor;
+    double g[67 * 67];
+} psf_geom;
+
+static int psf_geom_init(psf_geom* G, int Kf, int Kh, int D, double sigma)
+{
+    if (Kf < 1 || Kh < 1 || Kf % 2 == 0 || Kh % 2 == 0 || D < 1 || D > 4) return -1;
+    G->Kf = Kf; G->Kh = Kh; G->D = D;
+    G->Kg = em_oracle_psf_gauss(sigma, G->g);
+    if (G->Kg < 0) return -1;
+    G->S = D * Kf;
+    G->anchor = D * ((Kf - 1) / 2);
+    return 0;
+}
+
+/* value of h at fine stamp pixel (p, q): h placed about the anchor, 0 elsewhere */
+static double psf_hfine(const psf_geom* G, const double* h, int p, int q)
+{
+    const int ch = (G->Kh - 1) / 2;
+    const int a = p - G->anchor + ch, b = q - G->anchor + ch;
+    if (a < 0 || a >= G->Kh || b < 0 || b >= G->Kh) return 0.0;
+    return h[a * G->Kh + b];
+}
+
+/* m = D(h * g) on f's stamp (Kf x Kf) */
+static void psf_model(const psf_geom* G, const double* h, double* m)
+{
+    const int cg = (G->Kg - 1) / 2;
+    for (int I = 0; I < G->Kf * G->Kf; ++I) m[I] = 0.0;
+    for (int p = 0; p < G->S; ++p)
+        for (int q = 0; q < G->S; ++q) {
+            double c = 0.0;
+            for (int i = 0; i < G->Kg; ++i)
+                for (int j = 0; j < G->Kg; ++j)
+                    c += G->g[i * G->Kg + j] * psf_hfine(G, h, p + cg - i, q + cg - j);
+            m[(p / G->D) * G->Kf + q / G->D] += c;
+        }
+}
+
+/* sum of squared forward differences of h extended by zeros */
+static double psf_penalty(const psf_geom* G, const double* h)
+{
+    const int K = G->Kh;
+    double s = 0.0;
+    for (int i = -1; i < K; ++i)
+        for (int j = -1; j < K; ++j) {
+            const double c = (i >= 0 && j >= 0) ? h[i * K + j] : 0.0;
+            if (j >= 0) {
+                const double dn = (i + 1 < K) ? h[(i + 1) * K + j] : 0.0;
+                if (i >= 0 || i + 1 < K) s += (dn - c) * (dn - c);
+            }
+            if (i >= 0) {
+                const double rt = (j + 1 < K) ? h[i * K + j + 1] : 0.0;
+                s += (rt - c) * (rt - c);
+            }
+        }
+    return s;
+}
+
+static double psf_objective(const psf_geom* G, const float* f, double lambda, const double* h,
+                            double* m)
+{
+    psf_model(G, h, m);
+    double s = 0.0;
+    for (int I = 0; I < G->Kf * G->Kf; ++I) {
+        const double r = m[I] - (double)f[I];
+        s += r * r;
+    }
+    return s + lambda * psf_penalty(G, h);
+}
+
+/* gradient of the objective with respect to h (Kh x Kh) */
+static void psf_gradient(const psf_geom* G, const float* f, double lambda, const double* h,
+                         double* m, double* grad)
+{
+    const int K = G->Kh, ch = (K - 1) / 2, cg = (G->Kg - 1) / 2;
+    psf_model(G, h, m);
+    for (int k = 0; k < K * K; ++k) grad[k] = 0.0;
+    /* data term: 2 sum_{p,q} rho[p/D][q/D] * d(h*g)[p][q] / dh[a][b],
+       (h*g)[p][q] = sum_{a,b} h[a][b] g[p + cg - (a - ch + anchor)][q + cg - (b - ch + anchor)] */
+    for (int p = 0; p < G->S; ++p)
+        for (int q = 0; q < G->S; ++q) {
+            const double rho = m[(p / G->D) * G->Kf + q / G->D] - (double)f[(p / G->D) * G->Kf + q / G->D];
+            for (int a = 0; a < K; ++a) {
+                const int i = p + cg - (a - ch + G->anchor);
+                if (i < 0 || i >= G->Kg) continue;
+                for (int b = 0; b < K; ++b) {
+                    const int j = q + cg - (b - ch + G->anchor);
+                    if (j < 0 || j >= G->Kg) continue;
+                    grad[a * K + b] += 2.0 * rho * G->g[i * G->Kg + j];
+                }
+            }
+        }
+    /* penalty: d/dh of lambda sum (differences)^2 = 2 lambda (4 h - sum of 4 neighbours) */
+    for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b) {
+            const double up = a > 0 ? h[(a - 1) * K + b] : 0.0;
+            const double dn = a + 1 < K ? h[(a + 1) * K + b] : 0.0;
+            const double lf = b > 0 ? h[a * K + b - 1] : 0.0;
+            const double rt = b + 1 < K ? h[a * K + b + 1] : 0.0;
+            grad[a * K + b] += 2.0 * lambda * (4.0 * h[a * K + b] - up - dn - lf - rt);
+        }
+}
+
+static void psf_start(const psf_geom* G, const float* f, double* h)
+{
+    const int K = G->Kh, ch = (K - 1) / 2;
+    for (int a = 0; a < K; ++a)
+        for (int b = 0; b < K; ++b) {
+            const int p = a - ch + G->anchor, q = b - ch + G->anchor;
+            double v = 0.0;
+            if (p >= 0 && p < G->S && q >= 0 && q < G->S) {
+                v = (double)f[(p / G->D) * G->Kf + q / G->D] / (double)(G->D * G->D);
+                if (v < 0.0) v = 0.0;
+            }
+            h[a * K + b] = v;
+        }
+}
+
+int em_oracle_psf_objective(int Kf, int Kh, int D, double sigma, double lambda, const float* f,
+                            const double* h, double* model, double* objective)
+{
+    static psf_geom G;
+    if (psf_geom_init(&G, Kf, Kh, D, sigma)) return -1;
+    double* m = (double*)malloc(sizeof(double) * Kf * Kf);
+    if (!m) return -2;
+    *objective = psf_objective(&G, f, lambda, h, m);
+    if (model) memcpy(model, m, sizeof(double) * Kf * Kf);
+    free(m);
+    return 0;
+}
+
+int em_oracle_psf_gradient(int Kf, int Kh, int D, double sigma, double lambda, const float* f,
+                           const double* h, double* grad)
+{
+    static psf_geom G;
+    if (psf_geom_init(&G, Kf, Kh, D, sigma)) return -1;
+    double* m = (double*)malloc(sizeof(double) * Kf * Kf);
+    if (!m) return -2;
+    psf_gradient(&G, f, lambda, h, m, grad);
+    free(m);
+    return 0;
+}
+
+int em_oracle_psf_start(int Kf, int Kh, int D, const float* f, double* h)
+{
+    static psf_geom G;
+    if (psf_geom_init(&G, Kf, Kh, D, 0.0)) return -1;
+    psf_start(&G, f, h);
+    return 0;
+}
+
+/* n independent fits of Eq. (4) by projected Adam (S steps each).  f: n x Kf x Kf
+ * (binary32 data); h0: n x Kh x Kh or NULL (start of the header); h: n x Kh x Kh
+ * result; objective: n values at the result, or NULL. */
+int em_oracle_psf_fit(int n, int Kf, int Kh, int D, double sigma, double lambda, int S,
+                      double lr, double decay, double beta1, double beta2, double eps,
+                      const float* f, const float* h0, double* h, double* objective)
+{
+    static psf_geom G;
+    if (psf_geom_init(&G, Kf, Kh, D, sigma) || n < 1 || S < 0) return -1;
+    const int K2 = Kh * Kh;
+    double* m = (double*)malloc(sizeof(double) * Kf * Kf);
+    double* gr = (double*)malloc(sizeof(double) * K2);
+    double* mo = (double*)malloc(sizeof(double) * K2);
+    double* vo = (double*)malloc(sizeof(double) * K2);
+    if (!m || !gr || !mo || !vo) { free(m); free(gr); free(mo); free(vo); return -2; }
+    for (int t = 0; t < n; ++t) {
+        const float* ft = f + (long)t * Kf * Kf;
+        double* ht = h + (long)t * K2;
+        if (h0) for (int k = 0; k < K2; ++k) ht[k] = (double)h0[(long)t * K2 + k];
+        else psf_start(&G, ft, ht);
+        double fmax = 0.0;
+        for (int I = 0; I < Kf * Kf; ++I) if ((double)ft[I] > fmax) fmax = (double)ft[I];
+        for (int k = 0; k < K2; ++k) { mo[k] = 0.0; vo[k] = 0.0; }
+        for (int k = 1; k <= S; ++k) {
+            psf_gradient(&G, ft, lambda, ht, m, gr);
+            const double lrk = lr * fmax * pow(decay, S > 1 ? (double)(k - 1) / (double)(S - 1) : 0.0);
+            const double c1 = 1.0 - pow(beta1, k), c2 = 1.0 - pow(beta2, k);
+            for (int q = 0; q < K2; ++q) {
+                mo[q] = beta1 * mo[q] + (1.0 - beta1) * gr[q];
+                vo[q] = beta2 * vo[q] + (1.0 - beta2) * gr[q] * gr[q];
+                const double step = lrk * (mo[q] / c1) / (sqrt(vo[q] / c2) + eps);
+                const double nh = ht[q] - step;
+                ht[q] = nh > 0.0 ? nh : 0.0;
+            }
+        }
+        if (objective) objective[t] = psf_objective(&G, ft, lambda, ht, m);
+    }
+    free(m); free(gr); free(mo); free(vo);
     return 0;
 }

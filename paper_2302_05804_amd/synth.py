@@ -291,6 +291,24 @@ def make_problem(config: str = "c1", replica: int = 0, seed: Optional[int] = Non
                    n_iter=int(rec["n_iter"]), seed=int(seed))
 
 
+def coarse_psfs(n: int, kf: int = 43, factor: int = 2, seed: int = 4100,
+                fwhm=(3.0, 6.0), ell: float = 0.3) -> np.ndarray:
+    """n frame-grid PSFs (kf x kf, float32) to be super-resolved by Eq. (4):
+    elliptical Moffat, FWHM ~ U(fwhm) frame pixels, beta ~ U(2.5, 4.5),
+    ellipticity ~ U(0, ell), random angle, centre offset ~ U[0, 1)^2 fine
+    pixels (U[0, 1/factor)^2 frame pixels), unit sum."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    out = np.empty((n, kf, kf), np.float32)
+    for t in range(n):
+        fw = rng.uniform(*fwhm)
+        beta = rng.uniform(2.5, 4.5)
+        e = rng.uniform(0.0, ell)
+        th = rng.uniform(0.0, math.pi)
+        dy, dx = rng.uniform(0.0, 1.0, 2) / factor
+        out[t] = moffat_psf(kf, fw, beta, e, th, dy, dx).astype(np.float32)
+    return out
+
+
 def positive_start(shape, level: float, seed: int, spread: float = 0.5) -> np.ndarray:
     """A strictly positive, non-flat starting guess: level * U(1-spread, 1+spread)."""
     rng = np.random.Generator(np.random.PCG64(seed))
