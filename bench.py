@@ -11,7 +11,8 @@ the FP16 split matrix-core form (binary16 image with a power-of-two tile scale
 times a binary16 hi+lo PSF; the reported value), in the BF16 hi+lo split form
 and in plain FP32 on the same data.  --workload c4 is the super-resolution
 model of Eq. (3), c4y the super-resolution run described after Eq. (4)
-(up-sampled exposures), c5 the serving stream.  The full-size parity of the
+(up-sampled exposures), psf the fit of the super-resolved PSFs of Eq. (4)
+for c4's job, c5 the serving stream.  The full-size parity of the
 same launches against the oracle is a GPU test (tests/test_gpu_fullsize.py).
 
 Prints ONE JSON line on stdout; progress goes to stderr.
@@ -45,6 +46,9 @@ WORKLOADS = {
     "c4y": "c4y: the super-resolution run described after Eq. (4): c4's 16 frames of 2048x2048 "
            "up-sampled x2 on the GPU (flux-sharing replication) to 4096x4096, 43x43 "
            "super-resolved PSFs, plain EM on the fine grid (no down-sampling operator)",
+    "psf": "psf: the super-resolved PSFs of Eq. (4) for c4's job: 16 frame-grid PSFs of 43x43 "
+           "(Moffat, sub-pixel offsets) fitted to 43x43 fine-grid PSFs, Delta 2, Gaussian g of "
+           "sigma 2, lambda 1e-2, 2000 projected-Adam steps, all frames in one launch",
     "c5": "c5: serving stream, Poisson arrivals, frame tiles 256-2048 px (log-uniform), "
           "4-33 frames, sr 1 or 2, 43x43 Moffat PSFs, 50-200 iterations per job",
 }
@@ -185,6 +189,80 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream):
                      "frac": round(achieved / peak, 4),
                      "traffic": recorded_traffic(f"{name}-{prob.name}-{prec_name}")},
     }
+
+
+# ---------------------------------------------------------------------------
+# super-resolved PSFs (Eq. (4))
+# ---------------------------------------------------------------------------
+
+PSF_JOB = dict(n=16, kf=43, kh=43, factor=2, seed=4100)
+
+
+def psf_flops(p) -> float:
+    """Algorithmic flops of one fit: per frame and Adam step the four products
+    T = h A^T, A T, rho A, A^T U (2 flops per multiply-add)."""
+    kf, kh = p.psf_k, p.out_k
+    return 4.0 * kf * kh * (kf + kh) * p.n_frames * p.n_steps
+
+
+def time_psf_fit(em, synth, dev, stream, steps, warmup):
+    """Time em_psf_fit on the c4 job's PSFs; returns (ms per fit, problem)."""
+    import torch
+    J = PSF_JOB
+    f = torch.from_numpy(synth.coarse_psfs(J["n"], J["kf"], J["factor"], seed=J["seed"])).to(dev)
+    p = em.psf_problem(J["n"], J["kf"], J["kh"], J["factor"])
+    h = torch.empty((J["n"], J["kh"], J["kh"]), dtype=torch.float32, device=dev)
+    obj = torch.empty(J["n"], dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+    for _ in range(warmup):
+        em.psf_fit_into(p, f, h, obj, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(steps):
+        em.psf_fit_into(p, f, h, obj, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ok = bool(torch.isfinite(h).all().item()) and bool((h >= 0).all().item())
+    return e0.elapsed_time(e1) / steps, p, ok, f.cpu().numpy()
+
+
+def psf_bench(args, em, synth, dev, stream, out):
+    ms, p, ok, f = time_psf_fit(em, synth, dev, stream, args.steps, args.warmup)
+    fits_per_s = 1e3 / ms
+    achieved = psf_flops(p) / (ms / 1e3) / 1e12
+    peak = PEAKS_TFLOPS["fp32"]
+    log(f"psf: {ms:.3f} ms per fit of {p.n_frames} PSFs ({p.n_steps} Adam steps), "
+        f"{achieved:.3f} TFLOP/s")
+    out.update({
+        "metric": "Eq. (4) frame-PSF Adam steps/s", "unit": "frame-PSF Adam steps/s",
+        "value": round(p.n_frames * p.n_steps * fits_per_s, 1), "ms_per_step": round(ms, 4),
+        "dtype": "f32 (binary64 objective)",
+        "config": {"workload": WORKLOADS["psf"], "frames": p.n_frames, "psf_k": p.psf_k,
+                   "out_k": p.out_k, "factor": p.factor, "sigma": p.sigma,
+                   "lambda": round(float(p.lambda_), 6), "adam_steps": p.n_steps,
+                   "step": "one fit of every frame's PSF (one launch)",
+                   "result_finite_nonnegative": ok},
+        "roofline": {"bound": "alu", "kernel": "psf_fit", "achieved": round(achieved, 4),
+                     "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
+                     "workgroups": p.n_frames,
+                     "frac_of_occupied_cus": round(achieved / (peak * p.n_frames / 256.0), 4),
+                     "traffic": None},
+    })
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        steps = 2000
+        t0 = time.perf_counter()
+        oracle.psf_fit(f[:1], p.out_k, p.factor, sigma=float(p.sigma), lam=float(p.lambda_),
+                       steps=steps, lr=float(p.lr), decay=float(p.lr_decay))
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": round(steps / dt, 2), "unit": "frame-PSF Adam steps/s",
+                               "cores": 1, "kind": "oracle",
+                               "sample": f"one frame's fit ({steps} steps), FP64 single-threaded "
+                                         f"C oracle, {dt:.1f} s"}
+        log(f"cpu baseline: {out['cpu_baseline']['value']} frame-PSF Adam steps/s")
 
 
 # ---------------------------------------------------------------------------
@@ -357,6 +435,11 @@ def main() -> int:
         print(json.dumps(out), flush=True)
         return 0
 
+    if args.workload == "psf":
+        psf_bench(args, em, synth, dev, torch.cuda.Stream(dev), out)
+        print(json.dumps(out), flush=True)
+        return 0
+
     t0 = time.perf_counter()
     up = 2 if args.workload == "c4y" else 1
     prob = synth.make_problem("c4" if up > 1 else args.workload)
@@ -376,6 +459,9 @@ def main() -> int:
         e1.record(stream)
         torch.cuda.synchronize()
         extra["upsample_ms_once_per_job"] = round(e0.elapsed_time(e1), 4)
+        fit_ms, _, _, _ = time_psf_fit(em, synth, dev, stream, 3, 1)
+        extra["psf_fit_ms_once_per_job"] = round(fit_ms, 4)
+        log(f"  Eq. (4) fit of the 16 PSFs: {fit_ms:.3f} ms once per job")
         tensors = (yu, vu, tensors[2])
         prob = FineGrid(prob, up)
 

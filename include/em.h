@@ -241,6 +241,60 @@ int em_adjoint_op(const em_problem* p, const float* psf, const float* r, float* 
 int em_upsample(int32_t n_frames, int32_t frame_h, int32_t frame_w, int32_t factor,
                 const float* y, const float* v, float* y_up, float* v_up, void* stream);
 
+/*
+ * Super-resolved PSFs, Eq. (4) (arXiv:2302.05804, Sec. 2): for every frame t,
+ *     h_t = argmin_{h >= 0} sum_IJ ([D(h * g)]_IJ - f_t[I][J])^2 + lambda |grad h|^2,
+ * fitted by projected Adam (Kingma & Ba, 2015, Algorithm 1), the solver the
+ * paper uses.  Readings of what the paper leaves open:
+ *   - f_t is psf_k x psf_k on the frame grid, h_t out_k x out_k on the fine
+ *     grid (both odd).  The data term covers the factor*psf_k fine stamp that
+ *     D (factor x factor block sums, coarse pixel I = fine rows factor*I ..
+ *     factor*I + factor - 1) maps onto f's stamp; h's centre sits on fine
+ *     pixel factor*(psf_k-1)/2, the phase of D in Eq. (3).  h*g is a true
+ *     convolution; what falls outside the fine stamp is not seen.
+ *   - g: isotropic Gaussian, standard deviation `sigma` fine pixels (the
+ *     paper's width; sigma = factor by default), sampled at pixel centres
+ *     within ceil(4 sigma), unit sum; sigma = 0 is the unit impulse.
+ *   - |grad h|^2: squared forward differences of h extended by zeros, over
+ *     every pair of 4-neighbours with a pixel on the stamp.
+ *   - Each Adam step is followed by h = max(h, 0).  Step k of n_steps uses
+ *     lr * max(f_t) * lr_decay^((k-1)/(n_steps-1)).
+ *   - Start: f replicated into factor x factor blocks of value f/factor^2
+ *     (negative values set to 0), cropped to out_k x out_k about the anchor;
+ *     or h0 when given.
+ * Arguments (device pointers, row-major binary32):
+ *   f: n_frames x psf_k x psf_k, finite (read only);
+ *   h0: n_frames x out_k x out_k start, or NULL for the start above;
+ *   h: n_frames x out_k x out_k result (written);
+ *   objective: n_frames doubles, the objective at the result, or NULL.
+ * One workgroup per frame; asynchronous on `stream` (hipStream_t as void*,
+ * NULL = default stream); allocates nothing.  EM_EINVAL for NULL f or h,
+ * buffers that do not fit their device allocation, even or out-of-range
+ * sizes (psf_k, out_k in 1..63; factor 1..4; the EM kernels take PSFs up to
+ * 43), sigma outside [0, 8], lambda < 0, lr < 0, lr_decay <= 0, beta outside
+ * [0, 1), eps <= 0 or n_steps < 0.
+ */
+typedef struct {
+  int32_t n_frames; /* PSFs to fit */
+  int32_t psf_k;    /* side of f_t (odd) */
+  int32_t out_k;    /* side of h_t (odd) */
+  int32_t factor;   /* Delta of Eq. (3) */
+  int32_t n_steps;  /* Adam steps */
+  float sigma;      /* std of g in fine pixels */
+  float lambda;     /* weight of the gradient penalty */
+  float lr;         /* first step, relative to max f_t */
+  float lr_decay;   /* last step / first step */
+  float beta1, beta2, eps; /* Adam */
+} em_psf_problem;
+
+/* Fill p with the defaults: factor 2, sigma 2, lambda 1e-2, 2000 steps,
+ * lr 1e-2, lr_decay 1e-2, beta1 0.9, beta2 0.999, eps 1e-7, out_k 43,
+ * psf_k 43, n_frames 1. */
+void em_psf_defaults(em_psf_problem* p);
+
+int em_psf_fit(const em_psf_problem* p, const float* f, const float* h0, float* h,
+               double* objective, void* stream);
+
 /* ------------------------------------------------------------------------
  * Serving: continuous batching of deconvolution jobs on one GPU.
  *

@@ -952,4 +952,61 @@ int em_upsample(int32_t n_frames, int32_t frame_h, int32_t frame_w, int32_t fact
   return EM_OK;
 }
 
+void em_psf_defaults(em_psf_problem* p) {
+  if (!p) return;
+  p->n_frames = 1;
+  p->psf_k = 43;
+  p->out_k = 43;
+  p->factor = 2;
+  p->n_steps = 2000;
+  p->sigma = 2.f;
+  p->lambda = 1e-2f;
+  p->lr = 1e-2f;
+  p->lr_decay = 1e-2f;
+  p->beta1 = 0.9f;
+  p->beta2 = 0.999f;
+  p->eps = 1e-7f;
+}
+
+int em_psf_fit(const em_psf_problem* p, const float* f, const float* h0, float* h,
+               double* objective, void* stream) {
+  if (!p) return fail(EM_EINVAL, "problem is NULL");
+  const int kf = p->psf_k, kh = p->out_k;
+  if (p->n_frames < 1 || p->n_frames > (1 << 20)) return fail(EM_EINVAL, "n_frames out of range");
+  if (kf < 1 || kf > PSF_K_MAX || kf % 2 == 0 || kh < 1 || kh > PSF_K_MAX || kh % 2 == 0)
+    return fail(EM_EINVAL, "psf_k and out_k must be odd and in 1..%d", PSF_K_MAX);
+  if (p->factor < 1 || p->factor > 4) return fail(EM_EINVAL, "factor must be 1..4");
+  if (p->n_steps < 0) return fail(EM_EINVAL, "n_steps < 0");
+  if (!(p->sigma >= 0.f && p->sigma <= 8.f)) return fail(EM_EINVAL, "sigma must be in [0, 8]");
+  if (!(p->lambda >= 0.f) || !std::isfinite(p->lambda)) return fail(EM_EINVAL, "lambda must be >= 0");
+  if (!(p->lr >= 0.f) || !std::isfinite(p->lr)) return fail(EM_EINVAL, "lr must be >= 0");
+  if (!(p->lr_decay > 0.f) || !std::isfinite(p->lr_decay)) return fail(EM_EINVAL, "lr_decay must be > 0");
+  if (!(p->beta1 >= 0.f && p->beta1 < 1.f) || !(p->beta2 >= 0.f && p->beta2 < 1.f))
+    return fail(EM_EINVAL, "beta1 and beta2 must be in [0, 1)");
+  if (!(p->eps > 0.f) || !std::isfinite(p->eps)) return fail(EM_EINVAL, "eps must be > 0");
+  const size_t fb = (size_t)p->n_frames * kf * kf * sizeof(float);
+  const size_t hb = (size_t)p->n_frames * kh * kh * sizeof(float);
+  int rc;
+  if ((rc = check_device_range(f, fb, "f"))) return rc;
+  if ((rc = check_device_range(h, hb, "h"))) return rc;
+  if (h0 && (rc = check_device_range(h0, hb, "h0"))) return rc;
+  if (objective && (rc = check_device_range(objective, (size_t)p->n_frames * sizeof(double), "objective")))
+    return rc;
+  PsfParams P;
+  P.n = p->n_frames;
+  P.kf = kf;
+  P.kh = kh;
+  P.D = p->factor;
+  P.S = p->n_steps;
+  P.sigma = p->sigma;
+  P.lam = p->lambda;
+  P.lr = p->lr;
+  P.decay = p->lr_decay;
+  P.b1 = p->beta1;
+  P.b2 = p->beta2;
+  P.eps = p->eps;
+  EM_HIP(launch_psf_fit(P, f, h0, h, objective, static_cast<hipStream_t>(stream)));
+  return EM_OK;
+}
+
 }  // extern "C"

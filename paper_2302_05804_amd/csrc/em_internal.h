@@ -202,6 +202,16 @@ hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t 
 hipError_t launch_upsample(const float* y, const float* v, int n, int Hf, int Wf, int f,
                            float* yu, float* vu, hipStream_t s);
 
+// Super-resolved PSFs of Eq. (4) (em_psf.hip): one workgroup per frame.
+constexpr int PSF_K_MAX = 63;
+struct PsfParams {
+  int n, kf, kh, D, S;
+  float sigma, lam, lr, decay, b1, b2, eps;
+};
+size_t psf_lds_bytes(int kf, int kh);
+hipError_t launch_psf_fit(const PsfParams& P, const float* f, const float* h0, float* h,
+                          double* objective, hipStream_t s);
+
 }  // namespace em
 
 // One deconvolution job (opaque in the C ABI).

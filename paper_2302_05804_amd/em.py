@@ -56,6 +56,16 @@ class Problem(ctypes.Structure):
         return (self.frame_h * self.sr, self.frame_w * self.sr)
 
 
+class PsfProblem(ctypes.Structure):
+    """em_psf_problem: the fit of Eq. (4) (field meanings in include/em.h)."""
+    _fields_ = [("n_frames", ctypes.c_int32), ("psf_k", ctypes.c_int32),
+                ("out_k", ctypes.c_int32), ("factor", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("sigma", ctypes.c_float),
+                ("lambda_", ctypes.c_float), ("lr", ctypes.c_float),
+                ("lr_decay", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
 _P = ctypes.c_void_p
 _PP = ctypes.POINTER(ctypes.c_void_p)
 _sig = {
@@ -94,6 +104,8 @@ _sig = {
     "em_adjoint_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "em_upsample": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                    _P, _P, _P, _P, _P]),
+    "em_psf_defaults": (None, [ctypes.POINTER(PsfProblem)]),
+    "em_psf_fit": (ctypes.c_int, [ctypes.POINTER(PsfProblem), _P, _P, _P, _P, _P]),
 }
 for _name, (_res, _args) in _sig.items():
     _fn = getattr(_lib, _name)
@@ -291,6 +303,49 @@ def upsample(y, v, factor: int = 2, stream=None):
                             _dev_ptr(v, "v", n * hf * wf), _dev_ptr(yu, "y_up"),
                             _dev_ptr(vu, "v_up"), sp), "em_upsample")
     return yu, vu
+
+
+def psf_problem(n_frames: int, psf_k: int, out_k: int = 43, factor: int = 2, **kw) -> PsfProblem:
+    """em_psf_problem with the library's defaults, then the given fields
+    (sigma defaults to factor; keyword `lam` sets lambda, `steps` n_steps,
+    `decay` lr_decay)."""
+    p = PsfProblem()
+    _lib.em_psf_defaults(ctypes.byref(p))
+    p.n_frames, p.psf_k, p.out_k, p.factor = int(n_frames), int(psf_k), int(out_k), int(factor)
+    p.sigma = float(factor)
+    alias = {"lam": "lambda_", "steps": "n_steps", "decay": "lr_decay"}
+    for k, v in kw.items():
+        setattr(p, alias.get(k, k), v)
+    return p
+
+
+def psf_fit(f, out_k: int = 43, factor: int = 2, h0=None, objective: bool = True, stream=None,
+            **kw):
+    """Super-resolved PSFs of Eq. (4) for every frame-grid PSF in f
+    (n x Kf x Kf device tensor): (h n x out_k x out_k, objective n float64 or
+    None), new device tensors; keywords as psf_problem."""
+    torch = _torch()
+    n, kf = int(f.shape[0]), int(f.shape[1])
+    p = psf_problem(n, kf, out_k, factor, **kw)
+    h = torch.empty((n, out_k, out_k), dtype=torch.float32, device=f.device)
+    obj = torch.empty(n, dtype=torch.float64, device=f.device) if objective else None
+    psf_fit_into(p, f, h, obj, h0, stream)
+    return h, obj
+
+
+def psf_fit_into(p: PsfProblem, f, h, objective=None, h0=None, stream=None):
+    """em_psf_fit on caller-owned device tensors (f, h float32; objective
+    float64 of n_frames or None; h0 float32 or None); asynchronous."""
+    torch = _torch()
+    n, kf, kh = p.n_frames, p.psf_k, p.out_k
+    if objective is not None and (objective.dtype != torch.float64 or not objective.is_cuda
+                                  or objective.numel() != n):
+        raise TypeError("objective must be a CUDA float64 tensor of n_frames values")
+    sp, _ = _stream_ptr(stream)
+    _check(_lib.em_psf_fit(ctypes.byref(p), _dev_ptr(f, "f", n * kf * kf),
+                           _dev_ptr(h0, "h0", n * kh * kh), _dev_ptr(h, "h", n * kh * kh),
+                           None if objective is None else ctypes.c_void_p(objective.data_ptr()),
+                           sp), "em_psf_fit")
 
 
 def job_bytes(p: Problem) -> int:
