@@ -19,7 +19,9 @@ arXiv:2302.05804, Sec. 2):
 * ``upsample`` -- the up-sampled exposures of the super-resolution run the
   paper describes after Eq. (4) (fine grid, super-resolved PSFs, no D);
 * ``psf_gauss`` / ``psf_objective`` / ``psf_gradient`` / ``psf_start`` /
-  ``psf_fit`` -- the super-resolved PSFs of Eq. (4), fitted by projected Adam.
+  ``psf_fit`` -- the super-resolved PSFs of Eq. (4), fitted by projected Adam;
+* ``run_t`` / ``loglik_t`` / ``terms_t`` -- the EM iteration under Student-t
+  noise (the heavier-tailed noise the paper names as future work).
 
 The readings taken where the paper is silent (weight placement, clamp of a
 negative numerator, 0/0 guards, boundary, downsampling kernel) are listed in
@@ -95,6 +97,12 @@ def _load():
     lib.em_oracle_psf_start.argtypes = [I, I, I, P, P]
     lib.em_oracle_psf_fit.restype = I
     lib.em_oracle_psf_fit.argtypes = [I, I, I, I, D, D, I, D, D, D, D, D, P, P, P, P]
+    lib.em_oracle_loglik_t.restype = I
+    lib.em_oracle_loglik_t.argtypes = [I, I, I, I, I, D, P, P, P, P, P]
+    lib.em_oracle_terms_t.restype = I
+    lib.em_oracle_terms_t.argtypes = [I, I, I, I, I, D, P, P, P, P, P, P]
+    lib.em_oracle_run_t.restype = I
+    lib.em_oracle_run_t.argtypes = [I, I, I, I, I, D, P, P, P, P, I, P, P]
     lib.em_oracle_step_at.restype = I
     lib.em_oracle_step_at.argtypes = [I, I, I, I, I, P, P, P, P, I, P, P, P, P, P]
     _lib = lib
@@ -348,3 +356,49 @@ def psf_fit(f, kh: int = 43, factor: int = 2, sigma=None, h0=None, **kw):
     if rc:
         raise ValueError("bad Eq. (4) arguments")
     return h, obj
+
+
+# ---------------------------------------------------------------------------
+# Student-t noise (readings in the header of that part of em_oracle.c)
+# ---------------------------------------------------------------------------
+
+def loglik_t(y, v, psf, x, nu: float, sr: int = 1) -> float:
+    """Student-t log-likelihood (nu degrees of freedom, scale v) at x."""
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf, x = _f32(y), _f32(v), _f32(psf), _f64(x)
+    out = np.zeros(1, np.float64)
+    if lib.em_oracle_loglik_t(n, hf, wf, K, sr, float(nu), _p(y), _p(v), _p(psf), _p(x), _p(out)):
+        raise ValueError("oracle Student-t loglik failed")
+    return float(out[0])
+
+
+def terms_t(y, v, psf, x, nu: float, sr: int = 1):
+    """(B_w, Dn_w) of the Student-t EM step at x (latent grid each)."""
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf, x = _f32(y), _f32(v), _f32(psf), _f64(x)
+    B = np.zeros((hf * sr, wf * sr))
+    D = np.zeros((hf * sr, wf * sr))
+    if lib.em_oracle_terms_t(n, hf, wf, K, sr, float(nu), _p(y), _p(v), _p(psf), _p(x), _p(B), _p(D)):
+        raise ValueError("oracle Student-t terms failed")
+    return B, D
+
+
+def run_t(y, v, psf, x0, n_iter: int, nu: float, sr: int = 1, trace: bool = False,
+          relchange: bool = False):
+    """n_iter iterations of the Student-t EM from x0; as ``run``."""
+    lib = _load()
+    n, hf, wf, K = _shape(y, psf, sr)
+    y, v, psf = _f32(y), _f32(v), _f32(psf)
+    x = np.array(x0, dtype=np.float64, copy=True, order="C")
+    if x.shape != (hf * sr, wf * sr):
+        raise ValueError("x0 must be the latent grid")
+    tr = np.zeros(max(n_iter, 1), np.float64)
+    rc_ = np.zeros(max(n_iter, 1), np.float64)
+    if lib.em_oracle_run_t(n, hf, wf, K, sr, float(nu), _p(y), _p(v), _p(psf), _p(x), int(n_iter),
+                           _p(tr), _p(rc_)):
+        raise ValueError("oracle Student-t run failed")
+    if trace or relchange:
+        return x, tr[:n_iter], rc_[:n_iter]
+    return x
