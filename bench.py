@@ -11,7 +11,8 @@ the FP16 split matrix-core form (binary16 image with a power-of-two tile scale
 times a binary16 hi+lo PSF; the reported value), in the BF16 hi+lo split form
 and in plain FP32 on the same data.  --workload c4 is the super-resolution
 model of Eq. (3), c4y the super-resolution run described after Eq. (4)
-(up-sampled exposures), psf the fit of the super-resolved PSFs of Eq. (4)
+(up-sampled exposures), c3t c3 with satellite trails under Student-t noise,
+psf the fit of the super-resolved PSFs of Eq. (4)
 for c4's job, c5 the serving stream.  The full-size parity of the
 same launches against the oracle is a GPU test (tests/test_gpu_fullsize.py).
 
@@ -46,6 +47,9 @@ WORKLOADS = {
     "c4y": "c4y: the super-resolution run described after Eq. (4): c4's 16 frames of 2048x2048 "
            "up-sampled x2 on the GPU (flux-sharing replication) to 4096x4096, 43x43 "
            "super-resolved PSFs, plain EM on the fine grid (no down-sampling operator)",
+    "c3t": "c3t: c3 with unflagged satellite trails (1-2 per frame, 2-4 px wide, 20-200 sigma) "
+           "under Student-t noise of 4 degrees of freedom (the heavier-tailed noise model): E-step "
+           "weights refreshed every iteration, numerator and denominator adjoints, sr=1",
     "psf": "psf: the super-resolved PSFs of Eq. (4) for c4's job: 16 frame-grid PSFs of 43x43 "
            "(Moffat, sub-pixel offsets) fitted to 43x43 fine-grid PSFs, Delta 2, Gaussian g of "
            "sigma 2, lambda 1e-2, 2000 projected-Adam steps, all frames in one launch",
@@ -126,7 +130,11 @@ def cpu_baseline(prob, crop: int, iters: int):
     x0 = np.full((crop * s, crop * s), oracle.flat_x0(y, v, s), np.float32)
     oracle.build(force=False)
     t0 = time.perf_counter()
-    oracle.run(y, v, prob.psf, x0, iters, s)
+    nu = getattr(prob, "nu", 0.0)
+    if nu:
+        oracle.run_t(y, v, prob.psf, x0, iters, nu, s)
+    else:
+        oracle.run(y, v, prob.psf, x0, iters, s)
     dt = time.perf_counter() - t0
     fpix = prob.n * crop * crop * iters
     return {
@@ -139,12 +147,12 @@ def cpu_baseline(prob, crop: int, iters: int):
     }
 
 
-def time_form(em, prob, tensors, prec_name, steps, warmup, stream):
+def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
     """Time one precision form on resident inputs; returns a dict of figures."""
     import torch
     y, v, f = tensors
     n, hf, wf = y.shape
-    p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec_code(em, prec_name))
+    p = em.Problem.make(n, hf, wf, prob.K, sr=prob.sr, precision=prec_code(em, prec_name), nu=nu)
     x = torch.empty(p.latent_shape, dtype=torch.float32, device=y.device)
     torch.cuda.synchronize()
     with torch.cuda.stream(stream):
@@ -173,7 +181,9 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream):
     ctx.close()
     kc = prob.K if prob.sr == 1 else prob.K + 1
     flops = 2.0 * kc * kc * fpix    # one K_eff x K_eff convolution per frame pixel
-    dom = 0 if phases[0] >= phases[1] else 1
+    # under Student-t noise phases[0] also holds the weight kernel: the adjoint
+    # (with the fused update) is the kernel timed on its own
+    dom = 1 if nu else (0 if phases[0] >= phases[1] else 1)
     achieved = flops / (phases[dom] / 1e3) / 1e12
     mf = prec_name != "fp32"
     peak = PEAKS_TFLOPS["bf16" if mf else "fp32"]
@@ -442,7 +452,12 @@ def main() -> int:
 
     t0 = time.perf_counter()
     up = 2 if args.workload == "c4y" else 1
-    prob = synth.make_problem("c4" if up > 1 else args.workload)
+    nu = 4.0 if args.workload == "c3t" else 0.0
+    prob = synth.make_problem("c4" if up > 1 else "c3" if nu else args.workload)
+    if nu:
+        prob.y, trails = synth.add_trails(prob.y, prob.v, seed=3300)
+        prob.name, prob.nu = "c3t", nu
+        log(f"  trails on {trails.mean() * 100:.2f}% of the frame pixels")
     log(f"generated {args.workload}: frames {prob.y.shape} K={prob.K} sr={prob.sr} "
         f"in {time.perf_counter() - t0:.1f} s")
     tensors = tuple(torch.from_numpy(a).to(dev) for a in (prob.y, prob.v, prob.psf))
@@ -472,7 +487,7 @@ def main() -> int:
     res = {}
     for fm in forms:
         log(f"timing {fm}")
-        res[fm] = time_form(em, prob, tensors, fm, args.steps, args.warmup, stream)
+        res[fm] = time_form(em, prob, tensors, fm, args.steps, args.warmup, stream, nu)
     head = res[forms[0]]
     n, hf, wf = tensors[0].shape
     cfg = {
@@ -480,6 +495,7 @@ def main() -> int:
         "frames": n, "frame_h": hf, "frame_w": wf,
         "latent_h": prob.latent_shape[0], "latent_w": prob.latent_shape[1],
         "psf_k": prob.K, "sr": prob.sr, "precision": forms[0], **extra,
+        "noise": f"Student-t, nu = {nu:g}" if nu else "Gaussian",
         "iterations_per_job": prob.n_iter,
         "per_launch_ms": head["per_launch_ms"],
         "result_finite_nonnegative": head["ok"],

@@ -77,9 +77,24 @@ extern "C" {
                                exactly in the epilogue                       */
 #define EM_BF16        3    /* plain BF16 MFMA (ablation; below 1e-3 accuracy) */
 
-/* placement of the inverse-variance weights */
+/* placement of the inverse-variance weights, and the noise model */
 #define EM_W_ADJOINT   0    /* sum_t F_t^T (u_t (.) .)  (default)              */
 #define EM_W_LITERAL   1    /* sum_t u_t (.) F_t^T (.)  (Eq. (2) as typeset, sr=1) */
+#define EM_W_STUDENT_T 2    /* Student-t noise with nu degrees of freedom and
+                               scale v (the heavier-tailed noise the paper
+                               names as future work): every iteration gives
+                               each observed pixel the E-step weight
+                               w = (nu+1)/(nu + u (y - F_t x)^2) of the
+                               Gaussian scale-mixture form (Lange, Little &
+                               Taylor, 1989) and runs the update of Eq. (2)
+                               with u w in place of u, the numerator
+                               B = sum_t F_t^T(u_t w_t y_t) formed again;
+                               l(x) is the Student-t log-likelihood
+                               sum_{u>0} [lgamma((nu+1)/2) - lgamma(nu/2)
+                               - ln(nu pi v)/2 - (nu+1)/2 ln(1 + u (y-F_t x)^2/nu)].
+                               An iteration costs one forward and two adjoint
+                               passes; the workspace holds one more frame-sized
+                               plane.  Not served by em_server (EM_ENOTSUP). */
 
 typedef struct em_ctx em_ctx;
 typedef struct em_server em_server;
@@ -92,7 +107,10 @@ typedef struct {
     int32_t psf_k;        /* odd, 1 <= K <= 43                               */
     int32_t sr;           /* super-resolution factor: 1 or 2 (Eq. (3))       */
     int32_t precision;    /* EM_FP32, EM_BF16_SPLIT, EM_FP16_SPLIT, EM_BF16   */
-    int32_t weight_mode;  /* EM_W_ADJOINT (EM_W_LITERAL: sr = 1 only)        */
+    int32_t weight_mode;  /* EM_W_ADJOINT, EM_W_STUDENT_T (EM_W_LITERAL: sr = 1,
+                             oracle only)                                      */
+    float nu;             /* EM_W_STUDENT_T: degrees of freedom in (0, 1e30];
+                             ignored otherwise                                 */
 } em_problem;
 
 /* Library build / device description (NUL-terminated, static storage). */
@@ -169,6 +187,8 @@ int em_terms(em_ctx* ctx, float* B_out, float* Dn_out);
  *                                     the adjoint is not split over frame groups)
  *   phase_ms[2]  the separate update kernel (0 when fused)
  *   phase_ms[3]  the whole iteration
+ * Under EM_W_STUDENT_T phase_ms[0] is the forward kernel (raw F_t x) plus the
+ * weight kernel, and the numerator's adjoint counts in phase_ms[3] only.
  * Synchronous.
  */
 int em_profile(em_ctx* ctx, int32_t n_iter, double* phase_ms);

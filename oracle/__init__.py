@@ -103,6 +103,8 @@ def _load():
     lib.em_oracle_terms_t.argtypes = [I, I, I, I, I, D, P, P, P, P, P, P]
     lib.em_oracle_run_t.restype = I
     lib.em_oracle_run_t.argtypes = [I, I, I, I, I, D, P, P, P, P, I, P, P]
+    lib.em_oracle_step_at_t.restype = I
+    lib.em_oracle_step_at_t.argtypes = [I, I, I, I, I, D, P, P, P, P, I, P, P, P, P, P]
     lib.em_oracle_step_at.restype = I
     lib.em_oracle_step_at.argtypes = [I, I, I, I, I, P, P, P, P, I, P, P, P, P, P]
     _lib = lib
@@ -254,10 +256,11 @@ def run(y, v, psf, x0, n_iter: int, sr: int = 1, mode: int = W_ADJOINT,
     return x
 
 
-def step_at(y, v, psf, x0, rows, cols, sr: int = 1):
+def step_at(y, v, psf, x0, rows, cols, sr: int = 1, nu: float = 0.0):
     """One iteration evaluated only at latent pixels (rows[i], cols[i]).
 
-    Returns (B, Dn, x1) at those pixels, computed from x0 (float32 latent grid).
+    Returns (B, Dn, x1) at those pixels, computed from x0 (float32 latent grid);
+    nu > 0: Student-t noise with nu degrees of freedom.
     """
     lib = _load()
     n, hf, wf, K = _shape(y, psf, sr)
@@ -268,8 +271,12 @@ def step_at(y, v, psf, x0, rows, cols, sr: int = 1):
     B = np.empty(npts, np.float64)
     Dn = np.empty(npts, np.float64)
     x1 = np.empty(npts, np.float64)
-    rc = lib.em_oracle_step_at(n, hf, wf, K, sr, _p(y), _p(v), _p(psf), _p(x0), npts,
-                               _p(rows), _p(cols), _p(B), _p(Dn), _p(x1))
+    if nu > 0:
+        rc = lib.em_oracle_step_at_t(n, hf, wf, K, sr, float(nu), _p(y), _p(v), _p(psf), _p(x0),
+                                     npts, _p(rows), _p(cols), _p(B), _p(Dn), _p(x1))
+    else:
+        rc = lib.em_oracle_step_at(n, hf, wf, K, sr, _p(y), _p(v), _p(psf), _p(x0), npts,
+                                   _p(rows), _p(cols), _p(B), _p(Dn), _p(x1))
     if rc:
         raise ValueError(f"oracle step_at failed ({rc})")
     return B, Dn, x1

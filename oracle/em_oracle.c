@@ -399,14 +399,15 @@ int em_oracle_run(int n, int Hf, int Wf, int K, int sr, int mode,
 
 /*
  * One iteration evaluated only at selected latent pixels (for checks at sizes
- * where a whole run is out of reach).  x0 (float, latent grid) is x^(0); for each
+ * where a whole run is out of reach); Gaussian noise, or Student-t noise with
+ * nu degrees of freedom (_t).  x0 (float, latent grid) is x^(0); for each
  * point (rows[i], cols[i]) writes B, Dn and x^(1) there (adjoint weighting).
  * Each F_t x value needed is evaluated on demand from its definition.
  */
-int em_oracle_step_at(int n, int Hf, int Wf, int K, int sr,
-                      const float* y, const float* v, const float* psf, const float* x0,
-                      int npts, const int* rows, const int* cols,
-                      double* B_out, double* Dn_out, double* x1_out)
+static int emo_step_at(int n, int Hf, int Wf, int K, int sr, double nu,
+                       const float* y, const float* v, const float* psf, const float* x0,
+                       int npts, const int* rows, const int* cols,
+                       double* B_out, double* Dn_out, double* x1_out)
 {
     const int Hl = Hf * sr, Wl = Wf * sr, c = (K - 1) / 2;
     const long nl = (long)Hl * Wl;
@@ -436,9 +437,12 @@ int em_oracle_step_at(int n, int Hf, int Wf, int K, int sr,
                         free(xd); free(fd); return -1;
                     }
                     const double u = 1.0 / vv;
+                    const double yv = (double)yt[(long)I * Wf + J];
                     const double mval = em_oracle_forward_at(K, sr, Hl, Wl, fd, xd, I, J);
-                    bt += fd[a * K + b] * (u * (double)yt[(long)I * Wf + J]);
-                    dt += fd[a * K + b] * (u * mval);
+                    /* Gaussian noise (nu <= 0): weight 1; Student-t: the E-step weight */
+                    const double w = nu > 0.0 ? (nu + 1.0) / (nu + u * (yv - mval) * (yv - mval)) : 1.0;
+                    bt += fd[a * K + b] * (u * w * yv);
+                    dt += fd[a * K + b] * (u * w * mval);
                 }
             }
             Bv += bt;
@@ -453,6 +457,23 @@ int em_oracle_step_at(int n, int Hf, int Wf, int K, int sr,
     }
     free(xd); free(fd);
     return 0;
+}
+
+int em_oracle_step_at(int n, int Hf, int Wf, int K, int sr,
+                      const float* y, const float* v, const float* psf, const float* x0,
+                      int npts, const int* rows, const int* cols,
+                      double* B_out, double* Dn_out, double* x1_out)
+{
+    return emo_step_at(n, Hf, Wf, K, sr, 0.0, y, v, psf, x0, npts, rows, cols, B_out, Dn_out, x1_out);
+}
+
+int em_oracle_step_at_t(int n, int Hf, int Wf, int K, int sr, double nu,
+                        const float* y, const float* v, const float* psf, const float* x0,
+                        int npts, const int* rows, const int* cols,
+                        double* B_out, double* Dn_out, double* x1_out)
+{
+    if (!(nu > 0.0)) return -1;
+    return emo_step_at(n, Hf, Wf, K, sr, nu, y, v, psf, x0, npts, rows, cols, B_out, Dn_out, x1_out);
 }
 
 /* ===========================================================================

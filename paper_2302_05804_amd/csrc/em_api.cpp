@@ -58,8 +58,13 @@ bool make_geometry(const void* problem, Geometry* g, const char** why) {
     return false;
   }
   if (p->sr != 1 && p->sr != 2) { *why = "sr must be 1 or 2"; return false; }
-  if (p->weight_mode != EM_W_ADJOINT && p->weight_mode != EM_W_LITERAL) {
+  if (p->weight_mode != EM_W_ADJOINT && p->weight_mode != EM_W_LITERAL &&
+      p->weight_mode != EM_W_STUDENT_T) {
     *why = "unknown weight_mode";
+    return false;
+  }
+  if (p->weight_mode == EM_W_STUDENT_T && !(p->nu > 0.f && p->nu <= 1e30f)) {
+    *why = "nu must be in (0, 1e30] for Student-t noise";
     return false;
   }
   if (p->precision < EM_FP32 || p->precision > EM_BF16) { *why = "unknown precision"; return false; }
@@ -76,6 +81,7 @@ bool make_geometry(const void* problem, Geometry* g, const char** why) {
   g->Nl = (int64_t)g->Hl * g->Wl;
   g->precision = p->precision;
   g->weight_mode = p->weight_mode;
+  g->nu = p->weight_mode == EM_W_STUDENT_T ? p->nu : 0.f;
   if ((int64_t)g->n * g->Nf > ((int64_t)1 << 40)) { *why = "problem too large"; return false; }
   if (g->Nl >= ((int64_t)1 << 31)) { *why = "latent image of 2^31 pixels or more"; return false; }
   return true;
@@ -176,6 +182,7 @@ Layout make_layout(const Geometry& g, const Plan& pl) {
   const int G = pl.adj_groups;
   L.u = take(nf * sizeof(float));
   L.r = take(nf * sizeof(float));
+  L.ry = take(g.weight_mode == EM_W_STUDENT_T ? nf * sizeof(float) : 0);
   L.B = take((size_t)g.Nl * sizeof(float));
   L.planes = take(G > 1 ? (size_t)G * g.Nl * sizeof(float) : 0);
   L.tab = take((size_t)g.n * g.KC * TAB_LD * sizeof(float));
@@ -228,6 +235,7 @@ void em_bind_views(em_ctx* c) {
   const Layout& L = c->lay;
   c->u = reinterpret_cast<float*>(w + L.u);
   c->r = reinterpret_cast<float*>(w + L.r);
+  c->ry = reinterpret_cast<float*>(w + L.ry);
   c->B = reinterpret_cast<float*>(w + L.B);
   c->planes = reinterpret_cast<float*>(w + L.planes);
   c->tab = reinterpret_cast<float*>(w + L.tab);
@@ -385,6 +393,26 @@ static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
   return EM_OK;
 }
 
+// Student-t noise: r = F x (raw forward), then the E-step weights turn it into
+// r = u w F x and ry = u w y, with loglik partials in part_prep when asked.
+static int robust_forward(em_ctx* c, bool loglik) {
+  if (uses_mfma(c->g)) {
+    MfmaLaunch m;
+    fill_forward_mfma(c, &m, true, false);
+    m.u = nullptr;
+    EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_variant, c->pl.fwd_tiles, c->pl.fwd_groups, m,
+                       c->stream));
+  } else {
+    FwdLaunch f;
+    fill_forward_fp32(c, &f, true, false);
+    f.u = nullptr;
+    EM_HIP(launch_forward(c->g, c->pl, f, c->stream));
+  }
+  EM_HIP(launch_student_t(c->u, c->y, c->r, c->ry, (int64_t)c->g.n * c->g.Nf, c->g.nu,
+                          loglik ? c->part_prep : nullptr, c->pl.prep_blocks, c->stream));
+  return EM_OK;
+}
+
 // Adjoint of r summed over frames; with a single frame group the
 // multiplicative update is fused into its epilogue, else it writes the partial
 // planes (the update then runs separately, update_launch).
@@ -421,15 +449,20 @@ static int adjoint_update(em_ctx* c, double* part_rc, int* n_rc) {
 }
 
 // One EM iteration (Eq. (2)); optional FP64 loglik / relative-change bookkeeping.
+// Under Student-t noise the numerator is formed again from the new weights
+// before the adjoint of the denominator (which applies the update).
 static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
-  int rc = forward_pass(c, true, loglik);
+  const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
+  int rc = robust ? robust_forward(c, loglik) : forward_pass(c, true, loglik);
   if (rc) return rc;
+  if (robust && (rc = adjoint_sum(c, c->ry, c->B))) return rc;
   int n_rc = 0;
   if ((rc = adjoint_update(c, relchange ? c->part_rc : nullptr, &n_rc))) return rc;
   if (loglik || relchange) {
-    EM_HIP(launch_finalize_iter(loglik ? c->part_ll : nullptr, c->pl.fwd_tiles * c->pl.fwd_groups,
-                                relchange ? c->part_rc : nullptr, n_rc, c->scalars, c->trace_ll,
-                                c->trace_rc, c->counters, c->stream));
+    const double* pll = !loglik ? nullptr : robust ? c->part_prep : c->part_ll;
+    const int nll = robust ? c->pl.prep_blocks : c->pl.fwd_tiles * c->pl.fwd_groups;
+    EM_HIP(launch_finalize_iter(pll, nll, relchange ? c->part_rc : nullptr, n_rc, c->scalars,
+                                c->trace_ll, c->trace_rc, c->counters, c->stream));
   }
   return EM_OK;
 }
@@ -487,7 +520,7 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
-  if (g.weight_mode != EM_W_ADJOINT)
+  if (g.weight_mode == EM_W_LITERAL)
     return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
   const Plan pl = serving ? make_serving_plan(g) : make_plan(g);
   const Layout L = make_layout(g, pl);
@@ -621,10 +654,16 @@ int em_iterate_tol(em_ctx* c, int32_t max_iter, double tol, int32_t check_every,
 
 int em_loglik(em_ctx* c, double* out) {
   if (!c || !out) return fail(EM_EINVAL, "NULL argument");
-  int rc = forward_pass(c, false, true);
-  if (rc) return rc;
-  EM_HIP(launch_finalize_loglik(c->part_ll, c->pl.fwd_tiles * c->pl.fwd_groups, c->scalars,
-                                c->stream));
+  if (c->g.weight_mode == EM_W_STUDENT_T) {
+    int rc = robust_forward(c, true);
+    if (rc) return rc;
+    EM_HIP(launch_finalize_loglik(c->part_prep, c->pl.prep_blocks, c->scalars, c->stream));
+  } else {
+    int rc = forward_pass(c, false, true);
+    if (rc) return rc;
+    EM_HIP(launch_finalize_loglik(c->part_ll, c->pl.fwd_tiles * c->pl.fwd_groups, c->scalars,
+                                  c->stream));
+  }
   EM_HIP(hipMemcpyAsync(out, c->scalars + S_LOGLIK, sizeof(double), hipMemcpyDeviceToHost,
                         c->stream));
   EM_HIP(hipStreamSynchronize(c->stream));
@@ -635,6 +674,15 @@ int em_terms(em_ctx* c, float* B_out, float* Dn_out) {
   if (!c) return fail(EM_EINVAL, "ctx is NULL");
   const size_t lbytes = (size_t)c->g.Nl * sizeof(float);
   int rc;
+  if (c->g.weight_mode == EM_W_STUDENT_T) {
+    // both terms depend on the weights at the current iterate
+    if (B_out && (rc = check_device_range(B_out, lbytes, "B_out"))) return rc;
+    if (Dn_out && (rc = check_device_range(Dn_out, lbytes, "Dn_out"))) return rc;
+    if ((rc = robust_forward(c, false))) return rc;
+    if (B_out && (rc = adjoint_sum(c, c->ry, B_out))) return rc;
+    if (Dn_out && (rc = adjoint_sum(c, c->r, Dn_out))) return rc;
+    return EM_OK;
+  }
   if (B_out) {
     if ((rc = check_device_range(B_out, lbytes, "B_out"))) return rc;
     EM_HIP(hipMemcpyAsync(B_out, c->B, lbytes, hipMemcpyDeviceToDevice, c->stream));
@@ -650,14 +698,17 @@ int em_terms(em_ctx* c, float* B_out, float* Dn_out) {
 int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
   if (!c || !phase_ms) return fail(EM_EINVAL, "NULL argument");
   if (n_iter < 1) return fail(EM_EINVAL, "n_iter must be >= 1");
-  hipEvent_t ev[4];
-  for (int i = 0; i < 4; ++i) EM_HIP(hipEventCreate(&ev[i]));
+  hipEvent_t ev[5];
+  for (int i = 0; i < 5; ++i) EM_HIP(hipEventCreate(&ev[i]));
   double acc[4] = {0, 0, 0, 0};
   int rc = EM_OK;
   const bool fused = c->pl.adj_groups == 1;
+  const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
   for (int k = 0; k < n_iter && rc == EM_OK; ++k) {
     EM_HIP(hipEventRecord(ev[0], c->stream));
-    if ((rc = forward_pass(c, true, false))) break;
+    if ((rc = robust ? robust_forward(c, false) : forward_pass(c, true, false))) break;
+    EM_HIP(hipEventRecord(ev[4], c->stream));
+    if (robust && (rc = adjoint_sum(c, c->ry, c->B))) break;
     EM_HIP(hipEventRecord(ev[1], c->stream));
     if ((rc = adjoint_launch(c, nullptr))) break;
     EM_HIP(hipEventRecord(ev[2], c->stream));
@@ -665,7 +716,7 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
     EM_HIP(hipEventRecord(ev[3], c->stream));
     EM_HIP(hipEventSynchronize(ev[3]));
     float ms;
-    EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[1]));
+    EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[4]));
     acc[0] += ms;
     EM_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
     acc[1] += ms;
@@ -674,7 +725,7 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
     EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[3]));
     acc[3] += ms;
   }
-  for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
   if (rc) return rc;
   for (int i = 0; i < 4; ++i) phase_ms[i] = acc[i] / n_iter;
   return EM_OK;

@@ -47,6 +47,7 @@ struct Geometry {
   int n, Hf, Wf, sr, Hl, Wl, K, KT, KC;
   int64_t Nf, Nl;
   int precision, weight_mode;
+  float nu;   // Student-t degrees of freedom (EM_W_STUDENT_T)
 };
 
 // Launch shape chosen for a geometry (a pure function of the geometry, so the
@@ -70,8 +71,8 @@ struct Plan {
 
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct Layout {
-  size_t u, r, B, planes, tab, mtab_fwd, mtab_adj, tune, part_ll, part_rc, part_prep, scalars,
-      trace_ll, trace_rc, counters, total;
+  size_t u, r, ry, B, planes, tab, mtab_fwd, mtab_adj, tune, part_ll, part_rc, part_prep,
+      scalars, trace_ll, trace_rc, counters, total;
 };
 
 // true when the convolutions of geometry g run on the matrix cores
@@ -202,6 +203,11 @@ hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t 
 hipError_t launch_upsample(const float* y, const float* v, int n, int Hf, int Wf, int f,
                            float* yu, float* vu, hipStream_t s);
 
+// Student-t noise: E-step weights and the two adjoint inputs (em_elem.hip);
+// `blocks` partials of the log-likelihood into `part` when it is not NULL.
+hipError_t launch_student_t(const float* u, const float* y, float* r, float* ry, int64_t count,
+                            float nu, double* part, int blocks, hipStream_t s);
+
 // Super-resolved PSFs of Eq. (4) (em_psf.hip): one workgroup per frame.
 constexpr int PSF_K_MAX = 63;
 struct PsfParams {
@@ -228,6 +234,7 @@ struct em_ctx {
   // device views into the workspace
   float* u;
   float* r;
+  float* ry;   // u w y of the Student-t iteration (EM_W_STUDENT_T only)
   float* B;
   float* planes;
   float* tab;

@@ -27,7 +27,7 @@ OK, EINVAL, ENOMEM, EDEVICE, EAGAIN, ECANCELED, ENOTSUP = 0, -1, -2, -3, -4, -5,
 # precisions
 FP32, BF16_SPLIT, FP16_SPLIT, BF16 = 0, 1, 2, 3
 # weight placement
-W_ADJOINT, W_LITERAL = 0, 1
+W_ADJOINT, W_LITERAL, W_STUDENT_T = 0, 1, 2
 
 _NAMES = {OK: "EM_OK", EINVAL: "EM_EINVAL", ENOMEM: "EM_ENOMEM", EDEVICE: "EM_EDEVICE",
           EAGAIN: "EM_EAGAIN", ECANCELED: "EM_ECANCELED", ENOTSUP: "EM_ENOTSUP"}
@@ -44,12 +44,16 @@ class Problem(ctypes.Structure):
     _fields_ = [("n_frames", ctypes.c_int32), ("frame_h", ctypes.c_int32),
                 ("frame_w", ctypes.c_int32), ("psf_k", ctypes.c_int32),
                 ("sr", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("weight_mode", ctypes.c_int32)]
+                ("weight_mode", ctypes.c_int32), ("nu", ctypes.c_float)]
 
     @classmethod
-    def make(cls, n, frame_h, frame_w, psf_k, sr=1, precision=FP32, weight_mode=W_ADJOINT):
+    def make(cls, n, frame_h, frame_w, psf_k, sr=1, precision=FP32, weight_mode=W_ADJOINT,
+             nu=0.0):
+        """nu > 0 selects Student-t noise with nu degrees of freedom (EM_W_STUDENT_T)."""
+        if nu:
+            weight_mode = W_STUDENT_T
         return cls(int(n), int(frame_h), int(frame_w), int(psf_k), int(sr), int(precision),
-                   int(weight_mode))
+                   int(weight_mode), float(nu))
 
     @property
     def latent_shape(self):

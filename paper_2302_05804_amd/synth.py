@@ -291,6 +291,34 @@ def make_problem(config: str = "c1", replica: int = 0, seed: Optional[int] = Non
                    n_iter=int(rec["n_iter"]), seed=int(seed))
 
 
+def add_trails(y: np.ndarray, v: np.ndarray, seed: int, per_frame=(1, 2), width=(2, 4),
+               amp=(20.0, 200.0)):
+    """Unflagged satellite trails (outliers the variance map does not know
+    about): per frame U{per_frame} straight lines across the whole frame, width
+    U{width} px, adding amp ~ U(amp) standard deviations sqrt(v) on the line
+    (masked pixels untouched).  Returns (new y, boolean trail mask)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    y = y.copy()
+    n, H, W = y.shape
+    hit = np.zeros(y.shape, bool)
+    L = math.hypot(H, W)
+    steps = np.arange(-L / 2, L / 2, 0.5)
+    for t in range(n):
+        for _ in range(int(rng.integers(per_frame[0], per_frame[1] + 1))):
+            ang = rng.uniform(0, math.pi)
+            cy, cx = rng.uniform(0, H), rng.uniform(0, W)
+            wd = int(rng.integers(width[0], width[1] + 1))
+            for d in range(wd):
+                yy = cy + steps * math.sin(ang) + d * math.cos(ang)
+                xx = cx + steps * math.cos(ang) - d * math.sin(ang)
+                ok = (yy >= 0) & (yy < H) & (xx >= 0) & (xx < W)
+                hit[t, yy[ok].astype(np.int64), xx[ok].astype(np.int64)] = True
+        a = rng.uniform(*amp)
+        m = hit[t] & np.isfinite(v[t])
+        y[t][m] += (a * np.sqrt(v[t][m].astype(np.float64))).astype(np.float32)
+    return y, hit
+
+
 def coarse_psfs(n: int, kf: int = 43, factor: int = 2, seed: int = 4100,
                 fwhm=(3.0, 6.0), ell: float = 0.3) -> np.ndarray:
     """n frame-grid PSFs (kf x kf, float32) to be super-resolved by Eq. (4):

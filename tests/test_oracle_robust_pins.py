@@ -132,6 +132,22 @@ def test_outliers_are_down_weighted():
     assert d_t < 1e-5 and d_g > 1.0
 
 
+@pytest.mark.parametrize("sr", [1, 2])
+def test_step_at_matches_one_step(sr):
+    """The pointwise step (used at full size) equals a whole Student-t step."""
+    y, v, psf, _ = small_problem(14, 12, 3, 5, sr=sr, seed=90 + sr, mask=0.1)
+    y, _ = with_outliers(y, v, 0.05, 30.0, 92)
+    x0 = positive((14, 12), 93)
+    B, D = oracle.terms_t(y, v, psf, x0, 2.0, sr)
+    x1 = oracle.run_t(y, v, psf, x0, 1, 2.0, sr)
+    rows = np.array([0, 13, 7, 3, 0], np.int32)
+    cols = np.array([0, 11, 5, 9, 11], np.int32)
+    Bs, Ds, xs = oracle.step_at(y, v, psf, x0, rows, cols, sr, nu=2.0)
+    np.testing.assert_allclose(Bs, B[rows, cols], rtol=1e-12, atol=1e-12 * np.abs(B).max())
+    np.testing.assert_allclose(Ds, D[rows, cols], rtol=1e-12)
+    np.testing.assert_allclose(xs, x1[rows, cols], rtol=1e-12)
+
+
 def test_rejects_bad_nu():
     y, v, psf, _ = small_problem(6, 6, 2, 3, seed=88)
     with pytest.raises(ValueError):
