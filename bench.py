@@ -70,30 +70,41 @@ def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_sources_sha() -> str:
+# The files that hold a form's kernel code; a recorded traffic figure is tied to
+# their contents.
+KERNEL_FILES = {
+    (prec, 1): ["em_mfma.hip", "em_mfma_common.h", "em_device.h"]
+    for prec in ("fp16split", "bf16split", "bf16")
+}
+KERNEL_FILES.update({(prec, 2): ["em_mfma2.hip", "em_mfma_common.h", "em_device.h"]
+                     for prec in ("fp16split", "bf16split", "bf16")})
+KERNEL_FILES[("fp32", 1)] = KERNEL_FILES[("fp32", 2)] = ["em_fp32.hip", "em_device.h"]
+
+
+def kernel_sources_sha(prec: str, sr: int = 1) -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2302_05804_amd", "csrc")
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".h", ".cpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode())
-                h.update(f.read())
+    for name in KERNEL_FILES[(prec, sr)]:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def recorded_traffic(kernel_key: str):
+def recorded_traffic(kernel: str, workload: str, prec: str, sr: int):
     """HBM bytes per launch from committed rocprofv3 --pmc summaries, scaled by the
-    copy-kernel calibration; None if absent or taken on different kernel sources."""
+    copy-kernel calibration; None if absent or taken on other kernel sources."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.txt")
     if not os.path.exists(path):
         return None
-    sha = kernel_sources_sha()
+    sha = kernel_sources_sha(prec, sr)
+    key = f"{kernel}-{workload}-{prec}"
     for line in open(path):
         line = line.strip()
         if not line or line.startswith("#"):
             continue
         fields = dict(kv.split("=", 1) for kv in line.split() if "=" in kv)
-        if fields.get("kernel") == kernel_key and fields.get("sources") == sha:
+        if fields.get("kernel") == key and fields.get("sources") == sha:
             return float(fields["bytes_per_launch"])
     return None
 
@@ -197,7 +208,7 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
         "roofline": {"bound": "mfma" if mf else "alu", "kernel": name,
                      "achieved": round(achieved, 2), "peak": peak, "unit": "TFLOP/s",
                      "frac": round(achieved / peak, 4),
-                     "traffic": recorded_traffic(f"{name}-{prob.name}-{prec_name}")},
+                     "traffic": recorded_traffic(name, prob.name, prec_name, prob.sr)},
     }
 
 

@@ -15,15 +15,21 @@
 // (Kingma & Ba, 2015, Algorithm 1), the step lr max(f) decay^((k-1)/(S-1))
 // and the projection max(h, 0).
 //
-// Layout: one workgroup of PSF_NT threads per frame; A, A^T, f, rho, T, U and
-// two buffers of h (read one, write the other: one barrier per product) in
-// LDS, every row padded to a multiple of 4 floats so that the right operand of
-// each product is read 16 bytes at a time.  Each thread owns up to PSF_TPT
-// 1 x 4 strips of h and keeps their Adam moments in registers for the whole
-// run.  Arithmetic is binary32 except the schedule scalars and the final
-// objective (binary64).
+// Layout: one workgroup per frame; A, A^T, f, rho, T^T, U^T and two buffers of
+// h (read one, write the other) in LDS, each padded with zeros to KP x KP
+// (KP the multiple of 16 at or above Kf and Kh).  The products run on the
+// matrix cores in binary32 (v_mfma_f32_16x16x4f32), one 16 x 16 output block
+// per wave, so a workgroup has (KP/16)^2 waves; each lane reads 16-byte runs of
+// its row of the left operand and of the transposed right operand, and the
+// products that feed another one store their result transposed (T^T, U^T) so
+// that the next product reads it the same way.  A lane keeps the Adam moments
+// of the four pixels of its accumulator for the whole run.  One barrier
+// follows each product.  Arithmetic is binary32 except the schedule scalars
+// and the final objective (binary64).
 #include <hip/hip_runtime.h>
 #include <math.h>
+
+#include <algorithm>
 
 #include "em_device.h"
 #include "em_internal.h"
@@ -31,181 +37,170 @@
 namespace em {
 namespace {
 
-constexpr int PSF_NT = 512;
-constexpr int PSF_TPT = (PSF_K_MAX * ((PSF_K_MAX + 3) / 4) + PSF_NT - 1) / PSF_NT;
+typedef __attribute__((ext_vector_type(4))) float psf_f32x4;
 
-__host__ __device__ constexpr int pad4(int k) { return (k + 3) & ~3; }
-
-struct PsfLds {
-  float *A, *At, *F, *R, *T, *U, *H0, *H1;
-  double* red;
+// Every matrix is held padded to KP x KP (KP = 16, 32, 48 or 64, the multiple of
+// 16 at or above Kf and Kh) with zeros outside its Kf / Kh extent, rows PP
+// floats apart.  One wave per 16 x 16 output block.
+template <int KP>
+struct PsfShape {
+  static constexpr int NB = KP / 16;          // output blocks per side
+  static constexpr int NW = NB * NB;          // waves (one block each)
+  static constexpr int NT = 64 * NW;
+  static constexpr int KS = KP / 4;           // k values per lane group
+  static constexpr int PP = KP + 4;           // row pitch (floats)
+  static constexpr int MAT = KP * PP;         // floats per matrix
+  static constexpr int NMAT = 8;              // A, At, F, R, Tt, Ut, H0, H1
 };
 
-__host__ __device__ inline size_t psf_lds_floats(int kf, int kh) {
-  const int pf = pad4(kf), ph = pad4(kh);
-  return (size_t)kf * ph * 2 + (size_t)kh * pf * 2 + (size_t)kf * pf * 2 + (size_t)kh * ph * 2;
-}
-
-// out[r][c..c+3] = sum_{k < K} L[r][k] R[k][c..c+3]
-__device__ inline float4 row_times(const float* L, int ldl, const float* R, int ldr, int r, int c,
-                                   int K) {
-  float4 acc = make_float4(0.f, 0.f, 0.f, 0.f);
-  const float* lp = L + r * ldl;
-  const float* rp = R + c;
-#pragma unroll 4
-  for (int k = 0; k < K; ++k) {
-    const float l = lp[k];
-    const float4 b = *reinterpret_cast<const float4*>(rp + k * ldr);
-    acc.x = fmaf(l, b.x, acc.x);
-    acc.y = fmaf(l, b.y, acc.y);
-    acc.z = fmaf(l, b.z, acc.z);
-    acc.w = fmaf(l, b.w, acc.w);
+// C block (bm, bn) of L * R with R given transposed (Rt[n][k]): lane i supplies
+// L[16 bm + i%16][k] and Rt[16 bn + i%16][k] for the k values of its lane group
+// g = i/16, k in [g KS, g KS + KS).  The matrix instruction sums its four lane
+// groups, so every k is taken once.  Returns C[16 bm + 4 g + j][16 bn + i%16]
+// in element j.
+template <int KP>
+__device__ inline psf_f32x4 psf_block(const float* L, const float* Rt, int bm, int bn) {
+  using S = PsfShape<KP>;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const float* lp = L + (16 * bm + r) * S::PP + g * S::KS;
+  const float* rp = Rt + (16 * bn + r) * S::PP + g * S::KS;
+  psf_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int c = 0; c < S::KS; c += 4) {
+    const float4 a4 = *reinterpret_cast<const float4*>(lp + c);
+    const float4 b4 = *reinterpret_cast<const float4*>(rp + c);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc, 0, 0, 0);
   }
   return acc;
 }
 
-// T = h A^T (kh x kf), then rho = A T - f (kf x kf); pads of T and rho are 0.
-__device__ inline void psf_residual(const PsfLds& s, const float* H, int kf, int kh) {
-  const int pf = pad4(kf), ph = pad4(kh);
-  for (int q = threadIdx.x; q < kh * (pf / 4); q += PSF_NT) {
-    const int a = q / (pf / 4), c = (q % (pf / 4)) * 4;
-    *reinterpret_cast<float4*>(s.T + a * pf + c) = row_times(H, ph, s.At, pf, a, c, kh);
-  }
+// Tt = (h A^T)^T, then R = A T - F (pads stay 0: A and F are 0 there).
+template <int KP>
+__device__ inline void psf_residual(const float* A, const float* H, const float* F, float* Tt,
+                                    float* R, int bm, int bn) {
+  using S = PsfShape<KP>;
+  const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
+  const psf_f32x4 t = psf_block<KP>(H, A, bm, bn);            // T[a][J], a = 16bm+4g+j
+  *reinterpret_cast<psf_f32x4*>(Tt + (16 * bn + r) * S::PP + 16 * bm + 4 * g) = t;
   __syncthreads();
-  for (int q = threadIdx.x; q < kf * (pf / 4); q += PSF_NT) {
-    const int I = q / (pf / 4), c = (q % (pf / 4)) * 4;
-    float4 m = row_times(s.A, ph, s.T, pf, I, c, kh);
-    const float4 fv = *reinterpret_cast<const float4*>(s.F + I * pf + c);
-    m.x -= fv.x;
-    m.y -= fv.y;
-    m.z -= fv.z;
-    m.w -= fv.w;
-    *reinterpret_cast<float4*>(s.R + I * pf + c) = m;
+  const psf_f32x4 m = psf_block<KP>(A, Tt, bm, bn);           // M[I][J], I = 16bm+4g+j
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int o = (16 * bm + 4 * g + j) * S::PP + 16 * bn + r;
+    R[o] = m[j] - F[o];
   }
   __syncthreads();
 }
 
-__device__ inline float h_at(const float* H, int ph, int kh, int a, int b) {
-  return (a >= 0 && a < kh && b >= 0 && b < kh) ? H[a * ph + b] : 0.f;
-}
-
-__global__ __launch_bounds__(PSF_NT) void psf_fit_kernel(PsfParams P, const float* __restrict__ f,
-                                                        const float* __restrict__ h0,
-                                                        float* __restrict__ hout,
-                                                        double* __restrict__ objective) {
+template <int KP>
+__global__ __launch_bounds__(PsfShape<KP>::NT) void psf_fit_kernel(PsfParams P,
+                                                                  const float* __restrict__ f,
+                                                                  const float* __restrict__ h0,
+                                                                  float* __restrict__ hout,
+                                                                  double* __restrict__ objective) {
+  using S = PsfShape<KP>;
   extern __shared__ float4 psf_smem4[];
   float* sm = reinterpret_cast<float*>(psf_smem4);
+  float* A = sm;
+  float* At = A + S::MAT;
+  float* F = At + S::MAT;
+  float* R = F + S::MAT;
+  float* Tt = R + S::MAT;
+  float* Ut = Tt + S::MAT;
+  float* Hc = Ut + S::MAT;
+  float* Hn = Hc + S::MAT;
+  double* red = reinterpret_cast<double*>(Hn + S::MAT);
   const int kf = P.kf, kh = P.kh, D = P.D;
-  const int pf = pad4(kf), ph = pad4(kh);
   const int t = blockIdx.x, tid = threadIdx.x;
-  PsfLds s;
-  s.A = sm;
-  s.At = s.A + kf * ph;
-  s.F = s.At + kh * pf;
-  s.R = s.F + kf * pf;
-  s.T = s.R + kf * pf;
-  s.U = s.T + kh * pf;
-  s.H0 = s.U + kf * ph;
-  s.H1 = s.H0 + kh * ph;
-  s.red = reinterpret_cast<double*>(s.H1 + kh * ph);
-  const int nfl = (int)psf_lds_floats(kf, kh);
-  for (int i = tid; i < nfl; i += PSF_NT) sm[i] = 0.f;
+  const int w = tid >> 6, lane = tid & 63, g = lane >> 4, r = lane & 15;
+  const int bm = w / S::NB, bn = w % S::NB;
+  for (int i = tid; i < S::NMAT * S::MAT; i += S::NT) sm[i] = 0.f;
   __syncthreads();
 
-  // A and A^T from the 1-D Gaussian (binary64, rounded once)
+  // A[I][a] = sum over the D fine rows of coarse row I of g1(p - anchor - (a - ch)),
+  // g1 the unit-sum 1-D Gaussian (binary64, rounded once); A^T beside it
   const int ch = (kh - 1) / 2, anchor = D * ((kf - 1) / 2);
   const double sg = (double)P.sigma;
   const int rg = sg > 0.0 ? (int)ceil(4.0 * sg) : 0;
   double Z = 0.0;
   for (int d = -rg; d <= rg; ++d) Z += sg > 0.0 ? exp(-(double)(d * d) / (2.0 * sg * sg)) : 1.0;
-  for (int q = tid; q < kf * kh; q += PSF_NT) {
+  for (int q = tid; q < kf * kh; q += S::NT) {
     const int I = q / kh, a = q % kh;
     double v = 0.0;
     for (int p = D * I; p < D * I + D; ++p) {
       const int d = p - anchor - (a - ch);
       if (d >= -rg && d <= rg) v += sg > 0.0 ? exp(-(double)(d * d) / (2.0 * sg * sg)) : 1.0;
     }
-    s.A[I * ph + a] = (float)(v / Z);
-    s.At[a * pf + I] = (float)(v / Z);
+    A[I * S::PP + a] = (float)(v / Z);
+    At[a * S::PP + I] = (float)(v / Z);
   }
   // f, its maximum, and the start h
   const float* ft = f + (size_t)t * kf * kf;
   float fmax = 0.f;
-  for (int q = tid; q < kf * kf; q += PSF_NT) {
+  for (int q = tid; q < kf * kf; q += S::NT) {
     const float v = ft[q];
-    s.F[(q / kf) * pf + q % kf] = v;
+    F[(q / kf) * S::PP + q % kf] = v;
     fmax = fmaxf(fmax, v);
   }
-  for (int q = tid; q < kh * kh; q += PSF_NT) {
+  for (int q = tid; q < kh * kh; q += S::NT) {
     const int a = q / kh, b = q % kh;
     float v;
     if (h0) {
       v = h0[(size_t)t * kh * kh + q];
     } else {
-      const int p = a - ch + anchor, r = b - ch + anchor;
+      const int p = a - ch + anchor, c2 = b - ch + anchor;
       v = 0.f;
-      if (p >= 0 && p < D * kf && r >= 0 && r < D * kf)
-        v = fmaxf(ft[(p / D) * kf + r / D] / (float)(D * D), 0.f);
+      if (p >= 0 && p < D * kf && c2 >= 0 && c2 < D * kf)
+        v = fmaxf(ft[(p / D) * kf + c2 / D] / (float)(D * D), 0.f);
     }
-    s.H0[a * ph + b] = v;
+    Hc[a * S::PP + b] = v;
   }
-  // block maximum of f (reduction through the doubles of s.red)
-  {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) fmax = fmaxf(fmax, __shfl_xor(fmax, off, 64));
-    if ((tid & 63) == 0) s.red[tid >> 6] = (double)fmax;
-    __syncthreads();
-    for (int w = 0; w < PSF_NT / 64; ++w) fmax = fmaxf(fmax, (float)s.red[w]);
-    __syncthreads();
-  }
+  for (int off = 32; off > 0; off >>= 1) fmax = fmaxf(fmax, __shfl_xor(fmax, off, 64));
+  if (lane == 0) red[w] = (double)fmax;
+  __syncthreads();
+  for (int i = 0; i < S::NW; ++i) fmax = fmaxf(fmax, (float)red[i]);
+  __syncthreads();
 
-  // Adam state of the owned strips
-  float m1[PSF_TPT][4], m2[PSF_TPT][4];
-#pragma unroll
-  for (int j = 0; j < PSF_TPT; ++j)
-#pragma unroll
-    for (int e = 0; e < 4; ++e) m1[j][e] = m2[j][e] = 0.f;
-
+  // Adam state of the lane's four pixels (a = 16 bm + 4 g + j, b = 16 bn + r)
+  float m1[4] = {0.f, 0.f, 0.f, 0.f}, m2[4] = {0.f, 0.f, 0.f, 0.f};
   const double lr0 = (double)P.lr * (double)fmax;
   const double ldec = P.S > 1 ? log((double)P.decay) / (double)(P.S - 1) : 0.0;
   const float b1 = P.b1, b2 = P.b2, eps = P.eps, lam2 = 2.f * P.lam;
+  const int b = 16 * bn + r;
   double b1k = 1.0, b2k = 1.0;
-  float* Hc = s.H0;
-  float* Hn = s.H1;
   for (int k = 1; k <= P.S; ++k) {
-    psf_residual(s, Hc, kf, kh);
-    // U = rho A (kf x kh)
-    for (int q = tid; q < kf * (ph / 4); q += PSF_NT) {
-      const int I = q / (ph / 4), c = (q % (ph / 4)) * 4;
-      *reinterpret_cast<float4*>(s.U + I * ph + c) = row_times(s.R, pf, s.A, ph, I, c, kf);
-    }
+    psf_residual<KP>(A, Hc, F, Tt, R, bm, bn);
+    // U = rho A, stored transposed (Ut[b][I])
+    const psf_f32x4 u = psf_block<KP>(R, At, bm, bn);
+    *reinterpret_cast<psf_f32x4*>(Ut + (16 * bn + r) * S::PP + 16 * bm + 4 * g) = u;
     __syncthreads();
+    // gradient 2 A^T U + 2 lambda L h, Adam, projection
+    const psf_f32x4 gd = psf_block<KP>(At, Ut, bm, bn);
     b1k *= (double)b1;
     b2k *= (double)b2;
     const float lrk = (float)(lr0 * exp(ldec * (double)(k - 1)));
     const float c1 = (float)(1.0 - b1k), c2 = (float)(1.0 - b2k);
 #pragma unroll
-    for (int j = 0; j < PSF_TPT; ++j) {
-      const int q = tid + j * PSF_NT;
-      if (q < kh * (ph / 4)) {
-        const int a = q / (ph / 4), c = (q % (ph / 4)) * 4;
-        const float4 gd = row_times(s.At, pf, s.U, ph, a, c, kf);
-        const float gv[4] = {gd.x, gd.y, gd.z, gd.w};
-        float hn[4];
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int b = c + e;
-          const float hv = h_at(Hc, ph, kh, a, b);
-          const float nb = h_at(Hc, ph, kh, a - 1, b) + h_at(Hc, ph, kh, a + 1, b) +
-                           h_at(Hc, ph, kh, a, b - 1) + h_at(Hc, ph, kh, a, b + 1);
-          const float g = 2.f * gv[e] + lam2 * (4.f * hv - nb);
-          m1[j][e] = b1 * m1[j][e] + (1.f - b1) * g;
-          m2[j][e] = b2 * m2[j][e] + (1.f - b2) * g * g;
-          const float step = lrk * (m1[j][e] / c1) / (sqrtf(m2[j][e] / c2) + eps);
-          hn[e] = b < kh ? fmaxf(hv - step, 0.f) : 0.f;
-        }
-        *reinterpret_cast<float4*>(Hn + a * ph + c) = make_float4(hn[0], hn[1], hn[2], hn[3]);
+    for (int j = 0; j < 4; ++j) {
+      const int a = 16 * bm + 4 * g + j;
+      float hn = 0.f;
+      if (a < kh && b < kh) {
+        const float hv = Hc[a * S::PP + b];
+        const float nb = (a > 0 ? Hc[(a - 1) * S::PP + b] : 0.f) +
+                         (a + 1 < kh ? Hc[(a + 1) * S::PP + b] : 0.f) +
+                         (b > 0 ? Hc[a * S::PP + b - 1] : 0.f) +
+                         (b + 1 < kh ? Hc[a * S::PP + b + 1] : 0.f);
+        const float gr = 2.f * gd[j] + lam2 * (4.f * hv - nb);
+        m1[j] = b1 * m1[j] + (1.f - b1) * gr;
+        m2[j] = b2 * m2[j] + (1.f - b2) * gr * gr;
+        const float step = lrk * (m1[j] / c1) / (sqrtf(m2[j] / c2) + eps);
+        hn = fmaxf(hv - step, 0.f);
       }
+      Hn[a * S::PP + b] = hn;
     }
     __syncthreads();
     float* tmp = Hc;
@@ -214,41 +209,60 @@ __global__ __launch_bounds__(PSF_NT) void psf_fit_kernel(PsfParams P, const floa
   }
 
   float* ht = hout + (size_t)t * kh * kh;
-  for (int q = tid; q < kh * kh; q += PSF_NT) ht[q] = Hc[(q / kh) * ph + q % kh];
+  for (int q = tid; q < kh * kh; q += S::NT) ht[q] = Hc[(q / kh) * S::PP + q % kh];
   if (objective) {
-    psf_residual(s, Hc, kf, kh);
+    psf_residual<KP>(A, Hc, F, Tt, R, bm, bn);
     double part = 0.0;
-    for (int q = tid; q < kf * kf; q += PSF_NT) {
-      const double r = (double)s.R[(q / kf) * pf + q % kf];
-      part += r * r;
+    for (int q = tid; q < kf * kf; q += S::NT) {
+      const double rr = (double)R[(q / kf) * S::PP + q % kf];
+      part += rr * rr;
     }
     double pen = 0.0;
-    for (int q = tid; q < (kh + 1) * kh; q += PSF_NT) {
-      // pair (i, i+1) in column j and pair (j, j+1) in row j' = i (transposed)
+    auto hat = [&](int i, int j) -> double {
+      return (i >= 0 && i < kh && j >= 0 && j < kh) ? (double)Hc[i * S::PP + j] : 0.0;
+    };
+    for (int q = tid; q < (kh + 1) * kh; q += S::NT) {
+      // pair (i, i+1) in column j, and pair (i, i+1) along row j
       const int i = q / kh - 1, j = q % kh;
-      const double dv = (double)h_at(Hc, ph, kh, i + 1, j) - (double)h_at(Hc, ph, kh, i, j);
-      const double dh = (double)h_at(Hc, ph, kh, j, i + 1) - (double)h_at(Hc, ph, kh, j, i);
+      const double dv = hat(i + 1, j) - hat(i, j);
+      const double dh = hat(j, i + 1) - hat(j, i);
       pen += dv * dv + dh * dh;
     }
-    const double tot = block_sum<PSF_NT>(part + (double)P.lam * pen, s.red);
+    const double tot = block_sum<S::NT>(part + (double)P.lam * pen, red);
     if (tid == 0) objective[t] = tot;
   }
+}
+
+inline int psf_kp(int kf, int kh) { return 16 * ((std::max(kf, kh) + 15) / 16); }
+
+template <int KP>
+hipError_t launch_kp(const PsfParams& P, const float* f, const float* h0, float* h,
+                     double* objective, hipStream_t s) {
+  using S = PsfShape<KP>;
+  const size_t lds = (size_t)S::NMAT * S::MAT * sizeof(float) + S::NW * sizeof(double);
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&psf_fit_kernel<KP>),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(psf_fit_kernel<KP>, dim3(P.n), dim3(S::NT), lds, s, P, f, h0, h, objective);
+  return hipGetLastError();
 }
 
 }  // namespace
 
 size_t psf_lds_bytes(int kf, int kh) {
-  return psf_lds_floats(kf, kh) * sizeof(float) + (PSF_NT / 64) * sizeof(double);
+  const int kp = psf_kp(kf, kh);
+  return (size_t)8 * kp * (kp + 4) * sizeof(float) + (size_t)(kp / 16) * (kp / 16) * sizeof(double);
 }
 
 hipError_t launch_psf_fit(const PsfParams& P, const float* f, const float* h0, float* h,
                           double* objective, hipStream_t s) {
-  const size_t lds = psf_lds_bytes(P.kf, P.kh);
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&psf_fit_kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(psf_fit_kernel, dim3(P.n), dim3(PSF_NT), lds, s, P, f, h0, h, objective);
-  return hipGetLastError();
+  switch (psf_kp(P.kf, P.kh)) {
+    case 16: return launch_kp<16>(P, f, h0, h, objective, s);
+    case 32: return launch_kp<32>(P, f, h0, h, objective, s);
+    case 48: return launch_kp<48>(P, f, h0, h, objective, s);
+    case 64: return launch_kp<64>(P, f, h0, h, objective, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 }  // namespace em
