@@ -64,17 +64,21 @@ __device__ inline psf_f32x4 psf_block(const float* L, const float* Rt, int bm, i
   const int lane = threadIdx.x & 63, g = lane >> 4, r = lane & 15;
   const float* lp = L + (16 * bm + r) * S::PP + g * S::KS;
   const float* rp = Rt + (16 * bn + r) * S::PP + g * S::KS;
-  psf_f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+  // four independent accumulators, so that consecutive matrix instructions do
+  // not wait for each other's results
+  psf_f32x4 acc[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) acc[e] = psf_f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
   for (int c = 0; c < S::KS; c += 4) {
     const float4 a4 = *reinterpret_cast<const float4*>(lp + c);
     const float4 b4 = *reinterpret_cast<const float4*>(rp + c);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc, 0, 0, 0);
+    acc[0] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.x, b4.x, acc[0], 0, 0, 0);
+    acc[1] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.y, b4.y, acc[1], 0, 0, 0);
+    acc[2] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.z, b4.z, acc[2], 0, 0, 0);
+    acc[3] = __builtin_amdgcn_mfma_f32_16x16x4f32(a4.w, b4.w, acc[3], 0, 0, 0);
   }
-  return acc;
+  return (acc[0] + acc[1]) + (acc[2] + acc[3]);
 }
 
 // Tt = (h A^T)^T, then R = A T - F (pads stay 0: A and F are 0 there).
@@ -167,8 +171,9 @@ __global__ __launch_bounds__(PsfShape<KP>::NT) void psf_fit_kernel(PsfParams P,
 
   // Adam state of the lane's four pixels (a = 16 bm + 4 g + j, b = 16 bn + r)
   float m1[4] = {0.f, 0.f, 0.f, 0.f}, m2[4] = {0.f, 0.f, 0.f, 0.f};
-  const double lr0 = (double)P.lr * (double)fmax;
-  const double ldec = P.S > 1 ? log((double)P.decay) / (double)(P.S - 1) : 0.0;
+  // step k uses lr max(f) decay^((k-1)/(S-1)): a running product in binary64
+  double lrk_d = (double)P.lr * (double)fmax;
+  const double rdec = P.S > 1 ? exp(log((double)P.decay) / (double)(P.S - 1)) : 1.0;
   const float b1 = P.b1, b2 = P.b2, eps = P.eps, lam2 = 2.f * P.lam;
   const int b = 16 * bn + r;
   double b1k = 1.0, b2k = 1.0;
@@ -182,7 +187,8 @@ __global__ __launch_bounds__(PsfShape<KP>::NT) void psf_fit_kernel(PsfParams P,
     const psf_f32x4 gd = psf_block<KP>(At, Ut, bm, bn);
     b1k *= (double)b1;
     b2k *= (double)b2;
-    const float lrk = (float)(lr0 * exp(ldec * (double)(k - 1)));
+    const float lrk = (float)lrk_d;
+    lrk_d *= rdec;
     const float c1 = (float)(1.0 - b1k), c2 = (float)(1.0 - b2k);
 #pragma unroll
     for (int j = 0; j < 4; ++j) {

@@ -65,6 +65,34 @@ def test_run_matches_oracle(sr, prec_name):
         assert (np.diff(trg) >= -1e-6 * np.abs(trg[1:])).all()
 
 
+@pytest.mark.parametrize("case", ["n1_k15", "tiny_frames", "masked_frame", "zero_iters"])
+def test_edge_cases(case):
+    """One frame with a small PSF; frames smaller than the PSF; a frame masked
+    entirely; zero iterations (x0 returned as given)."""
+    em = _em()
+    if case == "n1_k15":
+        p, y, _ = _problem(1, 7600, H=40, W=56, n=1, K=15)
+    elif case == "tiny_frames":
+        p, y, _ = _problem(2, 7610, H=6, W=10, n=3, K=43)
+    else:
+        p, y, _ = _problem(1, 7620, H=48, W=40, n=3, K=43)
+    v = p.v.copy()
+    if case == "masked_frame":
+        y = y.copy()
+        y[1] = np.nan
+        v[1] = np.inf
+    p.v = v
+    x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(y, v, p.sr), 0.25), seed=7630)
+    k = 0 if case == "zero_iters" else 8
+    xg, _ = _run(p, y, 2.5, em.FP32, k, x0)
+    xo = oracle.run_t(y, v, p.psf, x0, k, 2.5, p.sr)
+    err = rel_l2(xg, xo)
+    log(f"  Student-t edge case {case}: rel L2(x) {err:.2e}")
+    assert err <= 1e-5
+    if case == "zero_iters":
+        assert np.array_equal(xg, x0.astype(np.float64))
+
+
 @pytest.mark.parametrize("sr", [1, 2])
 def test_terms_and_loglik(sr):
     import torch
