@@ -187,8 +187,9 @@ int em_terms(em_ctx* ctx, float* B_out, float* Dn_out);
  *                                     the adjoint is not split over frame groups)
  *   phase_ms[2]  the separate update kernel (0 when fused)
  *   phase_ms[3]  the whole iteration
- * Under EM_W_STUDENT_T phase_ms[0] is the forward kernel (raw F_t x) plus the
- * weight kernel, and the numerator's adjoint counts in phase_ms[3] only.
+ * Under EM_W_STUDENT_T phase_ms[0] is the forward kernel with the E-step
+ * weights in its epilogue, and the numerator's adjoint counts in phase_ms[3]
+ * only.
  * Synchronous.
  */
 int em_profile(em_ctx* ctx, int32_t n_iter, double* phase_ms);

@@ -393,23 +393,31 @@ static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
   return EM_OK;
 }
 
-// Student-t noise: r = F x (raw forward), then the E-step weights turn it into
-// r = u w F x and ry = u w y, with loglik partials in part_prep when asked.
+// Student-t noise: the forward epilogue applies the E-step weights, writing
+// r = u w F x and ry = u w y, with Student-t loglik partials when asked.
+static double student_t_lcst(double nu) {
+  return 2.0 * (std::lgamma(0.5 * (nu + 1.0)) - std::lgamma(0.5 * nu) - 0.5 * std::log(nu * M_PI)) +
+         std::log(2.0 * M_PI);
+}
+
 static int robust_forward(em_ctx* c, bool loglik) {
+  const double lcst = student_t_lcst((double)c->g.nu);
   if (uses_mfma(c->g)) {
     MfmaLaunch m;
-    fill_forward_mfma(c, &m, true, false);
-    m.u = nullptr;
+    fill_forward_mfma(c, &m, true, loglik);
+    m.out_y = c->ry;
+    m.nu = c->g.nu;
+    m.lcst = lcst;
     EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_variant, c->pl.fwd_tiles, c->pl.fwd_groups, m,
                        c->stream));
   } else {
     FwdLaunch f;
-    fill_forward_fp32(c, &f, true, false);
-    f.u = nullptr;
+    fill_forward_fp32(c, &f, true, loglik);
+    f.out_y = c->ry;
+    f.nu = c->g.nu;
+    f.lcst = lcst;
     EM_HIP(launch_forward(c->g, c->pl, f, c->stream));
   }
-  EM_HIP(launch_student_t(c->u, c->y, c->r, c->ry, (int64_t)c->g.n * c->g.Nf, c->g.nu,
-                          loglik ? c->part_prep : nullptr, c->pl.prep_blocks, c->stream));
   return EM_OK;
 }
 
@@ -459,10 +467,9 @@ static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
   int n_rc = 0;
   if ((rc = adjoint_update(c, relchange ? c->part_rc : nullptr, &n_rc))) return rc;
   if (loglik || relchange) {
-    const double* pll = !loglik ? nullptr : robust ? c->part_prep : c->part_ll;
-    const int nll = robust ? c->pl.prep_blocks : c->pl.fwd_tiles * c->pl.fwd_groups;
-    EM_HIP(launch_finalize_iter(pll, nll, relchange ? c->part_rc : nullptr, n_rc, c->scalars,
-                                c->trace_ll, c->trace_rc, c->counters, c->stream));
+    EM_HIP(launch_finalize_iter(loglik ? c->part_ll : nullptr, c->pl.fwd_tiles * c->pl.fwd_groups,
+                                relchange ? c->part_rc : nullptr, n_rc, c->scalars, c->trace_ll,
+                                c->trace_rc, c->counters, c->stream));
   }
   return EM_OK;
 }
@@ -654,16 +661,11 @@ int em_iterate_tol(em_ctx* c, int32_t max_iter, double tol, int32_t check_every,
 
 int em_loglik(em_ctx* c, double* out) {
   if (!c || !out) return fail(EM_EINVAL, "NULL argument");
-  if (c->g.weight_mode == EM_W_STUDENT_T) {
-    int rc = robust_forward(c, true);
-    if (rc) return rc;
-    EM_HIP(launch_finalize_loglik(c->part_prep, c->pl.prep_blocks, c->scalars, c->stream));
-  } else {
-    int rc = forward_pass(c, false, true);
-    if (rc) return rc;
-    EM_HIP(launch_finalize_loglik(c->part_ll, c->pl.fwd_tiles * c->pl.fwd_groups, c->scalars,
-                                  c->stream));
-  }
+  int rc = c->g.weight_mode == EM_W_STUDENT_T ? robust_forward(c, true)
+                                              : forward_pass(c, false, true);
+  if (rc) return rc;
+  EM_HIP(launch_finalize_loglik(c->part_ll, c->pl.fwd_tiles * c->pl.fwd_groups, c->scalars,
+                                c->stream));
   EM_HIP(hipMemcpyAsync(out, c->scalars + S_LOGLIK, sizeof(double), hipMemcpyDeviceToHost,
                         c->stream));
   EM_HIP(hipStreamSynchronize(c->stream));
@@ -814,8 +816,14 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
       MfmaLaunch m;
       int tiles, groups;
       if (dir == 0) {
-        // the forward writes r, which every iteration recomputes before use
+        // the forward writes r (and u w y under Student-t noise), which every
+        // iteration recomputes before use
         fill_forward_mfma(c, &m, true, false);
+        if (c->g.weight_mode == EM_W_STUDENT_T) {
+          m.out_y = c->ry;
+          m.nu = c->g.nu;
+          m.lcst = student_t_lcst((double)c->g.nu);
+        }
         tiles = c->pl.fwd_tiles;
         groups = c->pl.fwd_groups;
       } else {

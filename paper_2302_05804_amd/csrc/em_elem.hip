@@ -316,58 +316,6 @@ hipError_t launch_upsample(const float* y, const float* v, int n, int Hf, int Wf
   return hipGetLastError();
 }
 
-// Student-t noise (the heavier-tailed noise the paper names as future work):
-// the E-step weight w = (nu + 1) / (nu + u (y - m)^2) of every observed pixel at
-// the current iterate, applied before the adjoints.  In: r = m = F_t x (raw).
-// Out: r = u w m (input of the denominator's adjoint), ry = u w y (input of the
-// numerator's adjoint); masked pixels give 0.  With `part`, block partials of
-// (nu + 1) ln(1 + u (y - m)^2 / nu) - cst, cst = 2 (lgamma((nu+1)/2) -
-// lgamma(nu/2) - ln(nu pi)/2) + ln(2 pi): with the prep's sum of ln(2 pi v)
-// they give l(x) through the same -1/2 (sum + const) as the Gaussian case.
-__global__ __launch_bounds__(EW_NT) void student_t_kernel(const float* __restrict__ u,
-                                                          const float* __restrict__ y,
-                                                          float* __restrict__ r,
-                                                          float* __restrict__ ry, int64_t count,
-                                                          float nu, double cst,
-                                                          double* __restrict__ part) {
-  __shared__ double red[EW_NT / 64];
-  const float nu1 = nu + 1.f;
-  double llp = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * EW_NT;
-  for (int64_t p = (int64_t)blockIdx.x * EW_NT + threadIdx.x; p < count; p += stride) {
-    const float uu = u[p];
-    const float m = r[p];
-    float ro = 0.f, ryo = 0.f;
-    if (uu > 0.f) {
-      const float yy = y[p];
-      const float d = yy - m;
-      const float w = nu1 / (nu + uu * d * d);
-      ro = (uu * w) * m;
-      ryo = (uu * w) * yy;
-      if (part) {
-        const double dd = (double)yy - (double)m;
-        llp += ((double)nu + 1.0) * log1p((double)uu * dd * dd / (double)nu) - cst;
-      }
-    }
-    r[p] = ro;
-    ry[p] = ryo;
-  }
-  if (part) {
-    const double sblk = block_sum<EW_NT>(llp, red);
-    if (threadIdx.x == 0) part[blockIdx.x] = sblk;
-  }
-}
-
-hipError_t launch_student_t(const float* u, const float* y, float* r, float* ry, int64_t count,
-                            float nu, double* part, int blocks, hipStream_t s) {
-  const double nd = (double)nu;
-  const double cst = 2.0 * (lgamma(0.5 * (nd + 1.0)) - lgamma(0.5 * nd) - 0.5 * log(nd * M_PI)) +
-                     log(2.0 * M_PI);
-  hipLaunchKernelGGL(student_t_kernel, dim3(blocks), dim3(EW_NT), 0, s, u, y, r, ry, count, nu,
-                     cst, part);
-  return hipGetLastError();
-}
-
 hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t s) {
   hipLaunchKernelGGL(copy_kernel, dim3(ew_blocks(count)), dim3(EW_NT), 0, s, src, dst, count);
   return hipGetLastError();

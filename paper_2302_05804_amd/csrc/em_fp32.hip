@@ -24,6 +24,40 @@
 
 namespace em {
 
+// Forward epilogue of one output: m = F_t x raw (u == nullptr); r = u m and
+// the FP64 partial of u (y - m)^2; or, under Student-t noise (out_y), r = u w m,
+// out_y = u w y with w = (nu + 1) / (nu + u (y - m)^2), and the partial of
+// (nu + 1) ln(1 + u (y - m)^2 / nu) - lcst.
+__device__ inline void fwd_store(const FwdLaunch& a, int64_t idx, float m, double& llp) {
+  if (a.u == nullptr) {
+    a.out[idx] = m;
+    return;
+  }
+  const float uu = a.u[idx];
+  if (a.out_y != nullptr) {
+    float ro = 0.f, ryo = 0.f;
+    if (uu > 0.f) {
+      const float y = a.y[idx];
+      const float d = y - m;
+      const float w = (a.nu + 1.f) / (a.nu + uu * d * d);
+      ro = (uu * w) * m;
+      ryo = (uu * w) * y;
+      if (a.part != nullptr) {
+        const double dd = (double)y - (double)m;
+        llp += ((double)a.nu + 1.0) * log1p((double)uu * dd * dd / (double)a.nu) - a.lcst;
+      }
+    }
+    a.out[idx] = ro;
+    a.out_y[idx] = ryo;
+    return;
+  }
+  if (a.out) a.out[idx] = uu * m;
+  if (a.part != nullptr && uu > 0.f) {
+    const double d = (double)a.y[idx] - (double)m;
+    llp += (double)uu * d * d;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // sr = 1 forward:  m_t[i,j] = sum_{a,b} f_t[a,b] x[i+c-a, j+c-b]      (Eq. (1))
 //   epilogue: r_t = u_t m_t (or m_t raw), FP64 partial of u (y - m)^2.
@@ -92,18 +126,7 @@ __device__ inline void fwd1_body(const FwdLaunch& a, const int tile, const int g
       for (int r = 0; r < R; ++r) {
         const int i = i0 + w * R + r;
         if (i < a.Hf) {
-          const int64_t idx = base + (int64_t)i * a.Wf + j;
-          const float m = acc[r];
-          if (a.u == nullptr) {
-            a.out[idx] = m;
-          } else {
-            const float uu = a.u[idx];
-            if (a.out) a.out[idx] = uu * m;
-            if (a.part != nullptr && uu > 0.f) {
-              const double d = (double)a.y[idx] - (double)m;
-              llp += (double)uu * d * d;
-            }
-          }
+          fwd_store(a, base + (int64_t)i * a.Wf + j, acc[r], llp);
         }
       }
     }
@@ -187,18 +210,7 @@ __device__ inline void fwd2_body(const FwdLaunch& a, const int tile, const int g
       for (int r = 0; r < R; ++r) {
         const int I = I0 + w * R + r;
         if (I < a.Hf) {
-          const int64_t idx = base + (int64_t)I * a.Wf + J;
-          const float m = acc[r];
-          if (a.u == nullptr) {
-            a.out[idx] = m;
-          } else {
-            const float uu = a.u[idx];
-            if (a.out) a.out[idx] = uu * m;
-            if (a.part != nullptr && uu > 0.f) {
-              const double d = (double)a.y[idx] - (double)m;
-              llp += (double)uu * d * d;
-            }
-          }
+          fwd_store(a, base + (int64_t)I * a.Wf + J, acc[r], llp);
         }
       }
     }

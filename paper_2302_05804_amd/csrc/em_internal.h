@@ -94,6 +94,12 @@ struct FwdLaunch {
   double* part;        // loglik partials (nullptr => none)
   int n, Hf, Wf, Hl, Wl, fpg;
   int ntiles;          // tiles of the job (partial index = group * ntiles + tile)
+  // Student-t noise (out_y != nullptr): out = u w F_t x, out_y = u w y with the
+  // E-step weight w = (nu + 1) / (nu + u (y - F_t x)^2); loglik partials of
+  // (nu + 1) ln(1 + u (y - F_t x)^2 / nu) - lcst
+  float* out_y;
+  float nu;
+  double lcst;
 };
 
 struct AdjLaunch {
@@ -122,6 +128,9 @@ struct MfmaLaunch {
   int n, H, W, fpg;
   int fused;
   int ntiles;
+  float* out_y;        // forward under Student-t noise (as FwdLaunch)
+  float nu;
+  double lcst;
 };
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s);
@@ -202,11 +211,6 @@ hipError_t launch_reset_counters(int* counters, hipStream_t s);
 hipError_t launch_copy(const float* src, float* dst, int64_t count, hipStream_t s);
 hipError_t launch_upsample(const float* y, const float* v, int n, int Hf, int Wf, int f,
                            float* yu, float* vu, hipStream_t s);
-
-// Student-t noise: E-step weights and the two adjoint inputs (em_elem.hip);
-// `blocks` partials of the log-likelihood into `part` when it is not NULL.
-hipError_t launch_student_t(const float* u, const float* y, float* r, float* ry, int64_t count,
-                            float nu, double* part, int blocks, hipStream_t s);
 
 // Super-resolved PSFs of Eq. (4) (em_psf.hip): one workgroup per frame.
 constexpr int PSF_K_MAX = 63;

@@ -268,8 +268,9 @@ __device__ inline const int* table_exponents(const MfmaLaunch& a) {
                                       (size_t)a.n * C::KTP * 4 * 64 * 16);
 }
 
-// Forward: r_t = u_t * (f_t * x) for the frames of this group, x tile staged once.
-template <class C>
+// Forward: r_t = u_t * (f_t * x) for the frames of this group, x tile staged once
+// (ROB: the Student-t epilogue, which also writes u w y).
+template <class C, bool ROB = false>
 __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const int group) {
   constexpr int c = (C::KT - 1) / 2;
   __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
@@ -313,11 +314,19 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
     // exact removal of the image and PSF scales (scaled encodings)
     const int unscale = C::P::SCALED ? -(sx + table_exponents<C>(a)[t]) : 0;
     // epilogue: per-frame base pointers (wave-uniform) + 32-bit in-frame offsets
-    const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
-    const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;
-    float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
-    llp += forward_epilogue<C::BR, C::BC>(acc, unscale, BlockPos{k0 + row_base, l0 + col_base, 1},
-                                          a.H, a.W, ut, yt, ot);
+    if constexpr (ROB) {
+      llp += forward_epilogue_t<C::BR, C::BC>(
+          acc, unscale, BlockPos{k0 + row_base, l0 + col_base, 1}, a.H, a.W, a.u + (int64_t)t * N,
+          a.y + (int64_t)t * N, a.out + (int64_t)t * N, a.out_y + (int64_t)t * N, a.nu, a.lcst,
+          a.part != nullptr);
+    } else {
+      const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
+      const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;
+      float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
+      llp += forward_epilogue<C::BR, C::BC>(acc, unscale,
+                                            BlockPos{k0 + row_base, l0 + col_base, 1}, a.H, a.W,
+                                            ut, yt, ot);
+    }
   }
   if (a.part != nullptr) {
     const double s = block_sum<C::NT>(llp, red);
@@ -410,6 +419,10 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
 template <class C>
 __global__ __launch_bounds__(C::NT) void mfma_fwd_kernel(MfmaLaunch a) {
   mfma_fwd_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd_t_kernel(MfmaLaunch a) {
+  mfma_fwd_body<C, true>(a, blockIdx.x, blockIdx.y);
 }
 template <class C>
 __global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
@@ -525,7 +538,11 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
   static_assert(C0::TH == MF_TILE && C0::TW == MF_TILE, "tile");
   static_assert(C1::TH == MF_TILE && C1::TW == MF_TILE, "tile");
   static_assert(C2::TH == MF_TILE && C2::TW == MF_TILE, "tile");
-  if (dir == 0) {
+  if (dir == 0 && a.out_y != nullptr) {
+    if (variant == 1) hipLaunchKernelGGL(mfma_fwd_t_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
+    else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_t_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
+    else hipLaunchKernelGGL(mfma_fwd_t_kernel<C0>, grid, dim3(C0::NT), 0, s, a);
+  } else if (dir == 0) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
     else hipLaunchKernelGGL(mfma_fwd_kernel<C0>, grid, dim3(C0::NT), 0, s, a);

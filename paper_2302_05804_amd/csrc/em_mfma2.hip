@@ -169,7 +169,7 @@ __device__ inline void m2f_frame_lds(const unsigned short (*sh)[C::ROWS * C::PIT
   }
 }
 
-template <class C>
+template <class C, bool ROB = false>
 __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int group) {
   __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[C::NW];
@@ -223,11 +223,18 @@ __device__ inline void m2f_body(const MfmaLaunch& a, const int tile, const int g
     }
     const int unscale =
         C::P::SCALED ? -(sx + m2_table_exponents(a, M2_FWD_FRAME_BYTES)[t]) : 0;
-    const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
-    const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;
-    float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
-    llp += forward_epilogue<C::BR, C::BC>(
-        acc, unscale, BlockPos{I0 + wr * 16 * C::BR, J0 + wc * 16 * C::BC, 1}, a.H, a.W, ut, yt, ot);
+    const BlockPos pos{I0 + wr * 16 * C::BR, J0 + wc * 16 * C::BC, 1};
+    if constexpr (ROB) {
+      llp += forward_epilogue_t<C::BR, C::BC>(acc, unscale, pos, a.H, a.W, a.u + (int64_t)t * N,
+                                              a.y + (int64_t)t * N, a.out + (int64_t)t * N,
+                                              a.out_y + (int64_t)t * N, a.nu, a.lcst,
+                                              a.part != nullptr);
+    } else {
+      const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
+      const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;
+      float* ot = a.out ? a.out + (int64_t)t * N : nullptr;
+      llp += forward_epilogue<C::BR, C::BC>(acc, unscale, pos, a.H, a.W, ut, yt, ot);
+    }
   }
   if (a.part != nullptr) {
     const double s = block_sum<C::NT>(llp, red);
@@ -483,6 +490,10 @@ __global__ __launch_bounds__(C::NT) void m2f_kernel(MfmaLaunch a) {
   m2f_body<C>(a, blockIdx.x, blockIdx.y);
 }
 template <class C>
+__global__ __launch_bounds__(C::NT) void m2f_t_kernel(MfmaLaunch a) {
+  m2f_body<C, true>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
 __global__ __launch_bounds__(C::NT) void m2a_kernel(MfmaLaunch a) {
   m2a_body<C>(a, blockIdx.x, blockIdx.y);
 }
@@ -624,7 +635,11 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
     else                                                                                \
       hipLaunchKernelGGL(KER##_kernel<CFG>, grid, dim3(CFG::NT), 0, s, a);              \
   } while (0)
-  if (dir == 0) {
+  if (dir == 0 && !batched && a.out_y != nullptr) {
+    if (variant == 1) hipLaunchKernelGGL(m2f_t_kernel<F1>, grid, dim3(F1::NT), 0, s, a);
+    else if (variant == 2) hipLaunchKernelGGL(m2f_t_kernel<F2>, grid, dim3(F2::NT), 0, s, a);
+    else hipLaunchKernelGGL(m2f_t_kernel<F0>, grid, dim3(F0::NT), 0, s, a);
+  } else if (dir == 0) {
     if (variant == 1) EM_M2_LAUNCH(m2f, F1);
     else if (variant == 2) EM_M2_LAUNCH(m2f, F2);
     else EM_M2_LAUNCH(m2f, F0);

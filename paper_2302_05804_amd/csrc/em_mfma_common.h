@@ -277,6 +277,59 @@ __device__ inline double forward_epilogue_w(const f32x4 (&acc)[BR][BC], int unsc
   return llp;
 }
 
+// Forward epilogue under Student-t noise: with m = F_t x and the E-step weight
+// w = (nu + 1) / (nu + u (y - m)^2) of each observed pixel, out = u w m and
+// out_y = u w y (0 where u = 0); with `ll`, the FP64 partial of
+// (nu + 1) ln(1 + u (y - m)^2 / nu) - lcst.  Loads first, as below.
+template <int BR, int BC>
+__device__ inline double forward_epilogue_t(const f32x4 (&acc)[BR][BC], int unscale,
+                                            const BlockPos& P, int H, int W,
+                                            const float* __restrict__ ut,
+                                            const float* __restrict__ yt, float* __restrict__ ot,
+                                            float* __restrict__ oyt, float nu, double lcst,
+                                            bool ll) {
+  float uu[BR][BC][4], yy[BR][BC][4];
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int off = min(P.row(b, v), H - 1) * W + min(P.col(q), W - 1);
+        uu[b][q][v] = ut[off];
+        yy[b][q][v] = yt[off];
+      }
+  const float nu1 = nu + 1.f;
+  double llp = 0.0;
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = P.row(b, v), l = P.col(q);
+        if (k < H && l < W) {
+          const float m = ldexpf(acc[b][q][v], unscale);
+          const float u = uu[b][q][v];
+          float ro = 0.f, ryo = 0.f;
+          if (u > 0.f) {
+            const float y = yy[b][q][v];
+            const float d = y - m;
+            const float w = nu1 / (nu + u * d * d);
+            ro = (u * w) * m;
+            ryo = (u * w) * y;
+            if (ll) {
+              const double dd = (double)y - (double)m;
+              llp += ((double)nu + 1.0) * log1p((double)u * dd * dd / (double)nu) - lcst;
+            }
+          }
+          ot[k * W + l] = ro;
+          oyt[k * W + l] = ryo;
+        }
+      }
+  return llp;
+}
+
 template <int BR, int BC>
 __device__ inline double forward_epilogue(const f32x4 (&acc)[BR][BC], int unscale,
                                           const BlockPos& P, int H, int W,
