@@ -265,7 +265,7 @@ def psf_bench(args, em, synth, dev, stream, out):
                    "lambda": round(float(p.lambda_), 6), "adam_steps": p.n_steps,
                    "step": "one fit of every frame's PSF (one launch)",
                    "result_finite_nonnegative": ok},
-        "roofline": {"bound": "alu", "kernel": "psf_fit", "achieved": round(achieved, 4),
+        "roofline": {"bound": "mfma", "kernel": "psf_fit", "achieved": round(achieved, 4),
                      "peak": peak, "unit": "TFLOP/s", "frac": round(achieved / peak, 5),
                      "workgroups": p.n_frames,
                      "frac_of_occupied_cus": round(achieved / (peak * p.n_frames / 256.0), 4),
