@@ -157,3 +157,29 @@ def test_full_size_sampled_frames():
         oerr = abs(float(obj[t]) - oo[0]) / oo[0]
         log(f"  frame {t}: rel L2(h) {err:.2e}, objective rel err {oerr:.2e}")
         assert err <= H_BAR and oerr <= OBJ_BAR
+
+
+def test_paper_super_resolution_pipeline():
+    """The super-resolution run as the paper describes it after Eq. (4): PSFs h
+    fitted by Eq. (4) from the frame PSFs, exposures up-sampled to the fine grid,
+    then the update of Eq. (2) on the fine grid with h.  Each side runs the whole
+    pipeline itself (GPU: em_psf_fit, em_upsample, em_iterate; oracle: psf_fit,
+    upsample, run); 8 iterations compared."""
+    import torch
+    em = _em()
+    n, hf, wf = 3, 36, 44
+    f = synth.coarse_psfs(n, 43, 2, seed=67)
+    prob = synth.make_problem("c2", H=hf, W=wf, n=n, seed=68)     # frame-grid exposures
+    hg, _ = em.psf_fit(to_dev(f), 43, 2, steps=1000)
+    yu, vu = em.upsample(to_dev(prob.y), to_dev(prob.v), 2)
+    torch.cuda.synchronize()
+    p = em.psf_problem(n, 43, 43, 2, steps=1000)
+    ho, _ = oracle.psf_fit(f, 43, 2, sigma=float(p.sigma), **_oracle_kw(p))
+    yo, vo = oracle.upsample(prob.y, prob.v, 2)
+    x0 = synth.positive_start((2 * hf, 2 * wf), max(oracle.flat_x0(yo, vo), 0.25), seed=69)
+    from tests.gpu_common import gpu_run
+    xg, _ = gpu_run(yu.cpu().numpy(), vu.cpu().numpy(), hg.cpu().numpy(), 1, 8, x0=x0)
+    xo = oracle.run(yo, vo, ho.astype(np.float32), x0, 8, 1)
+    err = rel_l2(xg, xo)
+    log(f"  Eq. (4) + up-sampling + Eq. (2): rel L2(x) {err:.2e}")
+    assert err <= 1e-4
