@@ -94,7 +94,7 @@ extern "C" {
                                - ln(nu pi v)/2 - (nu+1)/2 ln(1 + u (y-F_t x)^2/nu)].
                                An iteration costs one forward and two adjoint
                                passes; the workspace holds one more frame-sized
-                               plane.  Not served by em_server (EM_ENOTSUP). */
+                               plane.  Served by em_server like the default. */
 
 typedef struct em_ctx em_ctx;
 typedef struct em_server em_server;

@@ -395,7 +395,7 @@ static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
 
 // Student-t noise: the forward epilogue applies the E-step weights, writing
 // r = u w F x and ry = u w y, with Student-t loglik partials when asked.
-static double student_t_lcst(double nu) {
+double em::student_t_lcst(double nu) {
   return 2.0 * (std::lgamma(0.5 * (nu + 1.0)) - std::lgamma(0.5 * nu) - 0.5 * std::log(nu * M_PI)) +
          std::log(2.0 * M_PI);
 }

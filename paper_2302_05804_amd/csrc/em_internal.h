@@ -139,14 +139,19 @@ int mfma_table_rows(int KT);
 hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int groups,
                         const MfmaLaunch& a, hipStream_t s);
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
-                                const int4* items, int n_items, int grid, hipStream_t s);
+                                const int4* items, int n_items, int grid, hipStream_t s,
+                                bool robust = false);
 hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                                hipStream_t s);
 size_t mfma2_table_bytes(int n, int dir);
 int mfma2_fwd_tile();
 int mfma2_adj_tile();
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
-                               const int4* items, int n_items, int grid, hipStream_t s);
+                               const int4* items, int n_items, int grid, hipStream_t s,
+                               bool robust = false);
+// 2 (lgamma((nu+1)/2) - lgamma(nu/2) - ln(nu pi)/2) + ln(2 pi): the constant of
+// the Student-t loglik partials (em_api.cpp)
+double student_t_lcst(double nu);
 hipError_t launch_forward_batched(int sr, int KT, const FwdLaunch* descs, const int4* items,
                                   int n_items, int grid, hipStream_t s);
 hipError_t launch_adjoint_batched(int sr, int KT, const AdjLaunch* descs, const int4* items,

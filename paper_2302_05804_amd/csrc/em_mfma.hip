@@ -440,6 +440,17 @@ __global__ __launch_bounds__(C::NT) void mfma_fwd_batched(const MfmaLaunch* __re
   }
 }
 template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd_t_batched(const MfmaLaunch* __restrict__ descs,
+                                                            const int4* __restrict__ items,
+                                                            int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const int4 w = items[i];
+    const MfmaLaunch d = descs[w.x];
+    mfma_fwd_body<C, true>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
+template <class C>
 __global__ __launch_bounds__(C::NT) void mfma_adj_batched(const MfmaLaunch* __restrict__ descs,
                                                           const int4* __restrict__ items,
                                                           int n_items) {
@@ -558,14 +569,18 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
 namespace {
 template <int KT, int PREC>
 hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* d, const int4* it,
-                              int n, hipStream_t s) {
+                              int n, hipStream_t s, bool robust) {
   // Toeplitz fragments: staged in LDS for the one-plane binary16 image (LDS
   // traffic is low there), register prefetch for the two-plane bf16 split
   constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
   using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, PFT>;
   using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, PFT>;
   using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, PFT>;
-  if (dir == 0) {
+  if (dir == 0 && robust) {
+    if (variant == 1) hipLaunchKernelGGL(mfma_fwd_t_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
+    else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_t_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
+    else hipLaunchKernelGGL(mfma_fwd_t_batched<C0>, dim3(grid), dim3(C0::NT), 0, s, d, it, n);
+  } else if (dir == 0) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
     else hipLaunchKernelGGL(mfma_fwd_batched<C0>, dim3(grid), dim3(C0::NT), 0, s, d, it, n);
@@ -579,16 +594,17 @@ hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* 
 }  // namespace
 
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
-                               const int4* items, int n_items, int grid, hipStream_t s) {
+                               const int4* items, int n_items, int grid, hipStream_t s,
+                               bool robust) {
   if (n_items <= 0) return hipSuccess;
 #define EM_MF_DISPATCH(KTV)                                                                  \
   switch (precision) {                                                                       \
     case EM_BF16_SPLIT:                                                                      \
-      return launch_dir_batched<KTV, EM_BF16_SPLIT>(dir, variant, grid, descs, items, n_items, s); \
+      return launch_dir_batched<KTV, EM_BF16_SPLIT>(dir, variant, grid, descs, items, n_items, s, robust); \
     case EM_FP16_SPLIT:                                                                      \
-      return launch_dir_batched<KTV, EM_FP16_SPLIT>(dir, variant, grid, descs, items, n_items, s); \
+      return launch_dir_batched<KTV, EM_FP16_SPLIT>(dir, variant, grid, descs, items, n_items, s, robust); \
     case EM_BF16:                                                                            \
-      return launch_dir_batched<KTV, EM_BF16>(dir, variant, grid, descs, items, n_items, s); \
+      return launch_dir_batched<KTV, EM_BF16>(dir, variant, grid, descs, items, n_items, s, robust); \
     default:                                                                                 \
       return hipErrorInvalidValue;                                                           \
   }

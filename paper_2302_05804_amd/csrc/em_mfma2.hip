@@ -508,6 +508,16 @@ __global__ __launch_bounds__(C::NT) void m2f_batched(const MfmaLaunch* __restric
   }
 }
 template <class C>
+__global__ __launch_bounds__(C::NT) void m2f_t_batched(const MfmaLaunch* __restrict__ descs,
+                                                       const int4* __restrict__ items, int n) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    const MfmaLaunch d = descs[w.x];
+    m2f_body<C, true>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
+template <class C>
 __global__ __launch_bounds__(C::NT) void m2a_batched(const MfmaLaunch* __restrict__ descs,
                                                      const int4* __restrict__ items, int n) {
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
@@ -615,7 +625,7 @@ namespace {
 // (per parity); 1: 4 waves of 4x2; 2: 4 waves of 2x4.
 template <int PREC>
 hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
-                   const MfmaLaunch* d, const int4* it, int n, hipStream_t s) {
+                   const MfmaLaunch* d, const int4* it, int n, hipStream_t s, bool robust = false) {
   // Toeplitz fragments staged in LDS for the one-plane binary16 image
   constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
   using F0 = M2F<PREC, 2, 2, 2, 2, PFT>;
@@ -635,7 +645,11 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
     else                                                                                \
       hipLaunchKernelGGL(KER##_kernel<CFG>, grid, dim3(CFG::NT), 0, s, a);              \
   } while (0)
-  if (dir == 0 && !batched && a.out_y != nullptr) {
+  if (dir == 0 && batched && robust) {
+    if (variant == 1) hipLaunchKernelGGL(m2f_t_batched<F1>, grid, dim3(F1::NT), 0, s, d, it, n);
+    else if (variant == 2) hipLaunchKernelGGL(m2f_t_batched<F2>, grid, dim3(F2::NT), 0, s, d, it, n);
+    else hipLaunchKernelGGL(m2f_t_batched<F0>, grid, dim3(F0::NT), 0, s, d, it, n);
+  } else if (dir == 0 && !batched && a.out_y != nullptr) {
     if (variant == 1) hipLaunchKernelGGL(m2f_t_kernel<F1>, grid, dim3(F1::NT), 0, s, a);
     else if (variant == 2) hipLaunchKernelGGL(m2f_t_kernel<F2>, grid, dim3(F2::NT), 0, s, a);
     else hipLaunchKernelGGL(m2f_t_kernel<F0>, grid, dim3(F0::NT), 0, s, a);
@@ -675,13 +689,14 @@ hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int 
 }
 
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
-                                const int4* items, int n_items, int grid, hipStream_t s) {
+                                const int4* items, int n_items, int grid, hipStream_t s,
+                                bool robust) {
   if (n_items <= 0) return hipSuccess;
   MfmaLaunch dummy{};
   switch (precision) {
-    case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
-    case EM_FP16_SPLIT: return launch2<EM_FP16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
-    case EM_BF16: return launch2<EM_BF16>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s);
+    case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);
+    case EM_FP16_SPLIT: return launch2<EM_FP16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);
+    case EM_BF16: return launch2<EM_BF16>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);
     default: return hipErrorInvalidValue;
   }
 }

@@ -117,16 +117,18 @@ class Arena {
 struct Family {
   int kind = 0;       // 0 = FP32 direct, 1 = matrix core
   int sr = 1, KT = 43, precision = EM_FP32, fvar = 0, avar = 0;
+  bool robust = false;  // Student-t noise: E-step weights in the forward, numerator adjoint
   std::vector<FwdLaunch> fwd32;
-  std::vector<AdjLaunch> adj32;
-  std::vector<MfmaLaunch> fwdmf, adjmf;
+  std::vector<AdjLaunch> adj32, adjB32;
+  std::vector<MfmaLaunch> fwdmf, adjmf, adjBmf;
   std::vector<int4> fitems, aitems;
   // device copies
   void* d_fdesc = nullptr;
   void* d_adesc = nullptr;
+  void* d_bdesc = nullptr;   // numerator adjoints (Student-t), same items as the adjoint
   int4* d_fitems = nullptr;
   int4* d_aitems = nullptr;
-  size_t cap_fdesc = 0, cap_adesc = 0, cap_fitems = 0, cap_aitems = 0;
+  size_t cap_fdesc = 0, cap_adesc = 0, cap_bdesc = 0, cap_fitems = 0, cap_aitems = 0;
 };
 
 // job bytes: inputs, iterate and workspace under the serving plan
@@ -210,12 +212,14 @@ int build_round(em_server* S) {
   old.swap(S->fams);
   auto family_of = [&](const em_ctx* c) -> Family& {
     const int kind = uses_mfma(c->g) ? 1 : 0;
+    const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
     for (auto& f : S->fams)
       if (f.kind == kind && f.sr == c->g.sr && f.KT == c->g.KT && f.precision == c->g.precision &&
-          f.fvar == c->pl.fwd_variant && f.avar == c->pl.adj_variant)
+          f.fvar == c->pl.fwd_variant && f.avar == c->pl.adj_variant && f.robust == robust)
         return f;
     Family f;
     f.kind = kind;
+    f.robust = robust;
     f.sr = c->g.sr;
     f.KT = c->g.KT;
     f.precision = c->g.precision;
@@ -226,6 +230,7 @@ int build_round(em_server* S) {
       Family& o = old.back();
       f.d_fdesc = o.d_fdesc; f.cap_fdesc = o.cap_fdesc;
       f.d_adesc = o.d_adesc; f.cap_adesc = o.cap_adesc;
+      f.d_bdesc = o.d_bdesc; f.cap_bdesc = o.cap_bdesc;
       f.d_fitems = o.d_fitems; f.cap_fitems = o.cap_fitems;
       f.d_aitems = o.d_aitems; f.cap_aitems = o.cap_aitems;
       old.pop_back();
@@ -242,36 +247,61 @@ int build_round(em_server* S) {
     Family& f = family_of(j->ctx);
     const em_ctx* c = j->ctx;
     // every descriptor is checked against its grid on the host before upload
+    const double lcst = f.robust ? student_t_lcst((double)c->g.nu) : 0.0;
     if (f.kind == 1) {
       MfmaLaunch m;
       fill_forward_mfma(c, &m, true, false);
+      if (f.robust) {
+        m.out_y = c->ry;
+        m.nu = c->g.nu;
+        m.lcst = lcst;
+      }
       if (!mfma_desc_ok(c->g, 0, c->pl.fwd_tiles, c->pl.fwd_groups, m))
         return fail(EM_EDEVICE, "inconsistent forward descriptor");
       add_items(f.fitems, (int)f.fwdmf.size(), c->pl.fwd_tiles, c->pl.fwd_groups);
       f.fwdmf.push_back(m);
       fill_adjoint_mfma(c, &m, nullptr);
-      if (!mfma_desc_ok(c->g, 1, c->pl.adj_tiles, 1, m))
+      if (!mfma_desc_ok(c->g, 1, c->pl.adj_tiles, 1, m) || m.fused != 1)
         return fail(EM_EDEVICE, "inconsistent adjoint descriptor");
       add_items(f.aitems, (int)f.adjmf.size(), c->pl.adj_tiles, 1);
       f.adjmf.push_back(m);
+      if (f.robust) {
+        // numerator of the iteration: sum_t F_t^T (u w y) into B
+        m.in = c->ry;
+        m.fused = 0;
+        m.plane = c->B;
+        f.adjBmf.push_back(m);
+      }
     } else {
       FwdLaunch fl;
       fill_forward_fp32(c, &fl, true, false);
+      if (f.robust) {
+        fl.out_y = c->ry;
+        fl.nu = c->g.nu;
+        fl.lcst = lcst;
+      }
       if (!forward_desc_ok(c->g, c->pl.fwd_tiles, c->pl.fwd_groups, fl))
         return fail(EM_EDEVICE, "inconsistent forward descriptor");
       add_items(f.fitems, (int)f.fwd32.size(), c->pl.fwd_tiles, c->pl.fwd_groups);
       f.fwd32.push_back(fl);
       AdjLaunch al;
       fill_adjoint_fp32(c, &al, nullptr);
-      if (!adjoint_desc_ok(c->g, c->pl.adj_tiles, 1, al))
+      if (!adjoint_desc_ok(c->g, c->pl.adj_tiles, 1, al) || al.fused != 1)
         return fail(EM_EDEVICE, "inconsistent adjoint descriptor");
       add_items(f.aitems, (int)f.adj32.size(), c->pl.adj_tiles, 1);
       f.adj32.push_back(al);
+      if (f.robust) {
+        al.in = c->ry;
+        al.fused = 0;
+        al.plane = c->B;
+        f.adjB32.push_back(al);
+      }
     }
   }
   for (auto& o : old) {
     if (o.d_fdesc) (void)hipFree(o.d_fdesc);
     if (o.d_adesc) (void)hipFree(o.d_adesc);
+    if (o.d_bdesc) (void)hipFree(o.d_bdesc);
     if (o.d_fitems) (void)hipFree(o.d_fitems);
     if (o.d_aitems) (void)hipFree(o.d_aitems);
   }
@@ -280,9 +310,11 @@ int build_round(em_server* S) {
     if (f.kind == 1) {
       if ((rc = upload(S, &f.d_fdesc, &f.cap_fdesc, f.fwdmf))) return rc;
       if ((rc = upload(S, &f.d_adesc, &f.cap_adesc, f.adjmf))) return rc;
+      if ((rc = upload(S, &f.d_bdesc, &f.cap_bdesc, f.adjBmf))) return rc;
     } else {
       if ((rc = upload(S, &f.d_fdesc, &f.cap_fdesc, f.fwd32))) return rc;
       if ((rc = upload(S, &f.d_adesc, &f.cap_adesc, f.adj32))) return rc;
+      if ((rc = upload(S, &f.d_bdesc, &f.cap_bdesc, f.adjB32))) return rc;
     }
     if ((rc = upload(S, reinterpret_cast<void**>(&f.d_fitems), &f.cap_fitems, f.fitems))) return rc;
     if ((rc = upload(S, reinterpret_cast<void**>(&f.d_aitems), &f.cap_aitems, f.aitems))) return rc;
@@ -299,16 +331,33 @@ int build_round(em_server* S) {
     const int n = (int)f.fitems.size();
     if (f.kind == 1 && f.sr == 2) {
       e = launch_mfma2_batched(f.precision, 0, f.fvar, static_cast<const MfmaLaunch*>(f.d_fdesc),
-                               f.d_fitems, n, std::min(n, 512), S->stream);
+                               f.d_fitems, n, std::min(n, 512), S->stream, f.robust);
     } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 0, f.fvar,
                               static_cast<const MfmaLaunch*>(f.d_fdesc), f.d_fitems, n,
-                              std::min(n, 512), S->stream);
+                              std::min(n, 512), S->stream, f.robust);
     } else {
       e = launch_forward_batched(f.sr, f.KT, static_cast<const FwdLaunch*>(f.d_fdesc),
                                  f.d_fitems, n, std::min(n, 1024), S->stream);
     }
     if (e != hipSuccess) break;
+  }
+  // Student-t families: the numerator of this iteration, before any update
+  for (auto& f : S->fams) {
+    if (e != hipSuccess) break;
+    if (!f.robust) continue;
+    const int n = (int)f.aitems.size();
+    if (f.kind == 1 && f.sr == 2) {
+      e = launch_mfma2_batched(f.precision, 1, f.avar, static_cast<const MfmaLaunch*>(f.d_bdesc),
+                               f.d_aitems, n, std::min(n, 1024), S->stream);
+    } else if (f.kind == 1) {
+      e = launch_mfma_batched(f.KT, f.precision, 1, f.avar,
+                              static_cast<const MfmaLaunch*>(f.d_bdesc), f.d_aitems, n,
+                              std::min(n, 512), S->stream);
+    } else {
+      e = launch_adjoint_batched(f.sr, f.KT, static_cast<const AdjLaunch*>(f.d_bdesc),
+                                 f.d_aitems, n, std::min(n, 1024), S->stream);
+    }
   }
   for (auto& f : S->fams) {
     if (e != hipSuccess) break;
@@ -565,6 +614,7 @@ int em_server_destroy(em_server* S) {
   for (auto& f : S->fams) {
     if (f.d_fdesc) (void)hipFree(f.d_fdesc);
     if (f.d_adesc) (void)hipFree(f.d_adesc);
+    if (f.d_bdesc) (void)hipFree(f.d_bdesc);
     if (f.d_fitems) (void)hipFree(f.d_fitems);
     if (f.d_aitems) (void)hipFree(f.d_aitems);
   }
@@ -584,7 +634,7 @@ int em_submit(em_server* S, const em_problem* p, const float* y_host, const floa
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
-  if (g.weight_mode != EM_W_ADJOINT) return fail(EM_ENOTSUP, "weight mode not provided");
+  if (g.weight_mode == EM_W_LITERAL) return fail(EM_ENOTSUP, "weight mode not provided");
   size_t total, a, b, c2, d, e, wsb;
   job_layout(g, &total, &a, &b, &c2, &d, &e, &wsb);
   if (total > S->budget)

@@ -3,7 +3,8 @@ uneven size, frame count and super-resolution factor.
 
 * Each job's result is bitwise the same alone and in a mix (the launch plan of
   a served job depends on its own shape; no reduction crosses jobs).
-* Served results match the FP64 oracle within the bar of their precision.
+* Served results match the FP64 oracle within the bar of their precision
+  (Gaussian and Student-t jobs).
 * Admission respects the HBM budget and the slot count; errors, cancellation.
 """
 import numpy as np
@@ -23,20 +24,25 @@ def _em():
 
 def _jobs():
     em = _em()
-    specs = [  # (recipe, latent H, W, n, sr, precision, iterations)
-        ("c2", 96, 96, 3, 1, em.BF16_SPLIT, 7),
-        ("c3", 160, 128, 5, 1, em.FP32, 5),
-        ("c4", 128, 96, 2, 2, em.BF16_SPLIT, 6),
-        ("c2", 200, 136, 2, 1, em.BF16_SPLIT, 9),
-        ("c1", 64, 64, 4, 1, em.FP32, 12),
-        ("c4", 64, 192, 3, 2, em.FP32, 4),
-        ("c3", 128, 160, 3, 1, em.FP16_SPLIT, 6),
-        ("c4", 96, 128, 2, 2, em.FP16_SPLIT, 5),
+    specs = [  # (recipe, latent H, W, n, sr, precision, iterations, Student-t nu or 0)
+        ("c2", 96, 96, 3, 1, em.BF16_SPLIT, 7, 0.0),
+        ("c3", 160, 128, 5, 1, em.FP32, 5, 0.0),
+        ("c4", 128, 96, 2, 2, em.BF16_SPLIT, 6, 0.0),
+        ("c2", 200, 136, 2, 1, em.BF16_SPLIT, 9, 0.0),
+        ("c1", 64, 64, 4, 1, em.FP32, 12, 0.0),
+        ("c4", 64, 192, 3, 2, em.FP32, 4, 0.0),
+        ("c3", 128, 160, 3, 1, em.FP16_SPLIT, 6, 0.0),
+        ("c4", 96, 128, 2, 2, em.FP16_SPLIT, 5, 0.0),
+        ("c2", 112, 96, 3, 1, em.FP16_SPLIT, 6, 4.0),     # Student-t jobs, with trails
+        ("c4", 96, 112, 2, 2, em.FP32, 5, 3.0),
+        ("c3", 96, 80, 2, 1, em.BF16_SPLIT, 4, 2.5),
     ]
     out = []
-    for k, (rec, H, W, n, sr, prec, it) in enumerate(specs):
+    for k, (rec, H, W, n, sr, prec, it, nu) in enumerate(specs):
         p = synth.make_problem(rec, H=H, W=W, n=n, seed=700 + k)
-        prob = em.Problem.make(n, H // sr, W // sr, p.K, sr=sr, precision=prec)
+        if nu:
+            p.y, _ = synth.add_trails(p.y, p.v, seed=800 + k)
+        prob = em.Problem.make(n, H // sr, W // sr, p.K, sr=sr, precision=prec, nu=nu)
         out.append((p, prob, it))
     return out
 
@@ -82,11 +88,15 @@ def test_served_results_match_oracle():
     res, st, _ = _serve(jobs, 512 << 20, 8)
     for (p, prob, it), (x, ll) in zip(jobs, res):
         x0 = np.full(p.latent_shape, oracle.flat_x0(p.y, p.v, p.sr), np.float32)
-        xo = oracle.run(p.y, p.v, p.psf, x0, it, p.sr)
-        llo = oracle.loglik(p.y, p.v, p.psf, xo, p.sr)
+        if prob.nu:
+            xo = oracle.run_t(p.y, p.v, p.psf, x0, it, prob.nu, p.sr)
+            llo = oracle.loglik_t(p.y, p.v, p.psf, xo, prob.nu, p.sr)
+        else:
+            xo = oracle.run(p.y, p.v, p.psf, x0, it, p.sr)
+            llo = oracle.loglik(p.y, p.v, p.psf, xo, p.sr)
         err = rel_l2(x, xo)
         tol = 1e-5 if prob.precision == em.FP32 else 1e-3
-        log(f"job {p.name} {p.latent_shape} sr={p.sr} prec={prob.precision}: rel L2 {err:.2e}, "
+        log(f"job {p.name} {p.latent_shape} sr={p.sr} prec={prob.precision} nu={prob.nu:g}: rel L2 {err:.2e}, "
             f"loglik rel err {abs(ll - llo) / abs(llo):.2e}")
         assert err <= tol
         assert abs(ll - llo) <= 1e-5 * abs(llo)
