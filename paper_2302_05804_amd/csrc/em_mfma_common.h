@@ -288,45 +288,55 @@ __device__ inline double forward_epilogue_t(const f32x4 (&acc)[BR][BC], int unsc
                                             const float* __restrict__ yt, float* __restrict__ ot,
                                             float* __restrict__ oyt, float nu, double lcst,
                                             bool ll) {
-  float uu[BR][BC][4], yy[BR][BC][4];
-#pragma unroll
-  for (int b = 0; b < BR; ++b)
-#pragma unroll
-    for (int q = 0; q < BC; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int off = min(P.row(b, v), H - 1) * W + min(P.col(q), W - 1);
-        uu[b][q][v] = ut[off];
-        yy[b][q][v] = yt[off];
-      }
+  // two halves of the block rows, each with its loads issued first: half the
+  // registers of loading u and y for every output at once
+  constexpr int BH = (BR + 1) / 2;
   const float nu1 = nu + 1.f;
   double llp = 0.0;
 #pragma unroll
-  for (int b = 0; b < BR; ++b)
+  for (int h = 0; h < BR; h += BH) {
+    float uu[BH][BC][4], yy[BH][BC][4];
 #pragma unroll
-    for (int q = 0; q < BC; ++q)
+    for (int bb = 0; bb < BH; ++bb)
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int k = P.row(b, v), l = P.col(q);
-        if (k < H && l < W) {
-          const float m = ldexpf(acc[b][q][v], unscale);
-          const float u = uu[b][q][v];
-          float ro = 0.f, ryo = 0.f;
-          if (u > 0.f) {
-            const float y = yy[b][q][v];
-            const float d = y - m;
-            const float w = nu1 / (nu + u * d * d);
-            ro = (u * w) * m;
-            ryo = (u * w) * y;
-            if (ll) {
-              const double dd = (double)y - (double)m;
-              llp += ((double)nu + 1.0) * log1p((double)u * dd * dd / (double)nu) - lcst;
-            }
-          }
-          ot[k * W + l] = ro;
-          oyt[k * W + l] = ryo;
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int b = min(h + bb, BR - 1);
+          const int off = min(P.row(b, v), H - 1) * W + min(P.col(q), W - 1);
+          uu[bb][q][v] = ut[off];
+          yy[bb][q][v] = yt[off];
         }
-      }
+#pragma unroll
+    for (int bb = 0; bb < BH; ++bb) {
+      const int b = h + bb;
+      if (b >= BR) break;
+#pragma unroll
+      for (int q = 0; q < BC; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int k = P.row(b, v), l = P.col(q);
+          if (k < H && l < W) {
+            const float m = ldexpf(acc[b][q][v], unscale);
+            const float u = uu[bb][q][v];
+            float ro = 0.f, ryo = 0.f;
+            if (u > 0.f) {
+              const float y = yy[bb][q][v];
+              const float d = y - m;
+              const float w = nu1 / (nu + u * d * d);
+              ro = (u * w) * m;
+              ryo = (u * w) * y;
+              if (ll) {
+                const double dd = (double)y - (double)m;
+                llp += ((double)nu + 1.0) * log1p((double)u * dd * dd / (double)nu) - lcst;
+              }
+            }
+            ot[k * W + l] = ro;
+            oyt[k * W + l] = ryo;
+          }
+        }
+    }
+  }
   return llp;
 }
 
