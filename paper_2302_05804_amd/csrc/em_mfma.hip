@@ -213,6 +213,31 @@ __device__ inline void issue_T(const typename C::frag* __restrict__ tab_t, int r
   }
 }
 
+// Copy of a frame's u tile (TH x TW floats, rows clamped into the frame) into LDS,
+// 1 KB per direct global-to-LDS instruction, spread over tap classes 1..13 (class
+// 0's barrier separates it from the previous frame's epilogue reads).
+struct UPre {
+  const float* ut;   // frame base of u, or nullptr (no copy)
+  float* ub;         // LDS destination
+  int k0, l0, H, W;
+};
+template <class C>
+__device__ inline void issue_u(const UPre& u, int r) {
+  constexpr int NCH = C::TH * C::TW / 256;   // 1 KB chunks of the tile
+  constexpr int CPC = (NCH + 12) / 13;       // chunks per class, classes 1..13
+  static_assert(C::RLAST >= 14, "the copy needs tap classes 1..13");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (u.ut == nullptr || r < 1 || r > 13) return;
+  const int end = min(r * CPC, NCH);
+  for (int ch = (r - 1) * CPC + w; ch < end; ch += C::NW) {
+    const int e = ch * 256 + 4 * lane;
+    const int gy = min(u.k0 + e / C::TW, u.H - 1), gx = min(u.l0 + e % C::TW, u.W - 4);
+    __builtin_amdgcn_global_load_lds(
+        (__attribute__((address_space(1))) void*)(u.ut + (int64_t)gy * u.W + gx),
+        (__attribute__((address_space(3))) void*)(u.ub + ch * 256), 16, 0, 0);
+  }
+}
+
 // One tap class with the Toeplitz fragments staged in LDS: start the copy of
 // the next class (the first class of tab_next after the last one, if any) into
 // the other buffer, read this class's fragments from LDS, issue its products,
@@ -223,11 +248,12 @@ __device__ inline void mfma_class_lds(int r, const unsigned short (*sh)[C::ROWS 
                                       const typename C::frag* __restrict__ tab_t,
                                       const typename C::frag* __restrict__ tab_next,
                                       TBuf<C>& tl, int& step, int row_base, int col_base,
-                                      f32x4 (&acc)[C::BR][C::BC]) {
+                                      f32x4 (&acc)[C::BR][C::BC], const UPre& up) {
   const int lane = threadIdx.x & 63;
   const int cur = step & 1;
   if (r + 1 < C::RLAST) issue_T<C>(tab_t, r + 1, (void*)&tl[cur ^ 1][0][0]);
   else if (tab_next != nullptr) issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+  issue_u<C>(up, r);
   typename C::frag Tc[C::MMAX][2][C::NB];
 #pragma unroll
   for (int m = 0; m < C::MMAX; ++m)
@@ -248,15 +274,17 @@ __device__ inline void mfma_frame_lds(const unsigned short (*sh)[C::ROWS * C::PI
                                       const typename C::frag* __restrict__ tab_t,
                                       const typename C::frag* __restrict__ tab_next,
                                       TBuf<C>& tl, int& step, int row_base, int col_base,
-                                      f32x4 (&acc)[C::BR][C::BC]) {
+                                      f32x4 (&acc)[C::BR][C::BC],
+                                      const UPre& up = UPre{nullptr, nullptr, 0, 0, 0, 0}) {
   int r = 0;
 #pragma unroll 1
   for (; r < C::RFULL; ++r)
-    mfma_class_lds<C, C::MMAX>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+    mfma_class_lds<C, C::MMAX>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc, up);
   if constexpr (C::MMAX > 1) {
 #pragma unroll 1
     for (; r < C::RLAST; ++r)
-      mfma_class_lds<C, C::MMAX - 1>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
+      mfma_class_lds<C, C::MMAX - 1>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc,
+                                     up);
   }
 }
 
@@ -286,6 +314,11 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
   const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
   constexpr int64_t TSTRIDE = (int64_t)C::KTP * 4 * 64;   // fragments per frame
   __shared__ __align__(16) TBufDecl<C> tl;
+  // u of the frame in LDS (LDS-staged fragments, plain epilogue, rows of whole 16-byte runs)
+  constexpr bool UPF = C::PFT == 2 && !ROB && C::TW == 128;
+  __shared__ __align__(16) std::conditional_t<UPF, float[C::TH * C::TW], float[4]> ubuf;
+  const bool use_ul = UPF && a.u != nullptr && a.part == nullptr && a.out != nullptr &&
+                      (a.W & 3) == 0 && a.W >= 4;
   int step = 0;
   if constexpr (C::PFT == 2) issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
   const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, a.H, a.W, k0 - c,
@@ -306,9 +339,10 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
 #pragma unroll
       for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
     const typename C::frag* tab_t = tab + t * TSTRIDE;
+    const UPre up{use_ul ? a.u + (int64_t)t * N : nullptr, &ubuf[0], k0, l0, a.H, a.W};
     if constexpr (C::PFT == 2)
       mfma_frame_lds<C>(sh, tab_t, t + 1 < t1 ? tab_t + TSTRIDE : nullptr, tl, step, row_base,
-                        col_base, acc);
+                        col_base, acc, up);
     else
       mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
     // exact removal of the image and PSF scales (scaled encodings)
@@ -319,6 +353,10 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
           acc, unscale, BlockPos{k0 + row_base, l0 + col_base, 1}, a.H, a.W, a.u + (int64_t)t * N,
           a.y + (int64_t)t * N, a.out + (int64_t)t * N, a.out_y + (int64_t)t * N, a.nu, a.lcst,
           a.part != nullptr);
+    } else if (UPF && use_ul) {
+      forward_epilogue_ul<C::BR, C::BC, C::TW>(acc, unscale,
+                                               BlockPos{k0 + row_base, l0 + col_base, 1}, a.H,
+                                               a.W, k0, l0, &ubuf[0], a.out + (int64_t)t * N);
     } else {
       const float* ut = a.u ? a.u + (int64_t)t * N : nullptr;
       const float* yt = (a.u && a.part) ? a.y + (int64_t)t * N : nullptr;

@@ -340,6 +340,26 @@ __device__ inline double forward_epilogue_t(const f32x4 (&acc)[BR][BC], int unsc
   return llp;
 }
 
+// Forward epilogue with u already in LDS (ub: the tile's TH x TW weights, row-major
+// from (k0, l0)): out = u * m.
+template <int BR, int BC, int TW>
+__device__ inline void forward_epilogue_ul(const f32x4 (&acc)[BR][BC], int unscale,
+                                           const BlockPos& P, int H, int W, int k0, int l0,
+                                           const float* ub, float* __restrict__ ot) {
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = P.row(b, v), l = P.col(q);
+        if (k < H && l < W) {
+          const float m = ldexpf(acc[b][q][v], unscale);
+          ot[k * W + l] = ub[(k - k0) * TW + (l - l0)] * m;
+        }
+      }
+}
+
 template <int BR, int BC>
 __device__ inline double forward_epilogue(const f32x4 (&acc)[BR][BC], int unscale,
                                           const BlockPos& P, int H, int W,
