@@ -213,29 +213,10 @@ __device__ inline void issue_T(const typename C::frag* __restrict__ tab_t, int r
   }
 }
 
-// Copy of a frame's u tile (TH x TW floats, rows clamped into the frame) into LDS,
-// 1 KB per direct global-to-LDS instruction, spread over tap classes 1..13 (class
-// 0's barrier separates it from the previous frame's epilogue reads).
-struct UPre {
-  const float* ut;   // frame base of u, or nullptr (no copy)
-  float* ub;         // LDS destination
-  int k0, l0, H, W;
-};
 template <class C>
 __device__ inline void issue_u(const UPre& u, int r) {
-  constexpr int NCH = C::TH * C::TW / 256;   // 1 KB chunks of the tile
-  constexpr int CPC = (NCH + 12) / 13;       // chunks per class, classes 1..13
   static_assert(C::RLAST >= 14, "the copy needs tap classes 1..13");
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (u.ut == nullptr || r < 1 || r > 13) return;
-  const int end = min(r * CPC, NCH);
-  for (int ch = (r - 1) * CPC + w; ch < end; ch += C::NW) {
-    const int e = ch * 256 + 4 * lane;
-    const int gy = min(u.k0 + e / C::TW, u.H - 1), gx = min(u.l0 + e % C::TW, u.W - 4);
-    __builtin_amdgcn_global_load_lds(
-        (__attribute__((address_space(1))) void*)(u.ut + (int64_t)gy * u.W + gx),
-        (__attribute__((address_space(3))) void*)(u.ub + ch * 256), 16, 0, 0);
-  }
+  issue_u_tile<C::TH, C::TW, C::NW>(u, r);
 }
 
 // One tap class with the Toeplitz fragments staged in LDS: start the copy of

@@ -340,6 +340,32 @@ __device__ inline double forward_epilogue_t(const f32x4 (&acc)[BR][BC], int unsc
   return llp;
 }
 
+// Copy of a frame's u tile (TH x TW floats from (k0, l0), rows and columns clamped
+// into the frame, which is a multiple of 4 wide) into LDS, 1 KB per direct
+// global-to-LDS instruction, spread over tap classes 1..13 of the frame (class
+// 0's barrier separates it from the previous frame's epilogue reads).
+struct UPre {
+  const float* ut;   // frame base of u, or nullptr (no copy)
+  float* ub;         // LDS destination
+  int k0, l0, H, W;
+};
+template <int TH, int TW, int NW>
+__device__ inline void issue_u_tile(const UPre& u, int r) {
+  static_assert(256 % TW == 0, "a 1 KB chunk holds whole tile rows");
+  constexpr int NCH = TH * TW / 256;         // 1 KB chunks of the tile
+  constexpr int CPC = (NCH + 12) / 13;       // chunks per class, classes 1..13
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (u.ut == nullptr || r < 1 || r > 13) return;
+  const int end = min(r * CPC, NCH);
+  for (int ch = (r - 1) * CPC + w; ch < end; ch += NW) {
+    const int e = ch * 256 + 4 * lane;
+    const int gy = min(u.k0 + e / TW, u.H - 1), gx = min(u.l0 + e % TW, u.W - 4);
+    __builtin_amdgcn_global_load_lds(
+        (__attribute__((address_space(1))) void*)(u.ut + (int64_t)gy * u.W + gx),
+        (__attribute__((address_space(3))) void*)(u.ub + ch * 256), 16, 0, 0);
+  }
+}
+
 // Forward epilogue with u already in LDS (ub: the tile's TH x TW weights, row-major
 // from (k0, l0)): out = u * m.
 template <int BR, int BC, int TW>

@@ -199,21 +199,24 @@ def test_fp16_deterministic_and_graph_replays():
     graphed.close()
 
 
+@pytest.mark.parametrize("sr", [1, 2])
 @pytest.mark.parametrize("variant", [0, 1, 2])
-def test_fp16_traced_and_untraced_iterations_agree_bitwise(variant):
-    """Without a log-likelihood trace the sr = 1 forward takes each frame's
-    weights from LDS (copied during the tap classes); with a trace it reads
-    them from HBM beside y.  The products are the same, so the iterates must be
-    bitwise equal; ragged frame widths (not a multiple of 4) use the HBM path."""
+def test_fp16_traced_and_untraced_iterations_agree_bitwise(sr, variant):
+    """Without a log-likelihood trace the forward takes each frame's weights
+    from LDS (copied during the tap classes); with a trace it reads them from
+    HBM beside y.  The products are the same, so the iterates must be bitwise
+    equal; frame widths that are not a multiple of 4 use the HBM path."""
     import torch
     em = _em()
-    for (H, W) in [(200, 264), (131, 258)]:
-        p = synth.make_problem("c2", H=H, W=W, n=3, seed=8800 + W)
+    # one frame width a multiple of 4 (LDS path), one not (HBM path)
+    for (H, W) in ([(200, 264), (134, 262)] if sr == 1 else [(200, 264), (134, 260)]):
+        rec = "c2" if sr == 1 else "c4"
+        p = synth.make_problem(rec, H=H, W=W, n=3, seed=8800 + W + sr)
         x0 = synth.positive_start(p.latent_shape, 20.0, seed=8801)
         out = []
         for trace in (True, False):
-            prob = em.Problem.make(3, H, W, p.K, precision=em.FP16_SPLIT)
-            x = torch.empty((H, W), dtype=torch.float32, device="cuda")
+            prob = em.Problem.make(3, H // sr, W // sr, p.K, sr=sr, precision=em.FP16_SPLIT)
+            x = torch.empty(p.latent_shape, dtype=torch.float32, device="cuda")
             ctx = em.Context(prob, to_dev(p.y), to_dev(p.v), to_dev(p.psf), x, x0=to_dev(x0))
             ctx.set_variants(variant, 2)
             ctx.iterate(4, trace=trace)
