@@ -145,19 +145,29 @@ def _torch():
     return torch
 
 
-def _dev_ptr(t, name, numel=None):
+def _dev_ptr(t, name, numel=None, dtype=None):
+    """Device address of a contiguous tensor of `dtype` (float32 unless given:
+    the workspace is the one byte buffer) holding `numel` elements."""
     torch = _torch()
     if t is None:
         return None
-    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+    if not isinstance(t, torch.Tensor):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
-    if t.dtype != torch.float32 and t.dtype != torch.uint8:
-        raise TypeError(f"{name} must be float32")
+    want = torch.float32 if dtype is None else dtype
+    if t.dtype != want:
+        raise TypeError(f"{name} must be {str(want).replace('torch.', '')}, not "
+                        f"{str(t.dtype).replace('torch.', '')}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     if numel is not None and t.numel() != numel:
         raise ValueError(f"{name} has {t.numel()} elements, {numel} expected")
+    if not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     return ctypes.c_void_p(t.data_ptr())
+
+
+def _ws_ptr(ws):
+    return _dev_ptr(ws, "workspace", dtype=_torch().uint8)
 
 
 def _stream_ptr(stream):
@@ -195,7 +205,7 @@ class Context:
         _check(_lib.em_init(ctypes.byref(h), ctypes.byref(p), _dev_ptr(y, "y", nf),
                             _dev_ptr(v, "v", nf), _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
                             _dev_ptr(x0, "x0", nl), _dev_ptr(x, "x", nl),
-                            _dev_ptr(self.ws, "workspace"), self.ws.numel(), sp), "em_init")
+                            _ws_ptr(self.ws), self.ws.numel(), sp), "em_init")
         self._h = h
 
     def iterate(self, n_iter: int, trace: bool = False) -> Optional[np.ndarray]:
@@ -275,7 +285,7 @@ def forward_op(p: Problem, psf, x, m=None, workspace=None, stream=None):
     _check(_lib.em_forward_op(ctypes.byref(p), _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
                               _dev_ptr(x, "x", nl),
                               _dev_ptr(m, "m", p.n_frames * p.frame_h * p.frame_w),
-                              _dev_ptr(ws, "workspace"), ws.numel(), sp), "em_forward_op")
+                              _ws_ptr(ws), ws.numel(), sp), "em_forward_op")
     return m
 
 
@@ -290,7 +300,7 @@ def adjoint_op(p: Problem, psf, r, s=None, workspace=None, stream=None):
     _check(_lib.em_adjoint_op(ctypes.byref(p), _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
                               _dev_ptr(r, "r", p.n_frames * p.frame_h * p.frame_w),
                               _dev_ptr(s, "s", p.n_frames * hl * wl),
-                              _dev_ptr(ws, "workspace"), ws.numel(), sp), "em_adjoint_op")
+                              _ws_ptr(ws), ws.numel(), sp), "em_adjoint_op")
     return s
 
 
@@ -342,13 +352,10 @@ def psf_fit_into(p: PsfProblem, f, h, objective=None, h0=None, stream=None):
     float64 of n_frames or None; h0 float32 or None); asynchronous."""
     torch = _torch()
     n, kf, kh = p.n_frames, p.psf_k, p.out_k
-    if objective is not None and (objective.dtype != torch.float64 or not objective.is_cuda
-                                  or objective.numel() != n):
-        raise TypeError("objective must be a CUDA float64 tensor of n_frames values")
     sp, _ = _stream_ptr(stream)
     _check(_lib.em_psf_fit(ctypes.byref(p), _dev_ptr(f, "f", n * kf * kf),
                            _dev_ptr(h0, "h0", n * kh * kh), _dev_ptr(h, "h", n * kh * kh),
-                           None if objective is None else ctypes.c_void_p(objective.data_ptr()),
+                           _dev_ptr(objective, "objective", n, dtype=torch.float64),
                            sp), "em_psf_fit")
 
 
