@@ -136,3 +136,59 @@ def test_budget_errors_cancel_and_release():
     st = srv.stats()
     assert st["arena_bytes_in_use"] == 0 and st["active"] == 0
     srv.close()
+
+
+def test_concurrent_clients_match_one_client_bitwise():
+    """Server calls are thread-safe: four client threads submit, poll and wait
+    on their own jobs while a fifth reads the statistics; every result is
+    bitwise the one a single client gets for the same job."""
+    import threading
+    import time
+
+    em = _em()
+    jobs = _jobs()[:8]
+    ref, _, _ = _serve(jobs, 512 << 20, 4)
+    srv = em.Server(512 << 20, max_slots=4)
+    out = [None] * len(jobs)
+    errors = []
+    done = threading.Event()
+
+    def client(ks):
+        try:
+            ids = [(k, srv.submit(jobs[k][1], jobs[k][0].y, jobs[k][0].v, jobs[k][0].psf,
+                                  jobs[k][2])) for k in ks]
+            for k, j in ids:
+                deadline = time.time() + 120
+                while srv.poll(j) is None:
+                    assert time.time() < deadline, f"job {k} still pending"
+                    time.sleep(0.002)
+                out[k] = srv.wait(j)
+        except Exception as e:   # reported in the main thread
+            errors.append(e)
+
+    def watcher():
+        try:
+            while not done.is_set():
+                st = srv.stats()
+                assert st["active"] <= 4 and st["failed"] == 0
+                time.sleep(0.001)
+        except Exception as e:
+            errors.append(e)
+
+    threads = [threading.Thread(target=client, args=(list(range(c, len(jobs), 4)),))
+               for c in range(4)]
+    w = threading.Thread(target=watcher)
+    w.start()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=300)
+    done.set()
+    w.join(timeout=30)
+    st = srv.stats()
+    srv.close()
+    assert not errors, errors
+    assert st["done"] == len(jobs) and st["failed"] == 0
+    for k, ((xa, la), res) in enumerate(zip(ref, out)):
+        assert res is not None, k
+        assert np.array_equal(xa, res[0]) and la == res[1], k
