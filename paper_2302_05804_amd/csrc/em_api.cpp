@@ -105,7 +105,8 @@ Plan make_plan(const Geometry& g) {
   pl.fwd_variant = 0;
   const bool mf = uses_mfma(g);
   if (mf && g.sr == 2)
-    pl.fwd_tiles = (int)(cdiv(g.Wf, mfma2_fwd_tile()) * cdiv(g.Hf, mfma2_fwd_tile()));
+    pl.fwd_tiles = (int)(cdiv(g.Wf, mfma2_fwd_tile_w(g.precision)) *
+                         cdiv(g.Hf, mfma2_fwd_tile_h(g.precision)));
   else if (mf)
     pl.fwd_tiles = (int)(cdiv(g.Wf, mfma_tile_w()) * cdiv(g.Hf, mfma_tile_h()));
   else
@@ -161,7 +162,7 @@ Plan make_serving_plan(const Geometry& g) {
     // the variants em_autotune picks on the large workloads (33 x 4096^2 sr = 1,
     // 16 x 2048^2 sr = 2) for each encoding
     const bool f16 = g.precision == EM_FP16_SPLIT;
-    pl.fwd_variant = g.sr == 1 ? (f16 ? 1 : 0) : (f16 ? 2 : 0);
+    pl.fwd_variant = g.sr == 1 ? (f16 ? 2 : 0) : (f16 ? 2 : 0);
     pl.adj_variant = g.sr == 1 ? 2 : 0;
   }
   return pl;

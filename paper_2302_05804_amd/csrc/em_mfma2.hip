@@ -38,7 +38,12 @@ constexpr int M2_KC = 44;        // box-extended kernel size for K = 43
 constexpr int M2_FROWS = 64;     // forward table rows (44 used, 2 classes of 32)
 constexpr int M2_FCH = 3;        // forward k-chunks per kernel row
 constexpr int M2_AROWS = 32;     // adjoint table rows per parity (22 used)
-constexpr int M2_FTILE = 64;     // forward: 64 x 64 frame pixels per workgroup
+constexpr int M2_FTILE = 64;     // forward: 64 x 64 frame pixels per workgroup (two image planes)
+// the one-plane binary16 form takes 128 x 64 frame pixels: 2 x 2 blocks per wave
+// halve the Toeplitz fragments read from LDS per product
+constexpr int M2_FTILE_H16 = 128;
+template <int PREC>
+constexpr int m2f_tile_h() { return PREC == EM_FP16_SPLIT ? M2_FTILE_H16 : M2_FTILE; }
 constexpr int M2_ATILE = 128;    // adjoint: 128 x 128 latent pixels per workgroup
 // bytes of one frame's fragment tables (16-byte fragments, 64 lanes)
 constexpr size_t M2_FWD_FRAME_BYTES = (size_t)M2_FROWS * M2_FCH * 2 * 64 * 16;
@@ -155,15 +160,24 @@ __device__ inline void m2f_frame_lds(const unsigned short (*sh)[C::ROWS * C::PIT
     const int cur = step & 1;
     if (r + 1 < 32) m2f_issue_T<C>(tab_t, r + 1, (void*)&tl[cur ^ 1][0][0]);
     else if (tab_next != nullptr) m2f_issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+    // the Toeplitz fragments of the class's members (2 for r < 12, else 1)
     typename C::frag Tc[2][M2_FCH][C::NB];
+    auto read_T = [&](int nm) {
 #pragma unroll
-    for (int m = 0; m < 2; ++m)
+      for (int m = 0; m < 2; ++m)
 #pragma unroll
-      for (int h = 0; h < M2_FCH; ++h)
+        for (int h = 0; h < M2_FCH; ++h)
 #pragma unroll
-        for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = tl[cur][(m * M2_FCH + h) * C::NB + q][lane];
-    if (r < M2_KC - 32) m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
-    else m2f_class<C, 1>(r, sh, Tc, row_base, col_base, acc);
+          for (int q = 0; q < C::NB; ++q)
+            if (m < nm) Tc[m][h][q] = tl[cur][(m * M2_FCH + h) * C::NB + q][lane];
+    };
+    if (r < M2_KC - 32) {
+      read_T(2);
+      m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
+    } else {
+      read_T(1);
+      m2f_class<C, 1>(r, sh, Tc, row_base, col_base, acc);
+    }
     frags_landed();
     ++step;
   }
@@ -616,26 +630,32 @@ hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fw
   return hipGetLastError();
 }
 
-int mfma2_fwd_tile() { return M2_FTILE; }
+int mfma2_fwd_tile_h(int precision) {
+  return precision == EM_FP16_SPLIT ? M2_FTILE_H16 : M2_FTILE;
+}
+int mfma2_fwd_tile_w(int) { return M2_FTILE; }
 int mfma2_adj_tile() { return M2_ATILE; }
 
 namespace {
-// forward variants (64 x 64 frame pixels): 0: 4 waves of 2x2 blocks; 1: 8 waves of 2x1;
-// 2: 8 waves of 1x2.  adjoint variants (128 x 128 latent): 0: 8 waves of 2x2 blocks
+// forward variants, FP16 split (128 x 64 frame pixels): 0: 8 waves of 2x2 blocks;
+// 1: 8 waves of 4x1; 2: 8 waves of 1x4.  Two-plane encodings (64 x 64): 0: 4 waves
+// of 2x2 blocks; 1: 8 waves of 2x1; 2: 8 waves of 1x2.  adjoint variants (128 x 128 latent): 0: 8 waves of 2x2 blocks
 // (per parity); 1: 4 waves of 4x2; 2: 4 waves of 2x4.
 template <int PREC>
 hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
                    const MfmaLaunch* d, const int4* it, int n, hipStream_t s, bool robust = false) {
   // Toeplitz fragments staged in LDS for the one-plane binary16 image
   constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
-  using F0 = M2F<PREC, 2, 2, 2, 2, PFT>;
-  using F1 = M2F<PREC, 2, 1, 2, 4, PFT>;
-  using F2 = M2F<PREC, 1, 2, 4, 2, PFT>;
+  constexpr bool H16 = PREC == EM_FP16_SPLIT;
+  using F0 = std::conditional_t<H16, M2F<PREC, 2, 2, 4, 2, PFT>, M2F<PREC, 2, 2, 2, 2, PFT>>;
+  using F1 = std::conditional_t<H16, M2F<PREC, 4, 1, 2, 4, PFT>, M2F<PREC, 2, 1, 2, 4, PFT>>;
+  using F2 = std::conditional_t<H16, M2F<PREC, 1, 4, 8, 1, PFT>, M2F<PREC, 1, 2, 4, 2, PFT>>;
   using A0 = M2A<PREC, 2, 2, 2, 4, PFT>;
   using A1 = M2A<PREC, 4, 2, 1, 4, PFT>;
   using A2 = M2A<PREC, 2, 4, 2, 2, PFT>;
-  static_assert(F0::TH == M2_FTILE && F0::TW == M2_FTILE && F1::TH == M2_FTILE &&
-                F1::TW == M2_FTILE && F2::TH == M2_FTILE && F2::TW == M2_FTILE, "fwd tile");
+  constexpr int FTH = m2f_tile_h<PREC>();
+  static_assert(F0::TH == FTH && F0::TW == M2_FTILE && F1::TH == FTH && F1::TW == M2_FTILE &&
+                F2::TH == FTH && F2::TW == M2_FTILE, "fwd tile");
   static_assert(A0::THL == M2_ATILE && A0::TWL == M2_ATILE && A1::THL == M2_ATILE &&
                 A1::TWL == M2_ATILE && A2::THL == M2_ATILE && A2::TWL == M2_ATILE, "adj tile");
 #define EM_M2_LAUNCH(KER, CFG)                                                          \
@@ -671,7 +691,8 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
 bool mfma2_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
   return dir == 0
       ? (a.H == g.Hf && a.W == g.Wf &&
-         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2_FTILE, M2_FTILE))
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W,
+                        mfma2_fwd_tile_h(g.precision), mfma2_fwd_tile_w(g.precision)))
       : (a.H == g.Hl && a.W == g.Wl && a.H % 2 == 0 && a.W % 2 == 0 &&
          launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2_ATILE, M2_ATILE));
 }
