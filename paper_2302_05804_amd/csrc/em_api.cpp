@@ -117,7 +117,8 @@ Plan make_plan(const Geometry& g) {
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.adj_variant = 0;
   if (mf && g.sr == 2)
-    pl.adj_tiles = (int)(cdiv(g.Wl, mfma2_adj_tile()) * cdiv(g.Hl, mfma2_adj_tile()));
+    pl.adj_tiles = (int)(cdiv(g.Wl, mfma2_adj_tile_w(g.precision)) *
+                         cdiv(g.Hl, mfma2_adj_tile_h(g.precision)));
   else if (mf)
     pl.adj_tiles = (int)(cdiv(g.Wl, mfma_tile_w()) * cdiv(g.Hl, mfma_tile_h()));
   else
@@ -160,10 +161,11 @@ Plan make_serving_plan(const Geometry& g) {
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
   if (uses_mfma(g)) {
     // the variants em_autotune picks on the large workloads (33 x 4096^2 sr = 1,
-    // 16 x 2048^2 sr = 2) for each encoding
+    // 16 x 2048^2 sr = 2) for each encoding; for the sr = 2 FP16 adjoint the 4x2-block
+    // variant, 3% slower alone but free of scratch reloads in its batched form
     const bool f16 = g.precision == EM_FP16_SPLIT;
     pl.fwd_variant = g.sr == 1 ? (f16 ? 2 : 0) : (f16 ? 2 : 0);
-    pl.adj_variant = g.sr == 1 ? 2 : 0;
+    pl.adj_variant = g.sr == 1 ? 2 : (f16 ? 1 : 0);
   }
   return pl;
 }

@@ -146,7 +146,8 @@ hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fw
 size_t mfma2_table_bytes(int n, int dir);
 int mfma2_fwd_tile_h(int precision);
 int mfma2_fwd_tile_w(int precision);
-int mfma2_adj_tile();
+int mfma2_adj_tile_h(int precision);
+int mfma2_adj_tile_w(int precision);
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
                                const int4* items, int n_items, int grid, hipStream_t s,
                                bool robust = false);

@@ -45,6 +45,11 @@ constexpr int M2_FTILE_H16 = 128;
 template <int PREC>
 constexpr int m2f_tile_h() { return PREC == EM_FP16_SPLIT ? M2_FTILE_H16 : M2_FTILE; }
 constexpr int M2_ATILE = 128;    // adjoint: 128 x 128 latent pixels per workgroup
+// the one-plane binary16 form: 128 x 256 latent pixels, so that 8 waves own 2 x 4
+// (or 4 x 2, 1 x 8) blocks and a class's Toeplitz fragments feed more products
+constexpr int M2_ATILE_W16 = 256;
+template <int PREC>
+constexpr int m2a_tile_w() { return PREC == EM_FP16_SPLIT ? M2_ATILE_W16 : M2_ATILE; }
 // bytes of one frame's fragment tables (16-byte fragments, 64 lanes)
 constexpr size_t M2_FWD_FRAME_BYTES = (size_t)M2_FROWS * M2_FCH * 2 * 64 * 16;
 constexpr size_t M2_ADJ_FRAME_BYTES = (size_t)2 * M2_AROWS * 2 * 64 * 16;
@@ -531,13 +536,18 @@ __global__ __launch_bounds__(C::NT) void m2f_t_batched(const MfmaLaunch* __restr
     __syncthreads();
   }
 }
+// One work item of the batched adjoint, out of line: inlined into the item loop,
+// the body's accumulators and the loop state together exceed the register file.
+template <class C>
+__device__ __attribute__((noinline)) void m2a_item(const MfmaLaunch d, int tile, int group) {
+  m2a_body<C>(d, tile, group);
+}
 template <class C>
 __global__ __launch_bounds__(C::NT) void m2a_batched(const MfmaLaunch* __restrict__ descs,
                                                      const int4* __restrict__ items, int n) {
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const int4 w = items[it];
-    const MfmaLaunch d = descs[w.x];
-    m2a_body<C>(d, w.y, w.z);
+    m2a_item<C>(descs[w.x], w.y, w.z);
     __syncthreads();
   }
 }
@@ -634,13 +644,18 @@ int mfma2_fwd_tile_h(int precision) {
   return precision == EM_FP16_SPLIT ? M2_FTILE_H16 : M2_FTILE;
 }
 int mfma2_fwd_tile_w(int) { return M2_FTILE; }
-int mfma2_adj_tile() { return M2_ATILE; }
+int mfma2_adj_tile_h(int) { return M2_ATILE; }
+int mfma2_adj_tile_w(int precision) {
+  return precision == EM_FP16_SPLIT ? M2_ATILE_W16 : M2_ATILE;
+}
 
 namespace {
 // forward variants, FP16 split (128 x 64 frame pixels): 0: 8 waves of 2x2 blocks;
 // 1: 8 waves of 4x1; 2: 8 waves of 1x4.  Two-plane encodings (64 x 64): 0: 4 waves
-// of 2x2 blocks; 1: 8 waves of 2x1; 2: 8 waves of 1x2.  adjoint variants (128 x 128 latent): 0: 8 waves of 2x2 blocks
-// (per parity); 1: 4 waves of 4x2; 2: 4 waves of 2x4.
+// of 2x2 blocks; 1: 8 waves of 2x1; 2: 8 waves of 1x2.  Adjoint variants, FP16 split
+// (128 x 256 latent): 0: 8 waves of 2x4 blocks (per parity); 1: 8 waves of 4x2;
+// 2: 8 waves of 1x8.  Two-plane encodings (128 x 128): 0: 8 waves of 2x2; 1: 4 waves
+// of 4x2; 2: 4 waves of 2x4.
 template <int PREC>
 hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
                    const MfmaLaunch* d, const int4* it, int n, hipStream_t s, bool robust = false) {
@@ -650,14 +665,15 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
   using F0 = std::conditional_t<H16, M2F<PREC, 2, 2, 4, 2, PFT>, M2F<PREC, 2, 2, 2, 2, PFT>>;
   using F1 = std::conditional_t<H16, M2F<PREC, 4, 1, 2, 4, PFT>, M2F<PREC, 2, 1, 2, 4, PFT>>;
   using F2 = std::conditional_t<H16, M2F<PREC, 1, 4, 8, 1, PFT>, M2F<PREC, 1, 2, 4, 2, PFT>>;
-  using A0 = M2A<PREC, 2, 2, 2, 4, PFT>;
-  using A1 = M2A<PREC, 4, 2, 1, 4, PFT>;
-  using A2 = M2A<PREC, 2, 4, 2, 2, PFT>;
+  using A0 = std::conditional_t<H16, M2A<PREC, 2, 4, 2, 4, PFT>, M2A<PREC, 2, 2, 2, 4, PFT>>;
+  using A1 = std::conditional_t<H16, M2A<PREC, 4, 2, 1, 8, PFT>, M2A<PREC, 4, 2, 1, 4, PFT>>;
+  using A2 = std::conditional_t<H16, M2A<PREC, 1, 8, 4, 2, PFT>, M2A<PREC, 2, 4, 2, 2, PFT>>;
   constexpr int FTH = m2f_tile_h<PREC>();
   static_assert(F0::TH == FTH && F0::TW == M2_FTILE && F1::TH == FTH && F1::TW == M2_FTILE &&
                 F2::TH == FTH && F2::TW == M2_FTILE, "fwd tile");
-  static_assert(A0::THL == M2_ATILE && A0::TWL == M2_ATILE && A1::THL == M2_ATILE &&
-                A1::TWL == M2_ATILE && A2::THL == M2_ATILE && A2::TWL == M2_ATILE, "adj tile");
+  constexpr int ATW = m2a_tile_w<PREC>();
+  static_assert(A0::THL == M2_ATILE && A0::TWL == ATW && A1::THL == M2_ATILE && A1::TWL == ATW &&
+                A2::THL == M2_ATILE && A2::TWL == ATW, "adj tile");
 #define EM_M2_LAUNCH(KER, CFG)                                                          \
   do {                                                                                  \
     if (batched)                                                                        \
@@ -694,7 +710,8 @@ bool mfma2_desc_ok(const Geometry& g, int dir, int tiles, int groups, const Mfma
          launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W,
                         mfma2_fwd_tile_h(g.precision), mfma2_fwd_tile_w(g.precision)))
       : (a.H == g.Hl && a.W == g.Wl && a.H % 2 == 0 && a.W % 2 == 0 &&
-         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2_ATILE, M2_ATILE));
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W,
+                        mfma2_adj_tile_h(g.precision), mfma2_adj_tile_w(g.precision)));
 }
 
 hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int groups,
