@@ -354,6 +354,42 @@ def test_literal_equals_adjoint_for_constant_variance():
     np.testing.assert_allclose(a, b, rtol=1e-11, atol=1e-11 * a.max())
 
 
+@pytest.mark.parametrize("shape", [(8, 8), (8, 6)])
+def test_literal_weighting_dense_spatially_varying(shape):
+    """Eq. (2) as typeset, with u varying over pixels and masked: from explicit
+    F_t matrices, B = sum_t u_t (.) (F_t^T yhat_t) and
+    Dn = sum_t u_t (.) (F_t^T F_t x), u read on the latent grid (= frame grid,
+    sr = 1) at the same pixel as the adjoint's output.  A non-square grid and
+    per-pixel random u make a transposed, shifted or frame-swapped read of u
+    fail; so does weighting before the adjoint."""
+    Hl, Wl = shape
+    n, K = 3, 5
+    y, v, psf, _ = small_problem(Hl, Wl, n, K, seed=82, mask=0.15, sky=(5.0, 300.0))
+    rng = RNG(83)
+    # spread v over two decades so that u differs strongly between pixels
+    v = np.where(np.isinf(v), v, v * rng.uniform(0.1, 10.0, v.shape)).astype(np.float32)
+    v64 = v.astype(np.float64)
+    u = np.where(np.isinf(v64), 0.0, 1.0 / v64)
+    yh = np.where(u > 0, y.astype(np.float64), 0.0)
+    x = positive((Hl, Wl), 84)
+    Fs = [dense_F(psf[t], Hl, Wl, 1) for t in range(n)]
+    B = sum(u[t].ravel() * (Fs[t].T @ yh[t].ravel()) for t in range(n)).reshape(Hl, Wl)
+    Dn = sum(u[t].ravel() * (Fs[t].T @ (Fs[t] @ x.ravel().astype(np.float64)))
+             for t in range(n)).reshape(Hl, Wl)
+    Bo = oracle.numerator(y, v, psf, mode=oracle.W_LITERAL)
+    Dno = oracle.denominator(y, v, psf, x, mode=oracle.W_LITERAL)
+    np.testing.assert_allclose(Bo, B, rtol=1e-12, atol=1e-12 * np.abs(B).max())
+    np.testing.assert_allclose(Dno, Dn, rtol=1e-12, atol=1e-12 * np.abs(Dn).max())
+    # one step of the typeset update, with the clamp and guards
+    x64 = x.astype(np.float64)
+    x1 = np.where(Dn == 0, x64, x64 * np.maximum(B, 0.0) / np.where(Dn == 0, 1.0, Dn))
+    xo = oracle.run(y, v, psf, x, 1, mode=oracle.W_LITERAL)
+    np.testing.assert_allclose(xo, x1, rtol=1e-12, atol=1e-12 * x1.max())
+    # the two weightings really differ here, so the pin tells them apart
+    Ba = oracle.numerator(y, v, psf, mode=oracle.W_ADJOINT)
+    assert np.abs(Ba - B).max() > 1e-3 * np.abs(B).max()
+
+
 def test_literal_differs_for_varying_variance():
     y, v, psf, _ = small_problem(16, 16, 3, 5, seed=81, mask=0.1)
     x0 = positive((16, 16), 8)
