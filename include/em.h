@@ -79,7 +79,15 @@ extern "C" {
 
 /* placement of the inverse-variance weights, and the noise model */
 #define EM_W_ADJOINT   0    /* sum_t F_t^T (u_t (.) .)  (default)              */
-#define EM_W_LITERAL   1    /* sum_t u_t (.) F_t^T (.)  (Eq. (2) as typeset, sr=1) */
+#define EM_W_LITERAL   1    /* sum_t u_t (.) F_t^T (.)  (Eq. (2) as typeset, sr=1):
+                               B = sum_t u_t (.) F_t^T yhat_t and
+                               Dn = sum_t u_t (.) F_t^T F_t x, u_t read on the
+                               latent grid (= the frame grid for sr = 1).  Each
+                               frame's adjoint goes to its own plane (the
+                               workspace holds n latent planes) and the planes
+                               are summed with their weights in frame order;
+                               l(x) is that of Eq. (1).  Not served by
+                               em_server (EM_ENOTSUP); EM_ENOTSUP for sr = 2. */
 #define EM_W_STUDENT_T 2    /* Student-t noise with nu degrees of freedom and
                                scale v (the heavier-tailed noise the paper
                                names as future work): every iteration gives
@@ -107,8 +115,7 @@ typedef struct {
     int32_t psf_k;        /* odd, 1 <= K <= 43                               */
     int32_t sr;           /* super-resolution factor: 1 or 2 (Eq. (3))       */
     int32_t precision;    /* EM_FP32, EM_BF16_SPLIT, EM_FP16_SPLIT, EM_BF16   */
-    int32_t weight_mode;  /* EM_W_ADJOINT, EM_W_STUDENT_T (EM_W_LITERAL: sr = 1,
-                             oracle only)                                      */
+    int32_t weight_mode;  /* EM_W_ADJOINT, EM_W_LITERAL (sr = 1), EM_W_STUDENT_T */
     float nu;             /* EM_W_STUDENT_T: degrees of freedom in (0, 1e30];
                              ignored otherwise                                 */
 } em_problem;
@@ -206,10 +213,11 @@ int em_set_variants(em_ctx* ctx, int32_t fwd_variant, int32_t adj_variant);
 /*
  * Autotuner: times every variant of the forward and the adjoint kernel on the
  * job's own data (n_rep launches each after one warm-up, HIP events on the
- * job's stream; the iterate x is not modified), selects the fastest for ctx
- * and records the choice for later em_init calls of the same problem shape
- * in this process.  Writes the chosen variants and, if ms != NULL, the mean
- * launch times ms[dir * em_variant_count() + v].  Synchronous.
+ * job's stream; the iterate x is not modified) and selects the fastest for
+ * ctx alone.  Every job starts on variants 0 / 0, whatever other jobs of the
+ * process chose, so its arithmetic never depends on them.  Writes the chosen
+ * variants and, if ms != NULL, the mean launch times
+ * ms[dir * em_variant_count() + v].  Synchronous.
  * EM_ENOTSUP for FP32 (one variant).
  */
 int em_autotune(em_ctx* ctx, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_variant,
@@ -363,7 +371,8 @@ int em_wait(em_server* server, em_job_id id, float* x_host_out, double* loglik_o
 /* Cancel a queued or running job (running jobs stop at the next round). */
 int em_cancel(em_server* server, em_job_id id);
 
-/* Forget a finished job and free its host result (EM_EAGAIN if pending). */
+/* Forget a finished job and free its host result (EM_EAGAIN while it is
+ * pending or another thread is still inside em_wait for it). */
 int em_release(em_server* server, em_job_id id);
 
 /* Steady-clock seconds at which the job was submitted, admitted, finished. */
@@ -373,6 +382,13 @@ int em_job_times(em_server* server, em_job_id id, double* t_submit, double* t_ad
 /* stats[8]: queued, active, done, failed, cancelled, rounds run, round graphs
  * built, arena bytes in use. */
 int em_server_stats(em_server* server, int64_t* stats);
+
+/* Seconds the server's worker has spent, since creation, in each phase:
+ * sec[0] admission (input upload, set-up of u, B and x0), sec[1] rebuilding
+ * the round after the set of jobs changed (descriptors, graph capture),
+ * sec[2] rounds (launch to completion of the batched iterations), sec[3]
+ * finishing jobs (final log-likelihood, result copy to the host). */
+int em_server_phase_seconds(em_server* server, double* sec);
 
 #ifdef __cplusplus
 }

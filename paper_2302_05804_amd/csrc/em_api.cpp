@@ -87,16 +87,6 @@ bool make_geometry(const void* problem, Geometry* g, const char** why) {
   return true;
 }
 
-// Kernel variants chosen by em_autotune, per problem shape and precision.
-// Process-wide; a job's variant depends only on its own shape.
-using TuneKey = std::tuple<int, int, int, int, int, int, int>;
-static std::mutex g_tune_mu;
-static std::map<TuneKey, std::pair<int, int>> g_tune;
-
-static TuneKey tune_key(const Geometry& g) {
-  return TuneKey(g.n, g.Hf, g.Wf, g.KT, g.sr, g.precision, g.weight_mode);
-}
-
 Plan make_plan(const Geometry& g) {
   Plan pl{};
   // ~4 workgroups per compute unit on 256 CUs (matrix-core kernels: one
@@ -132,16 +122,17 @@ Plan make_plan(const Geometry& g) {
     pl.adj_fpg = (int)cdiv(g.n, ag);
     pl.adj_groups = (int)cdiv(g.n, pl.adj_fpg);
   }
+  if (g.weight_mode == EM_W_LITERAL) {
+    // the typeset weighting multiplies each frame's adjoint by its own u:
+    // one frame per group, weighted sum of the planes afterwards
+    pl.adj_fpg = 1;
+    pl.adj_groups = g.n;
+  }
+  pl.adj_fused = pl.adj_groups == 1 && g.weight_mode != EM_W_LITERAL;
+  // every job starts on the default variants; only em_autotune or
+  // em_set_variants on that job change them
   pl.fwd_variant = 0;
   pl.adj_variant = 0;
-  if (mf) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(g));
-    if (it != g_tune.end()) {
-      pl.fwd_variant = it->second.first;
-      pl.adj_variant = it->second.second;
-    }
-  }
   pl.prep_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv((int64_t)g.n * g.Nf, 256)));
   pl.upd_blocks = (int)std::max<int64_t>(1, std::min<int64_t>(4096, cdiv(g.Nl, 256)));
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
@@ -156,6 +147,7 @@ Plan make_serving_plan(const Geometry& g) {
   Plan pl = make_plan(g);
   pl.adj_groups = 1;
   pl.adj_fpg = g.n;
+  pl.adj_fused = 1;
   pl.fwd_fpg = std::min(g.n, 4);
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
@@ -187,12 +179,12 @@ Layout make_layout(const Geometry& g, const Plan& pl) {
   L.r = take(nf * sizeof(float));
   L.ry = take(g.weight_mode == EM_W_STUDENT_T ? nf * sizeof(float) : 0);
   L.B = take((size_t)g.Nl * sizeof(float));
-  L.planes = take(G > 1 ? (size_t)G * g.Nl * sizeof(float) : 0);
+  L.planes = take(pl.adj_fused ? 0 : (size_t)G * g.Nl * sizeof(float));
   L.tab = take((size_t)g.n * g.KC * TAB_LD * sizeof(float));
   L.mtab_fwd = take(uses_mfma(g) ? mfma_table_bytes(g, 0) : 0);
   L.mtab_adj = take(uses_mfma(g) ? mfma_table_bytes(g, 1) : 0);
   L.tune = take(uses_mfma(g) ? (size_t)g.Nl * sizeof(float) : 0);
-  L.part_ll = take((size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double));
+  L.part_ll = take((size_t)std::max(pl.fwd_tiles * pl.fwd_groups, pl.prep_blocks) * sizeof(double));
   L.part_rc = take((size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double));
   L.part_prep = take((size_t)3 * pl.prep_blocks * sizeof(double));
   L.scalars = take(S_COUNT * sizeof(double));
@@ -275,7 +267,9 @@ size_t em_workspace_bytes(const em_problem* p) {
 // Adjoint of every frame of `in` (n x Nf), summed over frames, into `out`
 // (Nl floats); never applies the update.
 static int adjoint_sum(em_ctx* c, const float* in, float* out) {
-  float* dst = c->pl.adj_groups > 1 ? c->planes : out;
+  const bool lit = c->g.weight_mode == EM_W_LITERAL;
+  const bool via_planes = c->pl.adj_groups > 1 || lit;
+  float* dst = via_planes ? c->planes : out;
   if (uses_mfma(c->g)) {
     MfmaLaunch m{};
     m.in = in;
@@ -304,8 +298,9 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
     a.plane = dst;
     EM_HIP(launch_adjoint(c->g, c->pl, a, c->stream));
   }
-  if (c->pl.adj_groups > 1)
-    EM_HIP(launch_sum_planes(c->planes, c->pl.adj_groups, c->g.Nl, out, c->stream));
+  if (via_planes)
+    EM_HIP(launch_sum_planes(c->planes, lit ? c->u : nullptr, c->pl.adj_groups, c->g.Nl, out,
+                             c->stream));
   return EM_OK;
 }
 
@@ -344,7 +339,7 @@ void fill_forward_fp32(const em_ctx* c, FwdLaunch* f, bool write_r, bool loglik)
 }
 
 void fill_adjoint_mfma(const em_ctx* c, MfmaLaunch* m, double* part_rc) {
-  const bool fused = c->pl.adj_groups == 1;
+  const bool fused = c->pl.adj_fused != 0;
   *m = MfmaLaunch{};
   m->in = c->r;
   m->tab = c->mtab_adj;
@@ -361,7 +356,7 @@ void fill_adjoint_mfma(const em_ctx* c, MfmaLaunch* m, double* part_rc) {
 }
 
 void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc) {
-  const bool fused = c->pl.adj_groups == 1;
+  const bool fused = c->pl.adj_fused != 0;
   *a = AdjLaunch{};
   a->in = c->r;
   a->tab = c->tab;
@@ -381,18 +376,30 @@ void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc) {
 
 }  // namespace em
 
-// Forward pass at the current iterate: r = u F x (if write_r) and loglik partials.
-static int forward_pass(em_ctx* c, bool write_r, bool loglik) {
+// Forward pass at the current iterate: r = u F x (if write_r) and loglik
+// partials.  Under the typeset weighting r is the raw model F x (the weights act
+// after the adjoint) and the loglik partials come from a separate pass over r,
+// u and y.  *n_ll: the number of loglik partials written (may be NULL).
+static int forward_pass(em_ctx* c, bool write_r, bool loglik, int* n_ll = nullptr) {
+  const bool raw = write_r && c->g.weight_mode == EM_W_LITERAL;
+  if (n_ll) *n_ll = c->pl.fwd_tiles * c->pl.fwd_groups;
   if (uses_mfma(c->g)) {
     MfmaLaunch m;
-    fill_forward_mfma(c, &m, write_r, loglik);
+    fill_forward_mfma(c, &m, write_r, loglik && !raw);
+    if (raw) m.u = nullptr;
     EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_variant, c->pl.fwd_tiles, c->pl.fwd_groups, m,
                        c->stream));
-    return EM_OK;
+  } else {
+    FwdLaunch f;
+    fill_forward_fp32(c, &f, write_r, loglik && !raw);
+    if (raw) f.u = nullptr;
+    EM_HIP(launch_forward(c->g, c->pl, f, c->stream));
   }
-  FwdLaunch f;
-  fill_forward_fp32(c, &f, write_r, loglik);
-  EM_HIP(launch_forward(c->g, c->pl, f, c->stream));
+  if (raw && loglik) {
+    EM_HIP(launch_loglik_partials(c->r, c->u, c->y, (int64_t)c->g.n * c->g.Nf, c->part_ll,
+                                  c->pl.prep_blocks, c->stream));
+    if (n_ll) *n_ll = c->pl.prep_blocks;
+  }
   return EM_OK;
 }
 
@@ -442,7 +449,8 @@ static int adjoint_launch(em_ctx* c, double* part_rc) {
 }
 
 static int update_launch(em_ctx* c, double* part_rc) {
-  EM_HIP(launch_update(c->planes, c->pl.adj_groups, c->g.Nl, c->B, c->x, part_rc,
+  const float* w = c->g.weight_mode == EM_W_LITERAL ? c->u : nullptr;
+  EM_HIP(launch_update(c->planes, w, c->pl.adj_groups, c->g.Nl, c->B, c->x, part_rc,
                        c->pl.upd_blocks, c->stream));
   return EM_OK;
 }
@@ -451,7 +459,7 @@ static int update_launch(em_ctx* c, double* part_rc) {
 static int adjoint_update(em_ctx* c, double* part_rc, int* n_rc) {
   int rc = adjoint_launch(c, part_rc);
   if (rc) return rc;
-  if (c->pl.adj_groups == 1) {
+  if (c->pl.adj_fused) {
     *n_rc = c->pl.adj_tiles;
     return EM_OK;
   }
@@ -464,13 +472,14 @@ static int adjoint_update(em_ctx* c, double* part_rc, int* n_rc) {
 // before the adjoint of the denominator (which applies the update).
 static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
   const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
-  int rc = robust ? robust_forward(c, loglik) : forward_pass(c, true, loglik);
+  int n_ll = c->pl.fwd_tiles * c->pl.fwd_groups;
+  int rc = robust ? robust_forward(c, loglik) : forward_pass(c, true, loglik, &n_ll);
   if (rc) return rc;
   if (robust && (rc = adjoint_sum(c, c->ry, c->B))) return rc;
   int n_rc = 0;
   if ((rc = adjoint_update(c, relchange ? c->part_rc : nullptr, &n_rc))) return rc;
   if (loglik || relchange) {
-    EM_HIP(launch_finalize_iter(loglik ? c->part_ll : nullptr, c->pl.fwd_tiles * c->pl.fwd_groups,
+    EM_HIP(launch_finalize_iter(loglik ? c->part_ll : nullptr, n_ll,
                                 relchange ? c->part_rc : nullptr, n_rc, c->scalars, c->trace_ll,
                                 c->trace_rc, c->counters, c->stream));
   }
@@ -530,8 +539,8 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
-  if (g.weight_mode == EM_W_LITERAL)
-    return fail(EM_ENOTSUP, "weight mode %d not provided", g.weight_mode);
+  if (g.weight_mode == EM_W_LITERAL && g.sr != 1)
+    return fail(EM_ENOTSUP, "the typeset weighting is defined for sr = 1 only");
   const Plan pl = serving ? make_serving_plan(g) : make_plan(g);
   const Layout L = make_layout(g, pl);
   if (ws_bytes < L.total)
@@ -578,6 +587,7 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   pr.flags = c->counters + 4;
   pr.count = (int64_t)g.n * g.Nf;
   pr.blocks = pl.prep_blocks;
+  pr.raw_y = g.weight_mode == EM_W_LITERAL ? 1 : 0;
   if ((e = launch_prep(pr, c->stream)) != hipSuccess)
     return bail(fail(EM_EDEVICE, "prep: %s", hipGetErrorString(e)));
   if ((e = launch_psf_tables(g, psf, c->tab, c->counters + 4, c->stream)) != hipSuccess)
@@ -707,7 +717,7 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
   for (int i = 0; i < 5; ++i) EM_HIP(hipEventCreate(&ev[i]));
   double acc[4] = {0, 0, 0, 0};
   int rc = EM_OK;
-  const bool fused = c->pl.adj_groups == 1;
+  const bool fused = c->pl.adj_fused != 0;
   const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
   for (int k = 0; k < n_iter && rc == EM_OK; ++k) {
     EM_HIP(hipEventRecord(ev[0], c->stream));
@@ -778,11 +788,11 @@ int em_check_plan(const em_problem* p) {
     }
     // workspace capacities for what the kernels write
     const Layout& L = c.lay;
-    const size_t ll = (size_t)pl.fwd_tiles * pl.fwd_groups * sizeof(double);
+    const size_t ll = (size_t)std::max(pl.fwd_tiles * pl.fwd_groups, pl.prep_blocks) * sizeof(double);
     const size_t rcb = (size_t)2 * std::max(pl.adj_tiles, pl.upd_blocks) * sizeof(double);
     if (L.part_rc - L.part_ll < ll || L.part_prep - L.part_rc < rcb)
       return fail(EM_EINVAL, "%s: partial-sum buffers too small", what);
-    if (pl.adj_groups > 1 && L.tab - L.planes < (size_t)pl.adj_groups * g.Nl * sizeof(float))
+    if (!pl.adj_fused && L.tab - L.planes < (size_t)pl.adj_groups * g.Nl * sizeof(float))
       return fail(EM_EINVAL, "%s: partial planes too small", what);
   }
   return EM_OK;
@@ -861,10 +871,6 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
   c->pl.fwd_variant = bf;
   c->pl.adj_variant = ba;
   drop_graphs(c);
-  {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(c->g)] = std::make_pair(bf, ba);
-  }
   if (fwd_variant) *fwd_variant = bf;
   if (adj_variant) *adj_variant = ba;
   if (ms) std::copy(t.begin(), t.end(), ms);

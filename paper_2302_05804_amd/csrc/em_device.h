@@ -30,6 +30,19 @@ __device__ inline int lane_column(int lane) {
 typedef __attribute__((address_space(4))) const float* cfloat_ptr;
 __device__ inline cfloat_ptr as_const(const float* p) { return (cfloat_ptr)(p); }
 
+// The multiplicative update of Eq. (2) for one latent pixel, with the
+// non-negativity clamp and the guards: a zero stays zero (never 0 * inf); a
+// pixel no weighted frame pixel sees (Dn = 0) keeps its value; otherwise the
+// ratio q = max(B, 0) / Dn is formed first and then applied, x * q.  Every
+// kernel that updates x calls this one function, so the rule is the same bit
+// for bit in all of them.
+__device__ inline float em_update_value(float xo, float Bv, float Dn) {
+  if (xo == 0.f) return 0.f;
+  if (Dn == 0.f) return xo;
+  const float q = fmaxf(Bv, 0.f) / Dn;
+  return xo * q;
+}
+
 // FP64 sum over a wave of 64 lanes; the result is valid in lane 0.  The
 // reduction tree is fixed, so the result is reproducible bit for bit.
 __device__ inline double wave_sum(double v) {

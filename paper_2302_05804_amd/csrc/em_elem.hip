@@ -15,7 +15,8 @@ namespace em {
 
 constexpr int EW_NT = 256;
 
-// u = 1/v (0 where v = +inf), w = u * y (0 where masked), FP64 partials of
+// u = 1/v (0 where v = +inf), w = u * y (or y alone when raw_y; 0 where
+// masked in both), FP64 partials of
 // sum u y, sum u and sum_{u>0} ln(2 pi v); counts invalid pixels.
 __global__ __launch_bounds__(EW_NT) void prep_kernel(PrepLaunch a) {
   __shared__ double red[3 * EW_NT / 64];
@@ -32,7 +33,7 @@ __global__ __launch_bounds__(EW_NT) void prep_kernel(PrepLaunch a) {
       ++bad;
     } else {
       uu = 1.0f / vv;
-      ww = uu * yy;
+      ww = a.raw_y ? yy : uu * yy;
       suy += (double)yy / (double)vv;
       su += 1.0 / (double)vv;
       sl += log(2.0 * M_PI * (double)vv);
@@ -166,44 +167,49 @@ hipError_t launch_init_x(const float* x0, float* x, const double* scalars, int64
   return hipGetLastError();
 }
 
-// out = sum_g planes[g] in order g = 0..G-1.
-__global__ __launch_bounds__(EW_NT) void sum_planes_kernel(const float* planes, int G, int64_t Nl,
-                                                           float* out) {
-  const int64_t stride = (int64_t)gridDim.x * EW_NT;
-  for (int64_t p = (int64_t)blockIdx.x * EW_NT + threadIdx.x; p < Nl; p += stride) {
+// Sum of G planes at pixel p in order g = 0..G-1; with per-plane weights w
+// (the typeset weighting of Eq. (2): plane g is frame g's adjoint and w holds
+// the frames' u on the same grid) each plane is multiplied by its weight first.
+__device__ inline float plane_sum(const float* planes, const float* w, int G, int64_t Nl,
+                                  int64_t p) {
+  if (w == nullptr) {
     float acc = planes[p];
     for (int g = 1; g < G; ++g) acc += planes[(int64_t)g * Nl + p];
-    out[p] = acc;
+    return acc;
   }
+  float acc = w[p] * planes[p];
+  for (int g = 1; g < G; ++g) acc = fmaf(w[(int64_t)g * Nl + p], planes[(int64_t)g * Nl + p], acc);
+  return acc;
 }
 
-hipError_t launch_sum_planes(const float* planes, int G, int64_t Nl, float* out, hipStream_t s) {
-  hipLaunchKernelGGL(sum_planes_kernel, dim3(ew_blocks(Nl)), dim3(EW_NT), 0, s, planes, G, Nl,
+__global__ __launch_bounds__(EW_NT) void sum_planes_kernel(const float* planes, const float* w,
+                                                           int G, int64_t Nl, float* out) {
+  const int64_t stride = (int64_t)gridDim.x * EW_NT;
+  for (int64_t p = (int64_t)blockIdx.x * EW_NT + threadIdx.x; p < Nl; p += stride)
+    out[p] = plane_sum(planes, w, G, Nl, p);
+}
+
+hipError_t launch_sum_planes(const float* planes, const float* w, int G, int64_t Nl, float* out,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(sum_planes_kernel, dim3(ew_blocks(Nl)), dim3(EW_NT), 0, s, planes, w, G, Nl,
                      out);
   return hipGetLastError();
 }
 
 // Multiplicative update of Eq. (2) from G partial planes of Dn (summed in
-// order), with the non-negativity clamp and the 0/0 guards; FP64 partials of
-// ||x_new - x||^2 and ||x||^2 (if part != nullptr).
-__global__ __launch_bounds__(EW_NT) void update_kernel(const float* planes, int G, int64_t Nl,
-                                                       const float* B, float* x, double* part) {
+// order, weighted as in plane_sum when w != nullptr), with the non-negativity
+// clamp and the 0/0 guards; FP64 partials of ||x_new - x||^2 and ||x||^2 (if
+// part != nullptr).
+__global__ __launch_bounds__(EW_NT) void update_kernel(const float* planes, const float* w, int G,
+                                                       int64_t Nl, const float* B, float* x,
+                                                       double* part) {
   __shared__ double red[2 * EW_NT / 64];
   const int64_t stride = (int64_t)gridDim.x * EW_NT;
   double dsq = 0.0, xsq = 0.0;
   for (int64_t p = (int64_t)blockIdx.x * EW_NT + threadIdx.x; p < Nl; p += stride) {
-    float Dn = planes[p];
-    for (int g = 1; g < G; ++g) Dn += planes[(int64_t)g * Nl + p];
+    const float Dn = plane_sum(planes, w, G, Nl, p);
     const float xo = x[p];
-    float xn;
-    if (xo == 0.f) {
-      xn = 0.f;
-    } else if (Dn == 0.f) {
-      xn = xo;
-    } else {
-      const float q = fmaxf(B[p], 0.f) / Dn;
-      xn = xo * q;
-    }
+    const float xn = em_update_value(xo, B[p], Dn);
     x[p] = xn;
     const double d = (double)xn - (double)xo;
     dsq += d * d;
@@ -220,9 +226,35 @@ __global__ __launch_bounds__(EW_NT) void update_kernel(const float* planes, int 
   }
 }
 
-hipError_t launch_update(const float* planes, int G, int64_t Nl, const float* B, float* x,
-                         double* part, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(update_kernel, dim3(blocks), dim3(EW_NT), 0, s, planes, G, Nl, B, x, part);
+hipError_t launch_update(const float* planes, const float* w, int G, int64_t Nl, const float* B,
+                         float* x, double* part, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(update_kernel, dim3(blocks), dim3(EW_NT), 0, s, planes, w, G, Nl, B, x, part);
+  return hipGetLastError();
+}
+
+// FP64 partial sums of u (y - m)^2 over observed pixels (u > 0), one per block:
+// the quadratic term of l(x) (Eq. (1)) from a raw model m = F_t x.
+__global__ __launch_bounds__(EW_NT) void loglik_partials_kernel(const float* m, const float* u,
+                                                                const float* y, int64_t count,
+                                                                double* part) {
+  __shared__ double red[EW_NT / 64];
+  const int64_t stride = (int64_t)gridDim.x * EW_NT;
+  double acc = 0.0;
+  for (int64_t p = (int64_t)blockIdx.x * EW_NT + threadIdx.x; p < count; p += stride) {
+    const float uu = u[p];
+    if (uu > 0.f) {
+      const double d = (double)y[p] - (double)m[p];
+      acc += (double)uu * d * d;
+    }
+  }
+  const double s = block_sum<EW_NT>(acc, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+hipError_t launch_loglik_partials(const float* m, const float* u, const float* y, int64_t count,
+                                  double* part, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(loglik_partials_kernel, dim3(blocks), dim3(EW_NT), 0, s, m, u, y, count,
+                     part);
   return hipGetLastError();
 }
 

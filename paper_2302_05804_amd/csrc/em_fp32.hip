@@ -222,18 +222,6 @@ __device__ inline void fwd2_body(const FwdLaunch& a, const int tile, const int g
 }
 
 // ---------------------------------------------------------------------------
-// Epilogue of the adjoint: either store the frame-group partial sum, or apply
-// the multiplicative update of Eq. (2) with the clamp and guards:
-//   x == 0 -> 0;  Dn == 0 -> x;  else x * (max(B,0) / Dn).
-// ---------------------------------------------------------------------------
-__device__ inline float em_update_value(float xo, float Bv, float Dn) {
-  if (xo == 0.f) return 0.f;
-  if (Dn == 0.f) return xo;
-  const float q = fmaxf(Bv, 0.f) / Dn;
-  return xo * q;
-}
-
-// ---------------------------------------------------------------------------
 // sr = 1 adjoint: s[k,l] = sum_{a,b} f_t[a,b] r_t[k-c+a, l-c+b], summed over t.
 // ---------------------------------------------------------------------------
 template <int KT, int R, int WV>

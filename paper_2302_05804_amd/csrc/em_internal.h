@@ -61,8 +61,10 @@ struct Plan {
   // adjoint
   int adj_variant;
   int adj_tiles;       // latent-grid tiles
-  int adj_groups;      // frame groups; 1 => update fused into the adjoint
+  int adj_groups;      // frame groups
   int adj_fpg;
+  int adj_fused;       // 1 => update fused into the adjoint (one frame group and
+                       // the weights on the frame grid); else partial planes
   // reductions
   int prep_blocks;     // blocks of the per-pixel prep kernel
   int upd_blocks;      // blocks of the separate update kernel
@@ -189,7 +191,8 @@ struct PrepLaunch {
   const float* y;
   const float* v;
   float* u;
-  float* w;            // u * y (masked y -> 0)
+  float* w;            // u * y, or y alone when raw_y (masked y -> 0 in both)
+  int raw_y;
   double* part;        // 3 x blocks partial sums
   int* flags;          // [0] invalid data count
   int64_t count;       // n * Nf
@@ -200,14 +203,21 @@ hipError_t launch_prep(const PrepLaunch& a, hipStream_t s);
 hipError_t launch_psf_tables(const Geometry& g, const float* psf, float* tab, int* flags,
                              hipStream_t s);
 
+// FP64 partials of sum_{u>0} u (y - m)^2 over `count` frame pixels, one per
+// block (`blocks` of them), for forwards that write the raw model m = F_t x.
+hipError_t launch_loglik_partials(const float* m, const float* u, const float* y, int64_t count,
+                                  double* part, int blocks, hipStream_t s);
 // sums `count` partials of `nsum` interleaved arrays in fixed order
 hipError_t launch_finalize_prep(const double* part, int blocks, double* scalars, int sr,
                                 hipStream_t s);
 hipError_t launch_init_x(const float* x0, float* x, const double* scalars, int64_t count,
                          int* flags, hipStream_t s);
-hipError_t launch_sum_planes(const float* planes, int G, int64_t Nl, float* out, hipStream_t s);
-hipError_t launch_update(const float* planes, int G, int64_t Nl, const float* B, float* x,
-                         double* part, int blocks, hipStream_t s);
+// out = sum_g planes[g] (times w[g] when w != nullptr: the per-frame weights of
+// the typeset form of Eq. (2), G = n), in order g = 0..G-1
+hipError_t launch_sum_planes(const float* planes, const float* w, int G, int64_t Nl, float* out,
+                             hipStream_t s);
+hipError_t launch_update(const float* planes, const float* w, int G, int64_t Nl, const float* B,
+                         float* x, double* part, int blocks, hipStream_t s);
 // iteration bookkeeping: writes trace entries at counters[0] and advances it
 hipError_t launch_finalize_iter(const double* part_ll, int n_ll, const double* part_rc,
                                 int n_rc, const double* scalars, double* trace_ll,

@@ -6,6 +6,7 @@
 #include <math.h>
 
 #include "em.h"
+#include "em_device.h"
 
 namespace em {
 
@@ -213,13 +214,6 @@ __device__ inline int stage_tile(const float* __restrict__ src, int H, int W, in
     }
     return ex;
   }
-}
-
-__device__ inline float mf_update_value(float xo, float Bv, float Dn) {
-  if (xo == 0.f) return 0.f;
-  if (Dn == 0.f) return xo;
-  const float q = fmaxf(Bv, 0.f) / Dn;
-  return xo * q;
 }
 
 // Output position of accumulator element (b, q, v) of a wave whose block
@@ -446,7 +440,7 @@ __device__ inline void adjoint_epilogue(const f32x4 (&acc)[BR][BC], const BlockP
       for (int v = 0; v < 4; ++v) {
         const int k = P.row(b, v), l = P.col(q);
         if (k < H && l < W) {
-          const float xn = mf_update_value(xo[b][q][v], bv[b][q][v], acc[b][q][v]);
+          const float xn = em_update_value(xo[b][q][v], bv[b][q][v], acc[b][q][v]);
           x[k * W + l] = xn;
           const double d = (double)xn - (double)xo[b][q][v];
           dsq += d * d;

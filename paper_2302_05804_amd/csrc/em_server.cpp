@@ -59,6 +59,8 @@ struct Job {
   int err = EM_OK;
   std::string errmsg;
   bool cancel = false;
+  int waiters = 0;                // em_wait calls blocked on this job (em_release
+                                  // keeps the job while any is)
   size_t off = 0, bytes = 0;      // arena range
   em_ctx* ctx = nullptr;
   double t_submit = 0, t_admit = 0, t_done = 0;
@@ -178,6 +180,10 @@ struct em_server {
   hipGraphExec_t graph{};
   bool graph_ok = false;
   int64_t rounds = 0, graphs_built = 0;
+  // worker seconds per phase: admission (input upload, em_init), round
+  // rebuilds (descriptors, graph capture), rounds (launch to completion),
+  // finishing (final loglik, result copy)
+  double sec_admit = 0, sec_build = 0, sec_rounds = 0, sec_finish = 0;
   std::string worker_error;
 };
 
@@ -467,7 +473,9 @@ void worker_main(em_server* S) {
       j->state = J_ACTIVE;
       j->t_admit = now_s();
       lk.unlock();
+      const double ta = now_s();
       const int rc = admit(S, j);
+      S->sec_admit += now_s() - ta;
       lk.lock();
       if (rc != EM_OK) {
         j->err = rc;
@@ -499,7 +507,9 @@ void worker_main(em_server* S) {
     for (Job* j : S->active) k = std::min(k, j->n_iter - j->done_iter);
     lk.unlock();
     int rc = EM_OK;
+    const double tb = now_s();
     if (S->dirty) rc = build_round(S);
+    const double tr = now_s();
     if (rc == EM_OK) {
       for (int i = 0; i < k && rc == EM_OK; ++i)
         if (hipGraphLaunch(S->graph, S->stream) != hipSuccess) rc = fail(EM_EDEVICE, "round launch");
@@ -507,6 +517,8 @@ void worker_main(em_server* S) {
         rc = fail(EM_EDEVICE, "round sync: %s", hipGetErrorString(hipGetLastError()));
     }
     lk.lock();
+    S->sec_build += tr - tb;
+    S->sec_rounds += now_s() - tr;
     if (rc != EM_OK) {
       // a device failure ends every active job
       S->worker_error = em_last_error();
@@ -531,8 +543,10 @@ void worker_main(em_server* S) {
         continue;
       }
       lk.unlock();
+      const double tf = now_s();
       const int frc = finish(S, j);
       lk.lock();
+      S->sec_finish += now_s() - tf;
       j->err = frc;
       if (frc) j->errmsg = em_last_error();
       release_job_device(S, j);
@@ -680,10 +694,15 @@ int em_wait(em_server* S, em_job_id id, float* x_host_out, double* loglik_out) {
   auto it = S->jobs.find(id);
   if (it == S->jobs.end()) return fail(EM_EINVAL, "unknown job %lld", (long long)id);
   Job* j = it->second;
+  // the waiter count keeps em_release from freeing the job while this thread
+  // sleeps (the predicate reads it after every wake-up)
+  ++j->waiters;
   S->cv_done.wait(lk, [&] {
     return j->state == J_DONE || j->state == J_FAILED || j->state == J_CANCELED;
   });
-  return job_result(j, x_host_out, loglik_out);
+  const int rc = job_result(j, x_host_out, loglik_out);
+  --j->waiters;
+  return rc;
 }
 
 int em_cancel(em_server* S, em_job_id id) {
@@ -712,6 +731,8 @@ int em_release(em_server* S, em_job_id id) {
   Job* j = it->second;
   if (j->state == J_QUEUED || j->state == J_ACTIVE)
     return fail(EM_EAGAIN, "job %lld is still pending", (long long)id);
+  if (j->waiters > 0)
+    return fail(EM_EAGAIN, "job %lld: another thread is still in em_wait", (long long)id);
   S->jobs.erase(it);
   delete j;
   return EM_OK;
@@ -746,6 +767,16 @@ int em_server_stats(em_server* S, int64_t* stats) {
   stats[5] = S->rounds;
   stats[6] = S->graphs_built;
   stats[7] = (int64_t)(S->budget - S->arena.free_bytes());
+  return EM_OK;
+}
+
+int em_server_phase_seconds(em_server* S, double* sec) {
+  if (!S || !sec) return fail(EM_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  sec[0] = S->sec_admit;
+  sec[1] = S->sec_build;
+  sec[2] = S->sec_rounds;
+  sec[3] = S->sec_finish;
   return EM_OK;
 }
 

@@ -98,6 +98,7 @@ _sig = {
                                     ctypes.POINTER(ctypes.c_double),
                                     ctypes.POINTER(ctypes.c_double)]),
     "em_server_stats": (ctypes.c_int, [_P, _P]),
+    "em_server_phase_seconds": (ctypes.c_int, [_P, _P]),
     "em_variant_count": (ctypes.c_int, []),
     "em_check_plan": (ctypes.c_int, [ctypes.POINTER(Problem)]),
     "em_set_variants": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -432,6 +433,13 @@ class Server:
         keys = ["queued", "active", "done", "failed", "cancelled", "rounds", "graphs",
                 "arena_bytes_in_use"]
         return dict(zip(keys, st.tolist()))
+
+    def phase_seconds(self):
+        """Worker seconds per phase: admission, round rebuilds, rounds, finishing."""
+        sec = np.zeros(4, np.float64)
+        _check(_lib.em_server_phase_seconds(self._h, sec.ctypes.data_as(_P)),
+               "em_server_phase_seconds")
+        return dict(zip(["admit", "rebuild", "rounds", "finish"], sec.tolist()))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -66,3 +66,7 @@ def test_launch_plans_match_their_grids():
     for (h, w), n, k, sr, prec in itertools.product(sizes, (1, 3, 33), (1, 15, 43), (1, 2),
                                                      (em.FP32, em.BF16_SPLIT, em.FP16_SPLIT, em.BF16)):
         em.check_plan(em.Problem.make(n, h, w, k, sr=sr, precision=prec))
+    # the typeset weighting (sr = 1): one frame per adjoint group, never fused
+    for (h, w), n, prec in itertools.product(sizes[:7], (1, 3, 33),
+                                             (em.FP32, em.BF16_SPLIT, em.FP16_SPLIT)):
+        em.check_plan(em.Problem.make(n, h, w, 43, precision=prec, weight_mode=em.W_LITERAL))

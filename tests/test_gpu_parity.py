@@ -191,8 +191,10 @@ def test_invalid_inputs_are_rejected():
     with pytest.raises(em.EMError) as ei:
         init(ws=torch.empty(1024, dtype=torch.uint8, device="cuda"))
     assert ei.value.code == em.ENOMEM
+    # the typeset weighting of Eq. (2) is defined for sr = 1 only
     with pytest.raises(em.EMError) as ei:
-        init(prob=em.Problem.make(2, 32, 32, 15, weight_mode=em.W_LITERAL))
+        em.Context(em.Problem.make(2, 16, 16, 15, sr=2, weight_mode=em.W_LITERAL),
+                   to_dev(p.y[:, :16, :16]), to_dev(p.v[:, :16, :16]), to_dev(p.psf), x)
     assert ei.value.code == em.ENOTSUP
     # masked pixels with NaN exposures are fine and never read as numbers
     y2 = p.y.copy()
