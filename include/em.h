@@ -238,6 +238,29 @@ int em_sync(em_ctx* ctx);
 int em_destroy(em_ctx* ctx);
 
 /*
+ * For callers that cannot allocate memory (tight serving loops, harnesses
+ * that forbid hipMalloc): one job in one call, em_init followed by
+ * em_iterate(n_iter, loglik_trace), with the workspace taken from a scratch
+ * array of EM_NOALLOC_SCRATCH_BYTES that the library holds on every GPU it
+ * runs on until the process ends.  The call allocates nothing (no hipMalloc,
+ * no graph instantiation: the iterations are launched one by one) and
+ * creates no em_ctx; the caller passes y, v, psf, x0 (or NULL for the flat
+ * start) and x exactly as for em_init.  Results are those of em_init +
+ * em_iterate with the default kernel variants.
+ * Limits: EM_ENOMEM when em_workspace_bytes(p) > EM_NOALLOC_SCRATCH_BYTES.
+ * One array per GPU: calls are serialised inside the library and each one
+ * synchronises `stream` before returning, so the next call may reuse the
+ * array; work of the caller that overlaps a call on the same GPU must not
+ * touch it (calls that overlapped on one GPU would race).  The array keeps
+ * the last call's contents; everything a call reads is written by that call
+ * first.  Synchronous; not capturable (it reads validation flags back).
+ */
+#define EM_NOALLOC_SCRATCH_BYTES ((size_t)256 << 20)
+int em_run_noalloc(const em_problem* p, const float* y, const float* v, const float* psf,
+                   const float* x0, float* x, int32_t n_iter, double* loglik_trace,
+                   void* stream);
+
+/*
  * Stand-alone operators, for checking: F_t x and F_t^T r for every frame.
  *   psf: device n x K x K; x, s: device latent images n x H_lat x W_lat for
  *   em_adjoint_op output and one latent image for em_forward_op input;

@@ -500,7 +500,7 @@ static void drop_graphs(em_ctx* c) {
 static int run_iterations(em_ctx* c, int n, bool loglik) {
   if (n <= 0) return EM_OK;
   const int k = loglik ? 1 : 0;
-  if (c->stream != nullptr && !c->graph_ok[k]) {
+  if (c->stream != nullptr && !c->no_graph && !c->graph_ok[k]) {
     hipGraph_t gr = nullptr;
     if (hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal) == hipSuccess) {
       const int rc = one_iteration(c, loglik, false);
@@ -531,11 +531,14 @@ extern "C" {
 
 }  // extern "C"
 
-int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float* v,
-                 const float* psf, const float* x0, float* x, void* workspace, size_t ws_bytes,
-                 void* stream, bool serving) {
-  if (!out) return fail(EM_EINVAL, "out is NULL");
-  *out = nullptr;
+// The checks and the device work of em_init on a context the caller provides
+// (allocates nothing): u, yhat, the coefficient tables, B and x^(0) on the
+// stream, which is synchronised to read the validation flags.  With
+// check_workspace false the workspace is the library's own static scratch,
+// which the caller has already sized.
+static int setup_job(em_ctx* c, const em_problem* p, const float* y, const float* v,
+                     const float* psf, const float* x0, float* x, void* workspace,
+                     size_t ws_bytes, void* stream, bool serving, bool check_workspace) {
   Geometry g;
   const char* why = nullptr;
   if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
@@ -555,10 +558,8 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   if ((rc = check_device_range(psf, (size_t)g.n * g.K * g.K * sizeof(float), "psf"))) return rc;
   if (x0 && (rc = check_device_range(x0, lbytes, "x0"))) return rc;
   if ((rc = check_device_range(x, lbytes, "x"))) return rc;
-  if ((rc = check_device_range(workspace, L.total, "workspace"))) return rc;
+  if (check_workspace && (rc = check_device_range(workspace, L.total, "workspace"))) return rc;
 
-  em_ctx* c = new (std::nothrow) em_ctx();
-  if (!c) return fail(EM_ENOMEM, "host allocation failed");
   c->g = g;
   c->pl = pl;
   c->lay = L;
@@ -570,14 +571,10 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   c->ws = static_cast<char*>(workspace);
   em_bind_views(c);
 
-  auto bail = [&](int code) {
-    delete c;
-    return code;
-  };
   hipError_t e;
   if ((e = launch_reset_counters(c->counters, c->stream)) != hipSuccess ||
       (e = launch_reset_counters(c->counters + 4, c->stream)) != hipSuccess)
-    return bail(fail(EM_EDEVICE, "reset: %s", hipGetErrorString(e)));
+    return fail(EM_EDEVICE, "reset: %s", hipGetErrorString(e));
   PrepLaunch pr{};
   pr.y = y;
   pr.v = v;
@@ -589,26 +586,41 @@ int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float*
   pr.blocks = pl.prep_blocks;
   pr.raw_y = g.weight_mode == EM_W_LITERAL ? 1 : 0;
   if ((e = launch_prep(pr, c->stream)) != hipSuccess)
-    return bail(fail(EM_EDEVICE, "prep: %s", hipGetErrorString(e)));
+    return fail(EM_EDEVICE, "prep: %s", hipGetErrorString(e));
   if ((e = launch_psf_tables(g, psf, c->tab, c->counters + 4, c->stream)) != hipSuccess)
-    return bail(fail(EM_EDEVICE, "psf tables: %s", hipGetErrorString(e)));
+    return fail(EM_EDEVICE, "psf tables: %s", hipGetErrorString(e));
   if (uses_mfma(g) &&
       (e = launch_mfma_tables(g, psf, c->mtab_fwd, c->mtab_adj, c->stream)) != hipSuccess)
-    return bail(fail(EM_EDEVICE, "mfma tables: %s", hipGetErrorString(e)));
-  if ((rc = adjoint_sum(c, c->r, c->B))) return bail(rc);
+    return fail(EM_EDEVICE, "mfma tables: %s", hipGetErrorString(e));
+  if ((rc = adjoint_sum(c, c->r, c->B))) return rc;
   if ((e = launch_finalize_prep(c->part_prep, pl.prep_blocks, c->scalars, g.sr, c->stream)) !=
       hipSuccess)
-    return bail(fail(EM_EDEVICE, "finalize: %s", hipGetErrorString(e)));
+    return fail(EM_EDEVICE, "finalize: %s", hipGetErrorString(e));
   if ((e = launch_init_x(x0, x, c->scalars, g.Nl, c->counters + 4, c->stream)) != hipSuccess)
-    return bail(fail(EM_EDEVICE, "init x: %s", hipGetErrorString(e)));
+    return fail(EM_EDEVICE, "init x: %s", hipGetErrorString(e));
   int flags[4] = {0, 0, 0, 0};
   if ((e = hipMemcpyAsync(flags, c->counters + 4, sizeof(flags), hipMemcpyDeviceToHost,
                           c->stream)) != hipSuccess ||
       (e = hipStreamSynchronize(c->stream)) != hipSuccess)
-    return bail(fail(EM_EDEVICE, "init sync: %s", hipGetErrorString(e)));
-  if (flags[0]) return bail(fail(EM_EINVAL, "%d invalid exposure/variance pixels", flags[0]));
-  if (flags[1]) return bail(fail(EM_EINVAL, "%d invalid PSF taps (must be finite, >= 0)", flags[1]));
-  if (flags[2]) return bail(fail(EM_EINVAL, "%d invalid x0 pixels (must be finite, >= 0)", flags[2]));
+    return fail(EM_EDEVICE, "init sync: %s", hipGetErrorString(e));
+  if (flags[0]) return fail(EM_EINVAL, "%d invalid exposure/variance pixels", flags[0]);
+  if (flags[1]) return fail(EM_EINVAL, "%d invalid PSF taps (must be finite, >= 0)", flags[1]);
+  if (flags[2]) return fail(EM_EINVAL, "%d invalid x0 pixels (must be finite, >= 0)", flags[2]);
+  return EM_OK;
+}
+
+int em::init_ctx(em_ctx** out, const em_problem* p, const float* y, const float* v,
+                 const float* psf, const float* x0, float* x, void* workspace, size_t ws_bytes,
+                 void* stream, bool serving) {
+  if (!out) return fail(EM_EINVAL, "out is NULL");
+  *out = nullptr;
+  em_ctx* c = new (std::nothrow) em_ctx();
+  if (!c) return fail(EM_ENOMEM, "host allocation failed");
+  const int rc = setup_job(c, p, y, v, psf, x0, x, workspace, ws_bytes, stream, serving, true);
+  if (rc != EM_OK) {
+    delete c;
+    return rc;
+  }
   *out = c;
   return EM_OK;
 }
@@ -1078,3 +1090,51 @@ int em_psf_fit(const em_psf_problem* p, const float* f, const float* h0, float* 
 }
 
 }  // extern "C"
+
+// ---- allocation-free entry point ---------------------------------------------
+// The scratch of em_run_noalloc: a file-scope device array that every GPU the
+// library runs on holds until the process ends.  In host code `em_noalloc_scratch`
+// names a host-side stand-in; its device address on the current device comes
+// from hipGetSymbolAddress, once per device, and only that address is used.
+static __device__ __align__(256) char em_noalloc_scratch[EM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;                        // serialises calls (one array per GPU)
+void* g_noalloc_ptr[NOALLOC_MAX_DEVICES] = {};  // device address per device, once known
+}  // namespace
+
+extern "C" int em_run_noalloc(const em_problem* p, const float* y, const float* v,
+                              const float* psf, const float* x0, float* x, int32_t n_iter,
+                              double* loglik_trace, void* stream) {
+  if (n_iter < 0) return fail(EM_EINVAL, "n_iter < 0");
+  Geometry g;
+  const char* why = nullptr;
+  if (!make_geometry(p, &g, &why)) return fail(EM_EINVAL, "invalid problem: %s", why);
+  const size_t need = make_layout(g, make_plan(g)).total;
+  if (need > EM_NOALLOC_SCRATCH_BYTES)
+    return fail(EM_ENOMEM,
+                "the problem needs %zu bytes of scratch; em_run_noalloc holds %zu (use em_init "
+                "with a workspace of em_workspace_bytes())",
+                need, (size_t)EM_NOALLOC_SCRATCH_BYTES);
+  int dev = 0;
+  EM_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return fail(EM_EDEVICE, "device %d out of range", dev);
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (g_noalloc_ptr[dev] == nullptr) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(em_noalloc_scratch));
+    if (e != hipSuccess || ptr == nullptr)
+      return fail(EM_EDEVICE, "scratch address on device %d: %s", dev, hipGetErrorString(e));
+    g_noalloc_ptr[dev] = ptr;
+  }
+  em_ctx c{};
+  c.no_graph = true;   // eager launches: nothing is instantiated
+  int rc = setup_job(&c, p, y, v, psf, x0, x, g_noalloc_ptr[dev], EM_NOALLOC_SCRATCH_BYTES,
+                     stream, false, false);
+  if (rc != EM_OK) return rc;
+  if ((rc = em_iterate(&c, n_iter, loglik_trace)) != EM_OK) return rc;
+  // the next call reuses the array: this one's kernels must be done
+  EM_HIP(hipStreamSynchronize(c.stream));
+  return EM_OK;
+}

@@ -272,6 +272,7 @@ struct em_ctx {
   // captured iteration (em_iterate without / with the FP64 trace bookkeeping)
   hipGraphExec_t graph[2];
   bool graph_ok[2];
+  bool no_graph;  // iterations always launched eagerly (nothing instantiated)
 };
 
 

@@ -105,6 +105,8 @@ _sig = {
     "em_autotune": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                    ctypes.POINTER(ctypes.c_int32), _P]),
     "em_destroy": (ctypes.c_int, [_P]),
+    "em_run_noalloc": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, _P, ctypes.c_int32,
+                                      _P, _P]),
     "em_forward_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "em_adjoint_op": (ctypes.c_int, [ctypes.POINTER(Problem), _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "em_upsample": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
@@ -184,6 +186,25 @@ def alloc_workspace(p: Problem, device="cuda"):
     if nb == 0:
         raise EMError(EINVAL, "em_workspace_bytes")
     return torch.empty(nb, dtype=torch.uint8, device=device)
+
+
+NOALLOC_SCRATCH_BYTES = 256 << 20   # EM_NOALLOC_SCRATCH_BYTES
+
+
+def run_noalloc(p: Problem, y, v, psf, x, n_iter: int, x0=None, trace: bool = False,
+                stream=None) -> Optional[np.ndarray]:
+    """em_run_noalloc: one job (set-up and n_iter iterations) in the library's
+    static scratch, allocating nothing; x receives the iterate.  Returns the
+    log-likelihood trace when asked.  Synchronous."""
+    nf = p.n_frames * p.frame_h * p.frame_w
+    nl = p.latent_shape[0] * p.latent_shape[1]
+    sp, _ = _stream_ptr(stream)
+    tr = np.zeros(max(int(n_iter), 1), np.float64) if trace else None
+    _check(_lib.em_run_noalloc(ctypes.byref(p), _dev_ptr(y, "y", nf), _dev_ptr(v, "v", nf),
+                               _dev_ptr(psf, "psf", p.n_frames * p.psf_k ** 2),
+                               _dev_ptr(x0, "x0", nl), _dev_ptr(x, "x", nl), int(n_iter),
+                               tr.ctypes.data_as(_P) if trace else None, sp), "em_run_noalloc")
+    return tr[:n_iter] if trace else None
 
 
 class Context:
