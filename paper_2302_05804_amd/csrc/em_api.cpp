@@ -191,6 +191,9 @@ Layout make_layout(const Geometry& g, const Plan& pl) {
   L.trace_ll = take(TRACE_CAP * sizeof(double));
   L.trace_rc = take(TRACE_CAP * sizeof(double));
   L.counters = take(16 * sizeof(int));
+  const bool r16 = uses_r16(g);
+  L.r16 = take(r16 ? (size_t)g.n * r16_rows(g) * r16_pitch(g) * sizeof(uint16_t) : 0);
+  L.r16stat = take(r16 ? (size_t)(3 * g.n + R16_XBLOCKS) * sizeof(float) : 0);
   L.total = off;
   return L;
 }
@@ -244,6 +247,11 @@ void em_bind_views(em_ctx* c) {
   c->trace_ll = reinterpret_cast<double*>(w + L.trace_ll);
   c->trace_rc = reinterpret_cast<double*>(w + L.trace_rc);
   c->counters = reinterpret_cast<int*>(w + L.counters);
+  c->r16 = reinterpret_cast<unsigned short*>(w + L.r16);
+  c->r16_umax = reinterpret_cast<float*>(w + L.r16stat);
+  c->r16_fsum = c->r16_umax + c->g.n;
+  c->r16_e = reinterpret_cast<int*>(c->r16_fsum + c->g.n);
+  c->r16_xpart = reinterpret_cast<float*>(c->r16_e + c->g.n);
 }
 
 extern "C" {
@@ -374,19 +382,41 @@ void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc) {
   a->plane = c->planes;
 }
 
+// The iteration of an FP16 split sr = 1 job with Gaussian weights moves r
+// through binary16 planes: the forward writes them, the adjoint copies its
+// windows from them (dir 0: forward descriptor; dir 1: adjoint descriptor).
+void apply_r16(const em_ctx* c, MfmaLaunch* m, int dir) {
+  m->r16 = c->r16;
+  m->e16 = c->r16_e;
+  m->p16 = r16_pitch(c->g);
+  m->s16 = (int64_t)r16_rows(c->g) * r16_pitch(c->g);
+  if (dir == 0) m->out = nullptr;
+  else m->in = nullptr;
+}
+
 }  // namespace em
+
+static int r16_scale(em_ctx* c) {
+  EM_HIP(launch_r16_scale(c->g, c->x, c->r16_xpart, c->r16_umax, c->r16_fsum, c->r16_e,
+                          c->stream));
+  return EM_OK;
+}
 
 // Forward pass at the current iterate: r = u F x (if write_r) and loglik
 // partials.  Under the typeset weighting r is the raw model F x (the weights act
 // after the adjoint) and the loglik partials come from a separate pass over r,
 // u and y.  *n_ll: the number of loglik partials written (may be NULL).
-static int forward_pass(em_ctx* c, bool write_r, bool loglik, int* n_ll = nullptr) {
+// With r16 (the iteration of an FP16 split job, uses_r16) r goes to the
+// binary16 planes, whose scales r16_scale has set.
+static int forward_pass(em_ctx* c, bool write_r, bool loglik, int* n_ll = nullptr,
+                        bool r16 = false) {
   const bool raw = write_r && c->g.weight_mode == EM_W_LITERAL;
   if (n_ll) *n_ll = c->pl.fwd_tiles * c->pl.fwd_groups;
   if (uses_mfma(c->g)) {
     MfmaLaunch m;
     fill_forward_mfma(c, &m, write_r, loglik && !raw);
     if (raw) m.u = nullptr;
+    if (r16 && write_r) apply_r16(c, &m, 0);
     EM_HIP(launch_mfma(c->g, 0, c->pl.fwd_variant, c->pl.fwd_tiles, c->pl.fwd_groups, m,
                        c->stream));
   } else {
@@ -438,6 +468,7 @@ static int adjoint_launch(em_ctx* c, double* part_rc) {
   if (uses_mfma(c->g)) {
     MfmaLaunch m;
     fill_adjoint_mfma(c, &m, part_rc);
+    if (uses_r16(c->g)) apply_r16(c, &m, 1);
     EM_HIP(launch_mfma(c->g, 1, c->pl.adj_variant, c->pl.adj_tiles, c->pl.adj_groups, m,
                        c->stream));
   } else {
@@ -473,7 +504,10 @@ static int adjoint_update(em_ctx* c, double* part_rc, int* n_rc) {
 static int one_iteration(em_ctx* c, bool loglik, bool relchange) {
   const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
   int n_ll = c->pl.fwd_tiles * c->pl.fwd_groups;
-  int rc = robust ? robust_forward(c, loglik) : forward_pass(c, true, loglik, &n_ll);
+  const bool r16 = uses_r16(c->g);
+  int rc = r16 ? r16_scale(c) : EM_OK;
+  if (rc) return rc;
+  rc = robust ? robust_forward(c, loglik) : forward_pass(c, true, loglik, &n_ll, r16);
   if (rc) return rc;
   if (robust && (rc = adjoint_sum(c, c->ry, c->B))) return rc;
   int n_rc = 0;
@@ -592,6 +626,9 @@ static int setup_job(em_ctx* c, const em_problem* p, const float* y, const float
   if (uses_mfma(g) &&
       (e = launch_mfma_tables(g, psf, c->mtab_fwd, c->mtab_adj, c->stream)) != hipSuccess)
     return fail(EM_EDEVICE, "mfma tables: %s", hipGetErrorString(e));
+  if (uses_r16(g) && (e = launch_r16_setup(g, c->u, psf, c->r16, c->r16_umax, c->r16_fsum,
+                                           c->stream)) != hipSuccess)
+    return fail(EM_EDEVICE, "r16 planes: %s", hipGetErrorString(e));
   if ((rc = adjoint_sum(c, c->r, c->B))) return rc;
   if ((e = launch_finalize_prep(c->part_prep, pl.prep_blocks, c->scalars, g.sr, c->stream)) !=
       hipSuccess)
@@ -725,15 +762,18 @@ int em_terms(em_ctx* c, float* B_out, float* Dn_out) {
 int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
   if (!c || !phase_ms) return fail(EM_EINVAL, "NULL argument");
   if (n_iter < 1) return fail(EM_EINVAL, "n_iter must be >= 1");
-  hipEvent_t ev[5];
-  for (int i = 0; i < 5; ++i) EM_HIP(hipEventCreate(&ev[i]));
+  hipEvent_t ev[6];
+  for (int i = 0; i < 6; ++i) EM_HIP(hipEventCreate(&ev[i]));
+  const bool r16 = uses_r16(c->g);
   double acc[4] = {0, 0, 0, 0};
   int rc = EM_OK;
   const bool fused = c->pl.adj_fused != 0;
   const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
   for (int k = 0; k < n_iter && rc == EM_OK; ++k) {
     EM_HIP(hipEventRecord(ev[0], c->stream));
-    if ((rc = robust ? robust_forward(c, false) : forward_pass(c, true, false))) break;
+    if (r16 && (rc = r16_scale(c))) break;
+    EM_HIP(hipEventRecord(ev[5], c->stream));
+    if ((rc = robust ? robust_forward(c, false) : forward_pass(c, true, false, nullptr, r16))) break;
     EM_HIP(hipEventRecord(ev[4], c->stream));
     if (robust && (rc = adjoint_sum(c, c->ry, c->B))) break;
     EM_HIP(hipEventRecord(ev[1], c->stream));
@@ -743,7 +783,7 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
     EM_HIP(hipEventRecord(ev[3], c->stream));
     EM_HIP(hipEventSynchronize(ev[3]));
     float ms;
-    EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[4]));
+    EM_HIP(hipEventElapsedTime(&ms, ev[5], ev[4]));
     acc[0] += ms;
     EM_HIP(hipEventElapsedTime(&ms, ev[1], ev[2]));
     acc[1] += ms;
@@ -752,7 +792,7 @@ int em_profile(em_ctx* c, int32_t n_iter, double* phase_ms) {
     EM_HIP(hipEventElapsedTime(&ms, ev[0], ev[3]));
     acc[3] += ms;
   }
-  for (int i = 0; i < 5; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < 6; ++i) (void)hipEventDestroy(ev[i]);
   if (rc) return rc;
   for (int i = 0; i < 4; ++i) phase_ms[i] = acc[i] / n_iter;
   return EM_OK;
@@ -781,6 +821,24 @@ int em_check_plan(const em_problem* p) {
         fill_adjoint_mfma(&c, &m, nullptr);
         if (!mfma_desc_ok(g, 1, pl.adj_tiles, pl.adj_groups, m))
           return fail(EM_EINVAL, "%s: adjoint descriptor does not match its grid", what);
+        if (uses_r16(g) && !serving) {
+          // the iteration's binary16 r planes
+          MfmaLaunch f16;
+          fill_forward_mfma(&c, &f16, true, true);
+          apply_r16(&c, &f16, 0);
+          if (!mfma_desc_ok(g, 0, pl.fwd_tiles, pl.fwd_groups, f16))
+            return fail(EM_EINVAL, "%s: r16 forward descriptor does not match", what);
+          MfmaLaunch a16 = m;
+          apply_r16(&c, &a16, 1);
+          if (!mfma_desc_ok(g, 1, pl.adj_tiles, pl.adj_groups, a16))
+            return fail(EM_EINVAL, "%s: r16 adjoint descriptor does not match", what);
+          // every window of every tile inside its plane
+          const int64_t last_row = (int64_t)((g.Hl + 127) / 128 - 1) * 128 + 127 + g.KT - 1;
+          const int64_t last_col = (int64_t)((g.Wl + 127) / 128 - 1) * 128 + 175;
+          if (last_row >= r16_rows(g) || last_col >= r16_pitch(g) || r16_pitch(g) % 8 != 0 ||
+              c.lay.r16stat - c.lay.r16 < (size_t)g.n * r16_rows(g) * r16_pitch(g) * 2)
+            return fail(EM_EINVAL, "%s: r16 planes smaller than the windows", what);
+        }
         m.fpg = 1;   // stand-alone operator: one frame per group
         if (!mfma_desc_ok(g, 1, pl.adj_tiles, g.n, m))
           return fail(EM_EINVAL, "%s: per-frame adjoint descriptor does not match", what);
@@ -849,11 +907,16 @@ int em_autotune(em_ctx* c, int32_t n_rep, int32_t* fwd_variant, int32_t* adj_var
           m.nu = c->g.nu;
           m.lcst = student_t_lcst((double)c->g.nu);
         }
+        if (uses_r16(c->g)) {
+          apply_r16(c, &m, 0);
+          if ((rc = r16_scale(c))) break;
+        }
         tiles = c->pl.fwd_tiles;
         groups = c->pl.fwd_groups;
       } else {
         // the adjoint writes partial planes (never the iterate)
         fill_adjoint_mfma(c, &m, nullptr);
+        if (uses_r16(c->g)) apply_r16(c, &m, 1);
         m.fused = 0;
         m.plane = c->pl.adj_groups > 1 ? c->planes : c->tune;
         tiles = c->pl.adj_tiles;

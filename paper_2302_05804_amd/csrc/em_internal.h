@@ -74,7 +74,7 @@ struct Plan {
 // Workspace layout (byte offsets from the workspace base, 256-aligned).
 struct Layout {
   size_t u, r, ry, B, planes, tab, mtab_fwd, mtab_adj, tune, part_ll, part_rc, part_prep,
-      scalars, trace_ll, trace_rc, counters, total;
+      scalars, trace_ll, trace_rc, counters, r16, r16stat, total;
 };
 
 // true when the convolutions of geometry g run on the matrix cores
@@ -133,7 +133,33 @@ struct MfmaLaunch {
   float* out_y;        // forward under Student-t noise (as FwdLaunch)
   float nu;
   double lcst;
+  // binary16 r planes (FP16 split form, sr = 1, Gaussian weights; nullptr =>
+  // FP32 r in out / in): the forward writes 2^e16[t] u F x there and the
+  // adjoint copies its windows straight into LDS.  Frame t's plane starts at
+  // r16 + t * s16 halves; frame pixel (k, l) sits at row k + c, column l + c
+  // of rows of p16 halves, c = (KT - 1) / 2; the rest of the plane is zero.
+  unsigned short* r16;
+  const int* e16;
+  int p16;
+  int64_t s16;
 };
+// binary16 r plane geometry: every adjoint window of 128 x 128 outputs (rows
+// k0 - c .. k0 + 127 + c, columns l0 - c .. l0 + 175 - c) lies inside the plane
+// and starts on a 16-byte boundary.
+int r16_pitch(const Geometry& g);   // 128 * ceil(W / 128) + 48
+int r16_rows(const Geometry& g);    // 128 * ceil(H / 128) + KT - 1
+// the FP16 split sr = 1 iteration with Gaussian weights runs on binary16 r planes
+inline bool uses_r16(const Geometry& g) {
+  return g.precision == EM_FP16_SPLIT && g.sr == 1 && g.weight_mode == EM_W_ADJOINT;
+}
+// set-up of the binary16 r planes: zero planes, per-frame max u and sum of the PSF
+hipError_t launch_r16_setup(const Geometry& g, const float* u, const float* psf,
+                            unsigned short* r16, float* umax, float* fsum, hipStream_t s);
+// per iteration, before the forward: e16[t] from the bound 2 max u_t sum f_t max x
+// (max x from `nb` block partials in xpart)
+constexpr int R16_XBLOCKS = 256;
+hipError_t launch_r16_scale(const Geometry& g, const float* x, float* xpart, const float* umax,
+                            const float* fsum, int* e16, hipStream_t s);
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s);
 int mfma_table_rows(int KT);
@@ -269,6 +295,13 @@ struct em_ctx {
   double* trace_ll;
   double* trace_rc;
   int* counters;  // [0] iteration counter, [4..7] validation flags
+  // binary16 r planes (uses_r16): planes, then umax[n], fsum[n] (float),
+  // e16[n] (int), xpart[R16_XBLOCKS] (float)
+  unsigned short* r16;
+  float* r16_umax;
+  float* r16_fsum;
+  int* r16_e;
+  float* r16_xpart;
   // captured iteration (em_iterate without / with the FP64 trace bookkeeping)
   hipGraphExec_t graph[2];
   bool graph_ok[2];

@@ -33,6 +33,7 @@
 #include "em_internal.h"
 #include "em_mfma_common.h"
 
+#include <algorithm>
 #include <type_traits>
 
 namespace em {
@@ -249,8 +250,10 @@ __device__ inline void mfma_class_lds(int r, const unsigned short (*sh)[C::ROWS 
 
 // All classes of one frame with the Toeplitz fragments staged in LDS.  On entry
 // the fragments of class 0 are in buffer step & 1 (a barrier after their copy
-// has been passed).
-template <class C>
+// has been passed).  PEEL: class 0 outside the class loop, so that waits the
+// compiler places for loads still in flight from the previous frame's
+// epilogue land in class 0 only, not in every class of the loop.
+template <class C, bool PEEL = false>
 __device__ inline void mfma_frame_lds(const unsigned short (*sh)[C::ROWS * C::PITCH],
                                       const typename C::frag* __restrict__ tab_t,
                                       const typename C::frag* __restrict__ tab_next,
@@ -258,6 +261,10 @@ __device__ inline void mfma_frame_lds(const unsigned short (*sh)[C::ROWS * C::PI
                                       f32x4 (&acc)[C::BR][C::BC],
                                       const UPre& up = UPre{nullptr, nullptr, 0, 0, 0, 0}) {
   int r = 0;
+  if constexpr (PEEL) {
+    mfma_class_lds<C, C::MMAX>(0, sh, tab_t, tab_next, tl, step, row_base, col_base, acc, up);
+    r = 1;
+  }
 #pragma unroll 1
   for (; r < C::RFULL; ++r)
     mfma_class_lds<C, C::MMAX>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, acc, up);
@@ -278,9 +285,11 @@ __device__ inline const int* table_exponents(const MfmaLaunch& a) {
 }
 
 // Forward: r_t = u_t * (f_t * x) for the frames of this group, x tile staged once
-// (ROB: the Student-t epilogue, which also writes u w y).
-template <class C, bool ROB = false>
+// (ROB: the Student-t epilogue, which also writes u w y; R16: r written as
+// binary16 into the frames' r16 planes, scaled by 2^e16[t]).
+template <class C, bool ROB = false, bool R16 = false>
 __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const int group) {
+  static_assert(!R16 || (C::PREC == EM_FP16_SPLIT && !ROB), "r16 planes: FP16 split, Gaussian");
   constexpr int c = (C::KT - 1) / 2;
   __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[C::NW];
@@ -298,8 +307,8 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
   // u of the frame in LDS (LDS-staged fragments, plain epilogue, rows of whole 16-byte runs)
   constexpr bool UPF = C::PFT == 2 && !ROB && C::TW == 128;
   __shared__ __align__(16) std::conditional_t<UPF, float[C::TH * C::TW], float[4]> ubuf;
-  const bool use_ul = UPF && a.u != nullptr && a.part == nullptr && a.out != nullptr &&
-                      (a.W & 3) == 0 && a.W >= 4;
+  const bool use_ul = UPF && a.u != nullptr && a.part == nullptr &&
+                      (R16 ? a.r16 != nullptr : a.out != nullptr) && (a.W & 3) == 0 && a.W >= 4;
   int step = 0;
   if constexpr (C::PFT == 2) issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
   const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(a.in, a.H, a.W, k0 - c,
@@ -322,14 +331,25 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
     const typename C::frag* tab_t = tab + t * TSTRIDE;
     const UPre up{use_ul ? a.u + (int64_t)t * N : nullptr, &ubuf[0], k0, l0, a.H, a.W};
     if constexpr (C::PFT == 2)
-      mfma_frame_lds<C>(sh, tab_t, t + 1 < t1 ? tab_t + TSTRIDE : nullptr, tl, step, row_base,
-                        col_base, acc, up);
+      mfma_frame_lds<C, R16>(sh, tab_t, t + 1 < t1 ? tab_t + TSTRIDE : nullptr, tl, step,
+                             row_base, col_base, acc, up);
     else
       mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
     // exact removal of the image and PSF scales (scaled encodings)
     const int unscale = C::P::SCALED ? -(sx + table_exponents<C>(a)[t]) : 0;
     // epilogue: per-frame base pointers (wave-uniform) + 32-bit in-frame offsets
-    if constexpr (ROB) {
+    if constexpr (R16) {
+      const R16Out o{a.r16 + (int64_t)t * a.s16, a.p16, c, a.e16[t]};
+      const BlockPos P{k0 + row_base, l0 + col_base, 1};
+      if (UPF && use_ul)
+        forward_epilogue_ul16<C::BR, C::BC, C::TW>(acc, unscale, P, a.H, a.W, k0, l0, &ubuf[0], o);
+      else if (a.part != nullptr)
+        llp += forward_epilogue_w16<C::BR, C::BC, true>(acc, unscale, P, a.H, a.W,
+                                                        a.u + (int64_t)t * N, a.y + (int64_t)t * N, o);
+      else
+        (void)forward_epilogue_w16<C::BR, C::BC, false>(acc, unscale, P, a.H, a.W,
+                                                        a.u + (int64_t)t * N, nullptr, o);
+    } else if constexpr (ROB) {
       llp += forward_epilogue_t<C::BR, C::BC>(
           acc, unscale, BlockPos{k0 + row_base, l0 + col_base, 1}, a.H, a.W, a.u + (int64_t)t * N,
           a.y + (int64_t)t * N, a.out + (int64_t)t * N, a.out_y + (int64_t)t * N, a.nu, a.lcst,
@@ -433,6 +453,169 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
   }
 }
 
+// ---------------------------------------------------------------------------
+// Adjoint on binary16 r planes (FP16 split form): the forward has already
+// written r_t scaled by 2^e16[t] as binary16, zero outside the frame, in planes
+// laid out so that a tile's window (ROWS rows of COLS halves from plane row k0,
+// column l0) is ROWS runs of 352 bytes starting on 16-byte boundaries.  The
+// window is copied straight into LDS (global_load_lds_dwordx4, 1 KB per wave
+// instruction, no registers, no conversion): the next frame's window goes into
+// the second LDS buffer during the first classes of the current frame, one
+// copy per wave and class, and may stay in flight for one more class, since a
+// wave's loads complete in issue order and each class waits only until its
+// own newest copy is the one outstanding.
+// ---------------------------------------------------------------------------
+constexpr int WAIT_VM0 = 0x0070;   // s_waitcnt vmcnt(0) lgkmcnt(0)
+constexpr int WAIT_VM1 = 0x0071;   // s_waitcnt vmcnt(1) lgkmcnt(0)
+
+template <class C>
+struct Win16 {
+  static constexpr int HALVES = C::ROWS * C::PITCH;      // one staged window
+  static constexpr int BYTES = 2 * HALVES;
+  static constexpr int ROW_BYTES = 2 * C::PITCH;
+  static constexpr int NCH = (BYTES + 1023) / 1024;      // 1 KB copies per window
+  static constexpr int CCL = (NCH + C::NW - 1) / C::NW;  // classes that carry copies
+  static_assert(C::PITCH == C::COLS, "a window row is one contiguous run of its plane row");
+  static_assert(ROW_BYTES % 16 == 0, "16-byte pieces never straddle window rows");
+  // the last class of a frame carries no copy, so its wait completes the window
+  static_assert(CCL < C::RLAST, "the copies fit in the classes of one frame");
+};
+
+// Copy chunk `ch` (bytes [1024 ch, 1024 ch + 1024) of the window) of the window
+// at plane row k0, column l0 into LDS buffer dst; lanes past the window's end
+// copy nothing.
+template <class C>
+__device__ inline void copy_window_chunk(const unsigned short* __restrict__ plane, int p16, int k0,
+                                         int l0, int ch, unsigned short* dst) {
+  using Wn = Win16<C>;
+  const int o = ch * 1024 + 16 * (threadIdx.x & 63);
+  if (o < Wn::BYTES) {
+    const int row = o / Wn::ROW_BYTES, cb = o - row * Wn::ROW_BYTES;
+    const char* src =
+        reinterpret_cast<const char*>(plane + (int64_t)(k0 + row) * p16 + l0) + cb;
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src),
+                                     (__attribute__((address_space(3))) void*)(
+                                         reinterpret_cast<char*>(dst) + ch * 1024),
+                                     16, 0, 0);
+  }
+}
+
+// One tap class of a frame whose window is in `sh`: read this class's Toeplitz
+// fragments, start the copy of the next class's fragments, then this wave's
+// copy of the next frame's window for this class (if any), issue the class's
+// products, wait until at most the window copy is outstanding, meet at a
+// barrier.  (Reading the fragments before the copies are issued keeps the
+// compiler from waiting for the copies before the reads.)
+template <class C, int NM>
+__device__ inline void mfma_class_lds16(int r, const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                        const typename C::frag* __restrict__ tab_t,
+                                        const typename C::frag* __restrict__ tab_next,
+                                        TBuf<C>& tl, int& step, int row_base, int col_base,
+                                        f32x4 (&acc)[C::BR][C::BC],
+                                        const unsigned short* __restrict__ next_plane, int p16,
+                                        int k0, int l0, unsigned short* next_buf) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cur = step & 1;
+  typename C::frag Tc[C::MMAX][2][C::NB];
+#pragma unroll
+  for (int m = 0; m < C::MMAX; ++m)
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = tl[cur][(m * 2 + h) * C::NB + q][lane];
+  if (r + 1 < C::RLAST) issue_T<C>(tab_t, r + 1, (void*)&tl[cur ^ 1][0][0]);
+  else if (tab_next != nullptr) issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+  const int ch = r * C::NW + w;
+  const bool copied = next_plane != nullptr && r < Win16<C>::CCL && ch < Win16<C>::NCH;
+  if (copied) copy_window_chunk<C>(next_plane, p16, k0, l0, ch, next_buf);
+  mfma_class<C, NM>(r, sh, Tc, row_base, col_base, acc);
+  if (copied) __builtin_amdgcn_s_waitcnt(WAIT_VM1);
+  else __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+  __builtin_amdgcn_s_barrier();
+  ++step;
+}
+
+template <class C>
+__device__ inline void mfma_adj16_body(const MfmaLaunch& a, const int tile, const int group) {
+  static_assert(C::PREC == EM_FP16_SPLIT && C::PFT == 2, "r16 planes feed the FP16 split form");
+  using Wn = Win16<C>;
+  __shared__ __align__(16) unsigned short rb[2][Wn::HALVES];
+  __shared__ double red[2 * C::NW];
+  __shared__ __align__(16) TBufDecl<C> tl;
+  const int w = threadIdx.x >> 6;
+  const int row_base = (w / C::WC) * 16 * C::BR, col_base = (w % C::WC) * 16 * C::BC;
+  const int tiles_x = (a.W + C::TW - 1) / C::TW;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int k0 = ty * C::TH, l0 = tx * C::TW;
+  const int64_t N = (int64_t)a.H * a.W;
+
+  f32x4 acc[C::BR][C::BC];
+#pragma unroll
+  for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+    for (int q = 0; q < C::BC; ++q) acc[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = group * a.fpg;
+  const int t1 = min(a.n, t0 + a.fpg);
+  const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
+  constexpr int64_t TSTRIDE = (int64_t)C::KTP * 4 * 64;
+  const int* e_tab = table_exponents<C>(a);
+  int step = 0;
+  // first frame: its window and its first class's fragments, all waves
+  issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
+  for (int ch = w; ch < Wn::NCH; ch += C::NW)
+    copy_window_chunk<C>(a.r16 + (int64_t)t0 * a.s16, a.p16, k0, l0, ch, &rb[0][0]);
+  __builtin_amdgcn_s_waitcnt(WAIT_VM0);
+  __builtin_amdgcn_s_barrier();
+  for (int t = t0; t < t1; ++t) {
+    const int buf = (t - t0) & 1;
+    const unsigned short(*sh)[C::ROWS * C::PITCH] =
+        reinterpret_cast<const unsigned short(*)[C::ROWS * C::PITCH]>(&rb[buf][0]);
+    const bool more = t + 1 < t1;
+    const unsigned short* next_plane = more ? a.r16 + (int64_t)(t + 1) * a.s16 : nullptr;
+    const typename C::frag* tab_t = tab + t * TSTRIDE;
+    const typename C::frag* tab_next = more ? tab_t + TSTRIDE : nullptr;
+    f32x4 accf[C::BR][C::BC];
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int q = 0; q < C::BC; ++q) accf[b][q] = f32x4{0.f, 0.f, 0.f, 0.f};
+    int r = 0;
+#pragma unroll 1
+    for (; r < C::RFULL; ++r)
+      mfma_class_lds16<C, C::MMAX>(r, sh, tab_t, tab_next, tl, step, row_base, col_base, accf,
+                                   next_plane, a.p16, k0, l0, &rb[buf ^ 1][0]);
+    if constexpr (C::MMAX > 1) {
+#pragma unroll 1
+      for (; r < C::RLAST; ++r)
+        mfma_class_lds16<C, C::MMAX - 1>(r, sh, tab_t, tab_next, tl, step, row_base, col_base,
+                                         accf, next_plane, a.p16, k0, l0, &rb[buf ^ 1][0]);
+    }
+    // each frame has its own scales: add it to the total unscaled (exact)
+    const int unscale = -(a.e16[t] + e_tab[t]);
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int q = 0; q < C::BC; ++q)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[b][q][v] += ldexpf(accf[b][q][v], unscale);
+  }
+
+  double dsq = 0.0, xsq = 0.0;
+  adjoint_epilogue<C::BR, C::BC>(acc, BlockPos{k0 + row_base, l0 + col_base, 1}, a.H, a.W,
+                                 a.fused, a.x, a.B,
+                                 a.fused ? nullptr : a.plane + (int64_t)group * N, dsq, xsq);
+  if (a.fused && a.part != nullptr) {
+    const double s1 = block_sum<C::NT>(dsq, red);
+    __syncthreads();
+    const double s2 = block_sum<C::NT>(xsq, red + C::NW);
+    if (threadIdx.x == 0) {
+      a.part[2 * tile] = s1;
+      a.part[2 * tile + 1] = s2;
+    }
+  }
+}
+
 // Entry points: one job (grid = tiles x frame groups) or a batch of jobs
 // (persistent workgroups striding over (job, tile, frame group) work items).
 template <class C>
@@ -446,6 +629,14 @@ __global__ __launch_bounds__(C::NT) void mfma_fwd_t_kernel(MfmaLaunch a) {
 template <class C>
 __global__ __launch_bounds__(C::NT) void mfma_adj_kernel(MfmaLaunch a) {
   mfma_adj_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd16_kernel(MfmaLaunch a) {
+  mfma_fwd_body<C, false, true>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_adj16_kernel(MfmaLaunch a) {
+  mfma_adj16_body<C>(a, blockIdx.x, blockIdx.y);
 }
 template <class C>
 __global__ __launch_bounds__(C::NT) void mfma_fwd_batched(const MfmaLaunch* __restrict__ descs,
@@ -568,6 +759,22 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
   static_assert(C0::TH == MF_TILE && C0::TW == MF_TILE, "tile");
   static_assert(C1::TH == MF_TILE && C1::TW == MF_TILE, "tile");
   static_assert(C2::TH == MF_TILE && C2::TW == MF_TILE, "tile");
+  if constexpr (PREC == EM_FP16_SPLIT) {
+    if (a.r16 != nullptr && dir == 0) {
+      if (variant == 1) hipLaunchKernelGGL(mfma_fwd16_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
+      else if (variant == 2) hipLaunchKernelGGL(mfma_fwd16_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
+      else hipLaunchKernelGGL(mfma_fwd16_kernel<C0>, grid, dim3(C0::NT), 0, s, a);
+      return hipGetLastError();
+    }
+    if (a.r16 != nullptr) {
+      if (variant == 1) hipLaunchKernelGGL(mfma_adj16_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
+      else if (variant == 2) hipLaunchKernelGGL(mfma_adj16_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
+      else hipLaunchKernelGGL(mfma_adj16_kernel<C0>, grid, dim3(C0::NT), 0, s, a);
+      return hipGetLastError();
+    }
+  } else {
+    if (a.r16 != nullptr) return hipErrorInvalidValue;
+  }
   if (dir == 0 && a.out_y != nullptr) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_t_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_t_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
@@ -633,9 +840,106 @@ hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, cons
 }
 
 bool mfma_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
-  if (g.sr == 2) return mfma2_desc_ok(g, dir, tiles, groups, a);
+  if (g.sr == 2) return a.r16 == nullptr && mfma2_desc_ok(g, dir, tiles, groups, a);
+  // r16 planes: the plane geometry the set-up laid out, and the stride between frames
+  if (a.r16 != nullptr &&
+      (!uses_r16(g) || a.e16 == nullptr || a.p16 != r16_pitch(g) ||
+       a.s16 != (int64_t)r16_rows(g) * r16_pitch(g) || a.out_y != nullptr || a.out != nullptr ||
+       (dir == 1 && a.in != nullptr)))
+    return false;
   return a.H == g.Hl && a.W == g.Wl &&
          launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, MF_TILE, MF_TILE);
+}
+
+int r16_pitch(const Geometry& g) { return MF_TILE * ((g.Wl + MF_TILE - 1) / MF_TILE) + 48; }
+int r16_rows(const Geometry& g) { return MF_TILE * ((g.Hl + MF_TILE - 1) / MF_TILE) + g.KT - 1; }
+
+// Zero the r16 planes (16 bytes per thread).
+__global__ __launch_bounds__(256) void r16_clear_kernel(uint4* p, int64_t count) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * 256)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+// Per frame (one block each): the largest weight u_t and the sum of f_t.
+__global__ __launch_bounds__(1024) void r16_frame_stats_kernel(const float* u, int64_t Nf,
+                                                               const float* psf, int K,
+                                                               float* umax, float* fsum) {
+  __shared__ float redm[16];
+  __shared__ double reds[16];
+  const int t = blockIdx.x;
+  const float* ut = u + (int64_t)t * Nf;
+  float m = 0.f;
+  for (int64_t i = threadIdx.x; i < Nf; i += 1024) m = fmaxf(m, ut[i]);
+  double sf = 0.0;
+  for (int i = threadIdx.x; i < K * K; i += 1024) sf += (double)psf[(int64_t)t * K * K + i];
+  m = wave_max(m);
+  for (int off = 32; off > 0; off >>= 1) sf += __shfl_xor(sf, off, 64);
+  if ((threadIdx.x & 63) == 0) {
+    redm[threadIdx.x >> 6] = m;
+    reds[threadIdx.x >> 6] = sf;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float mm = 0.f;
+    double ss = 0.0;
+    for (int i = 0; i < 16; ++i) {
+      mm = fmaxf(mm, redm[i]);
+      ss += reds[i];
+    }
+    umax[t] = mm;
+    fsum[t] = (float)ss;
+  }
+}
+
+// Block maxima of x (R16_XBLOCKS blocks, grid-stride).
+__global__ __launch_bounds__(256) void r16_xmax_kernel(const float* x, int64_t Nl, float* part) {
+  __shared__ float red[4];
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < Nl; i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, x[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+// e16[t]: the power of two that maps the bound 2 max u_t (sum f_t) max x of
+// |u_t F_t x| into [2^14, 2^15) (x >= 0 and f_t >= 0, so 0 <= F_t x <= sum f_t
+// max x; the factor 2 covers the rounding of the matrix-core products), so no
+// scaled value overflows binary16 and values down to 2^-29 of the bound keep
+// 11 significant bits.
+__global__ __launch_bounds__(256) void r16_scale_kernel(const float* part, int nb,
+                                                        const float* umax, const float* fsum,
+                                                        int n, int* e16) {
+  __shared__ float red[4];
+  float m = 0.f;
+  for (int i = threadIdx.x; i < nb; i += 256) m = fmaxf(m, part[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  const float xm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  for (int t = threadIdx.x; t < n; t += 256) e16[t] = f16_scale_exp(2.f * umax[t] * fsum[t] * xm);
+}
+
+hipError_t launch_r16_setup(const Geometry& g, const float* u, const float* psf,
+                            unsigned short* r16, float* umax, float* fsum, hipStream_t s) {
+  const int64_t halves = (int64_t)g.n * r16_rows(g) * r16_pitch(g);   // multiple of 8
+  const int64_t n16 = halves / 8;
+  const int blocks = (int)std::min<int64_t>(8192, (n16 + 255) / 256);
+  hipLaunchKernelGGL(r16_clear_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s,
+                     reinterpret_cast<uint4*>(r16), n16);
+  hipLaunchKernelGGL(r16_frame_stats_kernel, dim3(g.n), dim3(1024), 0, s, u, g.Nf, psf, g.K,
+                     umax, fsum);
+  return hipGetLastError();
+}
+
+hipError_t launch_r16_scale(const Geometry& g, const float* x, float* xpart, const float* umax,
+                            const float* fsum, int* e16, hipStream_t s) {
+  hipLaunchKernelGGL(r16_xmax_kernel, dim3(R16_XBLOCKS), dim3(256), 0, s, x, g.Nl, xpart);
+  hipLaunchKernelGGL(r16_scale_kernel, dim3(1), dim3(256), 0, s, xpart, R16_XBLOCKS, umax, fsum,
+                     g.n, e16);
+  return hipGetLastError();
 }
 
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,

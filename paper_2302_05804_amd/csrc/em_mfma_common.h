@@ -380,6 +380,78 @@ __device__ inline void forward_epilogue_ul(const f32x4 (&acc)[BR][BC], int unsca
       }
 }
 
+// Forward epilogues that write r = u m as binary16 into an r16 plane (rows of
+// `pitch` halves, frame pixel (k, l) at row k + off, column l + off), scaled
+// by 2^e: the FP32 product u m, then the exact power-of-two scale, then one
+// rounding to binary16 (the encoding the adjoint's staging used to apply).
+struct R16Out {
+  unsigned short* plane;
+  int pitch, off, e;
+  __device__ void put(int k, int l, float r) const {
+    plane[(int64_t)(k + off) * pitch + (l + off)] = f16_bits((_Float16)ldexpf(r, e));
+  }
+};
+
+// u from LDS (ub: the tile's TH x TW weights from (k0, l0)), as forward_epilogue_ul.
+template <int BR, int BC, int TW>
+__device__ inline void forward_epilogue_ul16(const f32x4 (&acc)[BR][BC], int unscale,
+                                             const BlockPos& P, int H, int W, int k0, int l0,
+                                             const float* ub, const R16Out& o) {
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = P.row(b, v), l = P.col(q);
+        if (k < H && l < W) {
+          const float m = ldexpf(acc[b][q][v], unscale);
+          o.put(k, l, ub[(k - k0) * TW + (l - l0)] * m);
+        }
+      }
+}
+
+// u (and y, for the loglik partial of u (y - m)^2) from HBM, loads first, as
+// forward_epilogue_w.
+template <int BR, int BC, bool WITH_Y>
+__device__ inline double forward_epilogue_w16(const f32x4 (&acc)[BR][BC], int unscale,
+                                              const BlockPos& P, int H, int W,
+                                              const float* __restrict__ ut,
+                                              const float* __restrict__ yt, const R16Out& o) {
+  float uu[BR][BC][4], yy[BR][BC][4];
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int off = min(P.row(b, v), H - 1) * W + min(P.col(q), W - 1);
+        uu[b][q][v] = ut[off];
+        if constexpr (WITH_Y) yy[b][q][v] = yt[off];
+      }
+  double llp = 0.0;
+#pragma unroll
+  for (int b = 0; b < BR; ++b)
+#pragma unroll
+    for (int q = 0; q < BC; ++q)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int k = P.row(b, v), l = P.col(q);
+        if (k < H && l < W) {
+          const float m = ldexpf(acc[b][q][v], unscale);
+          const float u = uu[b][q][v];
+          o.put(k, l, u * m);
+          if constexpr (WITH_Y) {
+            if (u > 0.f) {
+              const double d = (double)yy[b][q][v] - (double)m;
+              llp += (double)u * d * d;
+            }
+          }
+        }
+      }
+  return llp;
+}
+
 template <int BR, int BC>
 __device__ inline double forward_epilogue(const f32x4 (&acc)[BR][BC], int unscale,
                                           const BlockPos& P, int H, int W,
