@@ -9,7 +9,13 @@ Inputs are synthetic, seeded, and resident in HBM before timing starts.
 Default: the HSC-shaped workload (33 frames of 4096^2, 43x43 PSFs) timed in
 the FP16 split matrix-core form (binary16 image with a power-of-two tile scale
 times a binary16 hi+lo PSF; the reported value), in the BF16 hi+lo split form
-and in plain FP32 on the same data.  --workload c4 is the super-resolution
+and in plain FP32 on the same data.  Each form runs the whole 100-iteration
+job from the flat start; the reported value is its last --steps iterations,
+and the whole job, untraced and with the FP64 log-likelihood traced every
+iteration, is reported beside it.  The default run then times two more legs
+(--legs): c4 in the same three forms, and a shortened c5 serving stream
+(--leg-jobs jobs): saturated jobs/s and frame-Mpix/s, p50/p99 latency at 0.8x
+capacity, and the one-job-at-a-time FP32 loop on the same trace.  --workload c4 is the super-resolution
 model of Eq. (3), c4y the super-resolution run described after Eq. (4)
 (up-sampled exposures), c3t c3 with satellite trails under Student-t noise,
 psf the fit of the super-resolved PSFs of Eq. (4)
@@ -122,8 +128,10 @@ class FineGrid:
         self.latent_shape = self.frame_shape
 
 
-def cpu_baseline(prob, crop: int, iters: int):
-    """The FP64 oracle as it stands, one thread, on a crop of the workload."""
+def cpu_baseline(prob, crop: int, iters: int, frames: int = 0):
+    """The FP64 oracle as it stands, one thread, on a crop of the workload (the
+    first `frames` frames when given: the rate per frame pixel does not depend
+    on the frame count)."""
     import numpy as np
 
     import oracle
@@ -132,8 +140,10 @@ def cpu_baseline(prob, crop: int, iters: int):
     H, W = src.frame_shape
     crop = min(crop // up, H, W)
     cy, cx = (H - crop) // 2, (W - crop) // 2
-    y = np.ascontiguousarray(src.y[:, cy:cy + crop, cx:cx + crop])
-    v = np.ascontiguousarray(src.v[:, cy:cy + crop, cx:cx + crop])
+    nf = prob.n if frames <= 0 else min(frames, prob.n)
+    y = np.ascontiguousarray(src.y[:nf, cy:cy + crop, cx:cx + crop])
+    v = np.ascontiguousarray(src.v[:nf, cy:cy + crop, cx:cx + crop])
+    psf = np.ascontiguousarray(prob.psf[:nf])
     if up > 1:
         y, v = oracle.upsample(y, v, up)
         crop *= up
@@ -143,23 +153,32 @@ def cpu_baseline(prob, crop: int, iters: int):
     t0 = time.perf_counter()
     nu = getattr(prob, "nu", 0.0)
     if nu:
-        oracle.run_t(y, v, prob.psf, x0, iters, nu, s)
+        oracle.run_t(y, v, psf, x0, iters, nu, s)
     else:
-        oracle.run(y, v, prob.psf, x0, iters, s)
+        oracle.run(y, v, psf, x0, iters, s)
     dt = time.perf_counter() - t0
-    fpix = prob.n * crop * crop * iters
+    fpix = nf * crop * crop * iters
     return {
         "value": round(fpix / dt / 1e6, 6),
         "unit": METRIC,
         "cores": 1,
         "kind": "oracle",
-        "sample": f"{crop}x{crop} centre crop of every frame ({prob.n} frames), {iters} "
-                  f"iterations, FP64 single-threaded C oracle, {dt:.1f} s",
+        "sample": f"{crop}x{crop} centre crop of {nf} of the {prob.n} frames, {iters} "
+                  f"iteration(s), FP64 single-threaded C oracle, {dt:.1f} s",
     }
 
 
 def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
-    """Time one precision form on resident inputs; returns a dict of figures."""
+    """Time one precision form on resident inputs; returns a dict of figures.
+
+    After the autotuner and `warmup` iterations (which also capture the traced
+    and untraced iteration graphs), the iterate is reset to the job's starting
+    image x^(0) and the whole job runs: n_iter iterations (the workload's count,
+    or `steps` if larger), of which the last `steps` are the timed region of the
+    reported value; the whole job's time is reported beside it.  The job then
+    runs again from x^(0) with the FP64 log-likelihood traced every iteration.
+    Per-kernel launch times come from em_profile at the job's final iterate.
+    """
     import torch
     y, v, f = tensors
     n, hf, wf = y.shape
@@ -169,22 +188,38 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
     with torch.cuda.stream(stream):
         ctx = em.Context(p, y, v, f, x, x0=None, stream=stream)
     torch.cuda.synchronize()
+    x_start = x.clone()
     tuned = None
     if prec_name != "fp32":
         fv, av, tms = ctx.autotune(3)
         tuned = {"forward_variant": fv, "adjoint_variant": av,
                  "variant_ms": [[round(t, 4) for t in row] for row in tms.tolist()]}
         log(f"  autotune: forward variant {fv}, adjoint variant {av}")
-    ctx.iterate(warmup)
+    ctx.iterate(max(warmup, 1))
+    ctx.iterate(1, trace=True)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
+    job_iters = max(prob.n_iter, steps)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+    x.copy_(x_start)
     torch.cuda.synchronize()
-    ev0.record(stream)
+    ev[0].record(stream)
+    ctx.iterate(job_iters - steps)
+    ev[1].record(stream)
     ctx.iterate(steps)          # graph-captured iteration, replayed `steps` times
-    ev1.record(stream)
+    ev[2].record(stream)
     torch.cuda.synchronize()
-    gpu_ms = ev0.elapsed_time(ev1)
+    gpu_ms = ev[1].elapsed_time(ev[2])
+    job_ms = ev[0].elapsed_time(ev[2])
+    x_end = x.clone()
+    x.copy_(x_start)
+    torch.cuda.synchronize()
+    ev[3].record(stream)
+    trace = ctx.iterate(job_iters, trace=True)
+    ev[4].record(stream)
+    torch.cuda.synchronize()
+    traced_ms = ev[3].elapsed_time(ev[4])
+    traced_same = bool(torch.equal(x, x_end))
+    ll_monotone = bool((trace[1:] >= trace[:-1] - 1e-12 * abs(trace[:-1])).all()) if not nu else None
     fpix = n * hf * wf
     value = fpix * steps / (gpu_ms / 1e3) / 1e6
     phases = ctx.profile(max(2, min(steps, 10)))
@@ -199,10 +234,23 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
     mf = prec_name != "fp32"
     peak = PEAKS_TFLOPS["bf16" if mf else "fp32"]
     name = ["forward", "adjoint"][dom]
-    log(f"  {prec_name}: {gpu_ms / steps:.3f} ms/step, {value:.1f} frame-Mpix/s; per launch "
-        f"forward {phases[0]:.3f} ms, adjoint {phases[1]:.3f} ms")
+    log(f"  {prec_name}: {gpu_ms / steps:.3f} ms/step (iterations {job_iters - steps + 1}-"
+        f"{job_iters}), {value:.1f} frame-Mpix/s; whole {job_iters}-iteration job {job_ms:.1f} ms, "
+        f"with the loglik traced {traced_ms:.1f} ms; per launch forward {phases[0]:.3f} ms, "
+        f"adjoint {phases[1]:.3f} ms")
+    job = {"iterations": job_iters, "ms": round(job_ms, 3),
+           "value": round(fpix * job_iters / (job_ms / 1e3) / 1e6, 2),
+           "ms_per_iteration": round(job_ms / job_iters, 4),
+           "traced_loglik_ms": round(traced_ms, 3),
+           "traced_ms_per_iteration": round(traced_ms / job_iters, 4),
+           "traced_value": round(fpix * job_iters / (traced_ms / 1e3) / 1e6, 2),
+           "traced_x_bitwise_equal_untraced": traced_same,
+           "loglik_first_last": [float(trace[0]), float(trace[-1])]}
+    if ll_monotone is not None:
+        job["loglik_nondecreasing"] = ll_monotone
     return {
-        "value": value, "ms_per_step": gpu_ms / steps, "tuned": tuned, "ok": ok,
+        "value": value, "ms_per_step": gpu_ms / steps, "tuned": tuned, "ok": ok, "job": job,
+        "timed_iterations": [job_iters - steps + 1, job_iters],
         "per_launch_ms": {"forward": round(phases[0], 4), "adjoint": round(phases[1], 4),
                           "update": round(phases[2], 4), "iteration": round(phases[3], 4)},
         "roofline": {"bound": "mfma" if mf else "alu", "kernel": name,
@@ -335,19 +383,21 @@ def serving_bench(args):
         t_end = time.perf_counter()
         tms = [srv.times(i) for i in ids]
         st = srv.stats()
+        ph = srv.phase_seconds()
         srv.close()
         lat = np.array([t[2] - t[0] for t in tms])
-        return t_end - t_start, lat, st
+        return t_end - t_start, lat, st, ph
 
     # capacity: everything submitted at once
-    mk, _, st = run_server([0.0] * len(jobs))
+    mk, _, st, ph = run_server([0.0] * len(jobs))
     capacity = len(jobs) / mk
-    log(f"saturated: {len(jobs)} jobs in {mk:.2f} s = {capacity:.2f} jobs/s; stats {st}")
+    log(f"saturated: {len(jobs)} jobs in {mk:.2f} s = {capacity:.2f} jobs/s; stats {st}; "
+        f"worker seconds {ph}")
     # latency at 0.8 x capacity, Poisson arrivals
     rate = 0.8 * capacity
     gaps = np.random.default_rng(5004).exponential(1.0 / rate, len(jobs))
     arrivals = np.cumsum(gaps) - gaps[0]
-    mk2, lat, st2 = run_server(arrivals.tolist())
+    mk2, lat, st2, _ = run_server(arrivals.tolist())
     p50, p99 = np.percentile(lat, 50), np.percentile(lat, 99)
     log(f"Poisson at {rate:.2f} jobs/s: makespan {mk2:.2f} s, p50 {p50 * 1e3:.0f} ms, "
         f"p99 {p99 * 1e3:.0f} ms")
@@ -385,10 +435,14 @@ def serving_bench(args):
         "serving": {
             "jobs": len(jobs), "slots": args.slots, "hbm_budget_gib": args.serve_budget_gib,
             "capacity_jobs_per_s": round(capacity, 3),
+            "saturated_frame_mpix_per_s": round(total_fpix / mk / 1e6, 1),
+            "saturated_makespan_s": round(mk, 3),
+            "saturated_worker_seconds": {k: round(v, 3) for k, v in ph.items()},
             "arrival_rate_jobs_per_s": round(rate, 3),
             "p50_latency_ms": round(float(p50) * 1e3, 1),
             "p99_latency_ms": round(float(p99) * 1e3, 1),
             "mixed_precision": f"{args.serve_precision} (matrix cores) for every job",
+            "speedup_vs_fp32_one_at_a_time": round(capacity / base_cap, 3),
             "fp32_one_at_a_time": {
                 "capacity_jobs_per_s": round(base_cap, 3),
                 "frame_mpix_per_s": round(total_fpix / sum(svc) / 1e6, 1),
@@ -400,6 +454,12 @@ def serving_bench(args):
     }
 
 
+def forms_cfg(res):
+    return {fm: {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
+                 "job": r["job"], "per_launch_ms": r["per_launch_ms"], "roofline": r["roofline"]}
+            for fm, r in res.items()}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawTextHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -409,9 +469,15 @@ def main() -> int:
     ap.add_argument("--precision", default="auto",
                     choices=["auto", "fp32", "bf16split", "fp16split", "bf16"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-crop", type=int, default=128)
-    ap.add_argument("--cpu-iters", type=int, default=2)
+    ap.add_argument("--cpu-crop", type=int, default=512)
+    ap.add_argument("--cpu-iters", type=int, default=1)
+    ap.add_argument("--cpu-frames", type=int, default=8,
+                    help="frames of the CPU baseline's crop (0 = all)")
     ap.add_argument("--jobs", type=int, default=200, help="c5: jobs in the stream")
+    ap.add_argument("--legs", default="c4,c5",
+                    help="c3 only: further workloads timed after c3 and reported in config "
+                         "(comma list of c4, c5; '' for none)")
+    ap.add_argument("--leg-jobs", type=int, default=80, help="jobs of the c5 leg of a c3 run")
     ap.add_argument("--slots", type=int, default=16, help="c5: server slots")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="c5: HBM budget")
     ap.add_argument("--serve-precision", default="fp16split", choices=["fp16split", "bf16split"],
@@ -511,17 +577,50 @@ def main() -> int:
         "per_launch_ms": head["per_launch_ms"],
         "result_finite_nonnegative": head["ok"],
         "autotune": head["tuned"],
-        "forms": {fm: {"value": round(r["value"], 2), "ms_per_step": round(r["ms_per_step"], 4),
-                       "per_launch_ms": r["per_launch_ms"], "roofline": r["roofline"]}
-                  for fm, r in res.items()},
+        "timed_iterations": head["timed_iterations"],
+        "job": head["job"],
+        "forms": forms_cfg(res),
     }
     if "fp32" in res and forms[0] != "fp32":
         cfg["speedup_vs_fp32"] = round(head["value"] / res["fp32"]["value"], 3)
     out.update({"value": round(head["value"], 2), "ms_per_step": round(head["ms_per_step"], 4),
                 "dtype": DTYPES[forms[0]], "config": cfg, "roofline": head["roofline"]})
+    legs = [l for l in args.legs.split(",") if l] if args.workload == "c3" else []
+    if legs:
+        del tensors
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        cfg["legs"] = {}
+    if "c4" in legs:
+        t0 = time.perf_counter()
+        p4 = synth.make_problem("c4")
+        log(f"leg c4: generated frames {p4.y.shape} on a {p4.latent_shape} latent grid in "
+            f"{time.perf_counter() - t0:.1f} s")
+        t4 = tuple(torch.from_numpy(a).to(dev) for a in (p4.y, p4.v, p4.psf))
+        r4 = {}
+        for fm in forms:
+            log(f"timing c4 {fm}")
+            r4[fm] = time_form(em, p4, t4, fm, args.steps, args.warmup, stream)
+        del t4
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+        leg = {"workload": WORKLOADS["c4"], "value": round(r4[forms[0]]["value"], 2),
+               "precision": forms[0], "timed_iterations": r4[forms[0]]["timed_iterations"],
+               "forms": forms_cfg(r4)}
+        if "fp32" in r4 and forms[0] != "fp32":
+            leg["speedup_vs_fp32"] = round(r4[forms[0]]["value"] / r4["fp32"]["value"], 3)
+        cfg["legs"]["c4"] = leg
+    if "c5" in legs:
+        log(f"leg c5: serving stream of {args.leg_jobs} jobs")
+        a5 = argparse.Namespace(**vars(args))
+        a5.jobs = args.leg_jobs
+        r5 = serving_bench(a5)
+        cfg["legs"]["c5"] = {"workload": WORKLOADS["c5"], "metric": METRIC + " and job latency",
+                             "value": round(r5["value"], 2), "dtype": DTYPES[args.serve_precision],
+                             **r5["serving"]}
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a crop ...")
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_crop, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_crop, args.cpu_iters, args.cpu_frames)
         log(f"cpu baseline: {out['cpu_baseline']['value']} frame-Mpix/s")
     print(json.dumps(out), flush=True)
     return 0
