@@ -160,6 +160,17 @@ hipError_t launch_r16_setup(const Geometry& g, const float* u, const float* psf,
 constexpr int R16_XBLOCKS = 256;
 hipError_t launch_r16_scale(const Geometry& g, const float* x, float* xpart, const float* umax,
                             const float* fsum, int* e16, hipStream_t s);
+// the scale step of several jobs' r16 planes in one pair of launches (serving)
+struct R16Job {
+  const float* x;
+  int64_t Nl;
+  float* xpart;
+  const float* umax;
+  const float* fsum;
+  int* e16;
+  int n;
+};
+hipError_t launch_r16_scale_batched(const R16Job* jobs, int n_jobs, hipStream_t s);
 hipError_t launch_mfma(const Geometry& g, int dir, int variant, int tiles, int groups,
                        const MfmaLaunch& a, hipStream_t s);
 int mfma_table_rows(int KT);
@@ -178,7 +189,7 @@ int mfma2_adj_tile_h(int precision);
 int mfma2_adj_tile_w(int precision);
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
                                const int4* items, int n_items, int grid, hipStream_t s,
-                               bool robust = false);
+                               bool robust = false, bool r16 = false);
 // 2 (lgamma((nu+1)/2) - lgamma(nu/2) - ln(nu pi)/2) + ln(2 pi): the constant of
 // the Student-t loglik partials (em_api.cpp)
 double student_t_lcst(double nu);
@@ -317,6 +328,8 @@ void fill_forward_fp32(const em_ctx* c, FwdLaunch* f, bool write_r, bool loglik)
 void fill_forward_mfma(const em_ctx* c, MfmaLaunch* m, bool write_r, bool loglik);
 void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc);
 void fill_adjoint_mfma(const em_ctx* c, MfmaLaunch* m, double* part_rc);
+// point a forward (dir 0) or adjoint (dir 1) descriptor at the job's binary16 r planes
+void apply_r16(const em_ctx* c, MfmaLaunch* m, int dir);
 // em_init with the plan used by the serving loop (single frame group in the
 // adjoint, fixed kernel variants), so a served job computes the same way
 // alone and in any mix.

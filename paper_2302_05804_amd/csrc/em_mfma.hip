@@ -671,6 +671,28 @@ __global__ __launch_bounds__(C::NT) void mfma_adj_batched(const MfmaLaunch* __re
     __syncthreads();
   }
 }
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_fwd16_batched(const MfmaLaunch* __restrict__ descs,
+                                                            const int4* __restrict__ items,
+                                                            int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const int4 w = items[i];
+    const MfmaLaunch d = descs[w.x];
+    mfma_fwd_body<C, false, true>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void mfma_adj16_batched(const MfmaLaunch* __restrict__ descs,
+                                                            const int4* __restrict__ items,
+                                                            int n_items) {
+  for (int i = blockIdx.x; i < n_items; i += gridDim.x) {
+    const int4 w = items[i];
+    const MfmaLaunch d = descs[w.x];
+    mfma_adj16_body<C>(d, w.y, w.z);
+    __syncthreads();
+  }
+}
 
 // Toeplitz fragment tables, one block per (frame, kernel row a): entry
 // [t][a][h][s][lane] holds the 8 16-bit values U_a[32h + 8(lane/16) + e][lane%16],
@@ -795,13 +817,29 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
 namespace {
 template <int KT, int PREC>
 hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* d, const int4* it,
-                              int n, hipStream_t s, bool robust) {
+                              int n, hipStream_t s, bool robust, bool r16) {
   // Toeplitz fragments: staged in LDS for the one-plane binary16 image (LDS
   // traffic is low there), register prefetch for the two-plane bf16 split
   constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
   using C0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, PFT>;
   using C1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, PFT>;
   using C2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, PFT>;
+  if constexpr (PREC == EM_FP16_SPLIT) {
+    if (r16 && dir == 0) {
+      if (variant == 1) hipLaunchKernelGGL(mfma_fwd16_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
+      else if (variant == 2) hipLaunchKernelGGL(mfma_fwd16_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
+      else hipLaunchKernelGGL(mfma_fwd16_batched<C0>, dim3(grid), dim3(C0::NT), 0, s, d, it, n);
+      return hipGetLastError();
+    }
+    if (r16) {
+      if (variant == 1) hipLaunchKernelGGL(mfma_adj16_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
+      else if (variant == 2) hipLaunchKernelGGL(mfma_adj16_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
+      else hipLaunchKernelGGL(mfma_adj16_batched<C0>, dim3(grid), dim3(C0::NT), 0, s, d, it, n);
+      return hipGetLastError();
+    }
+  } else {
+    if (r16) return hipErrorInvalidValue;
+  }
   if (dir == 0 && robust) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_t_batched<C1>, dim3(grid), dim3(C1::NT), 0, s, d, it, n);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_t_batched<C2>, dim3(grid), dim3(C2::NT), 0, s, d, it, n);
@@ -821,16 +859,16 @@ hipError_t launch_dir_batched(int dir, int variant, int grid, const MfmaLaunch* 
 
 hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, const MfmaLaunch* descs,
                                const int4* items, int n_items, int grid, hipStream_t s,
-                               bool robust) {
+                               bool robust, bool r16) {
   if (n_items <= 0) return hipSuccess;
 #define EM_MF_DISPATCH(KTV)                                                                  \
   switch (precision) {                                                                       \
     case EM_BF16_SPLIT:                                                                      \
-      return launch_dir_batched<KTV, EM_BF16_SPLIT>(dir, variant, grid, descs, items, n_items, s, robust); \
+      return launch_dir_batched<KTV, EM_BF16_SPLIT>(dir, variant, grid, descs, items, n_items, s, robust, r16); \
     case EM_FP16_SPLIT:                                                                      \
-      return launch_dir_batched<KTV, EM_FP16_SPLIT>(dir, variant, grid, descs, items, n_items, s, robust); \
+      return launch_dir_batched<KTV, EM_FP16_SPLIT>(dir, variant, grid, descs, items, n_items, s, robust, r16); \
     case EM_BF16:                                                                            \
-      return launch_dir_batched<KTV, EM_BF16>(dir, variant, grid, descs, items, n_items, s, robust); \
+      return launch_dir_batched<KTV, EM_BF16>(dir, variant, grid, descs, items, n_items, s, robust, r16); \
     default:                                                                                 \
       return hipErrorInvalidValue;                                                           \
   }
@@ -920,6 +958,39 @@ __global__ __launch_bounds__(256) void r16_scale_kernel(const float* part, int n
   __syncthreads();
   const float xm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
   for (int t = threadIdx.x; t < n; t += 256) e16[t] = f16_scale_exp(2.f * umax[t] * fsum[t] * xm);
+}
+
+// Several jobs at once (serving): job j = blockIdx.y / blockIdx.x.
+__global__ __launch_bounds__(256) void r16_xmax_batched_kernel(const R16Job* jobs) {
+  __shared__ float red[4];
+  const R16Job j = jobs[blockIdx.y];
+  float m = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < j.Nl;
+       i += (int64_t)gridDim.x * 256)
+    m = fmaxf(m, j.x[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) j.xpart[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+}
+
+__global__ __launch_bounds__(256) void r16_scale_batched_kernel(const R16Job* jobs) {
+  __shared__ float red[4];
+  const R16Job j = jobs[blockIdx.x];
+  float m = 0.f;
+  for (int i = threadIdx.x; i < R16_XBLOCKS; i += 256) m = fmaxf(m, j.xpart[i]);
+  m = wave_max(m);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+  __syncthreads();
+  const float xm = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+  for (int t = threadIdx.x; t < j.n; t += 256) j.e16[t] = f16_scale_exp(2.f * j.umax[t] * j.fsum[t] * xm);
+}
+
+hipError_t launch_r16_scale_batched(const R16Job* jobs, int n_jobs, hipStream_t s) {
+  if (n_jobs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(r16_xmax_batched_kernel, dim3(R16_XBLOCKS, n_jobs), dim3(256), 0, s, jobs);
+  hipLaunchKernelGGL(r16_scale_batched_kernel, dim3(n_jobs), dim3(256), 0, s, jobs);
+  return hipGetLastError();
 }
 
 hipError_t launch_r16_setup(const Geometry& g, const float* u, const float* psf,

@@ -120,6 +120,7 @@ struct Family {
   int kind = 0;       // 0 = FP32 direct, 1 = matrix core
   int sr = 1, KT = 43, precision = EM_FP32, fvar = 0, avar = 0;
   bool robust = false;  // Student-t noise: E-step weights in the forward, numerator adjoint
+  bool r16 = false;     // FP16 split, sr = 1, Gaussian: r through binary16 planes
   std::vector<FwdLaunch> fwd32;
   std::vector<AdjLaunch> adj32, adjB32;
   std::vector<MfmaLaunch> fwdmf, adjmf, adjBmf;
@@ -161,6 +162,9 @@ struct em_server {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
+  // admissions (input upload, set-up) and finishing run on a second stream,
+  // so that jobs can be admitted while the rounds of the others run
+  hipStream_t side = nullptr;
   char* arena_base = nullptr;
   size_t budget = 0;
   Arena arena;
@@ -176,6 +180,9 @@ struct em_server {
   std::thread worker;
   // round state
   std::vector<Family> fams;
+  std::vector<R16Job> r16jobs;     // scale step of the r16 jobs of the round
+  void* d_r16jobs = nullptr;
+  size_t cap_r16jobs = 0;
   bool dirty = true;
   hipGraphExec_t graph{};
   bool graph_ok = false;
@@ -219,13 +226,16 @@ int build_round(em_server* S) {
   auto family_of = [&](const em_ctx* c) -> Family& {
     const int kind = uses_mfma(c->g) ? 1 : 0;
     const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
+    const bool r16 = uses_r16(c->g);
     for (auto& f : S->fams)
       if (f.kind == kind && f.sr == c->g.sr && f.KT == c->g.KT && f.precision == c->g.precision &&
-          f.fvar == c->pl.fwd_variant && f.avar == c->pl.adj_variant && f.robust == robust)
+          f.fvar == c->pl.fwd_variant && f.avar == c->pl.adj_variant && f.robust == robust &&
+          f.r16 == r16)
         return f;
     Family f;
     f.kind = kind;
     f.robust = robust;
+    f.r16 = r16;
     f.sr = c->g.sr;
     f.KT = c->g.KT;
     f.precision = c->g.precision;
@@ -249,6 +259,7 @@ int build_round(em_server* S) {
   std::stable_sort(order.begin(), order.end(), [](const Job* a, const Job* b) {
     return (double)a->g.n * a->g.Nl > (double)b->g.n * b->g.Nl;
   });
+  S->r16jobs.clear();
   for (Job* j : order) {
     Family& f = family_of(j->ctx);
     const em_ctx* c = j->ctx;
@@ -262,11 +273,17 @@ int build_round(em_server* S) {
         m.nu = c->g.nu;
         m.lcst = lcst;
       }
+      if (f.r16) {
+        apply_r16(c, &m, 0);
+        S->r16jobs.push_back(R16Job{c->x, c->g.Nl, c->r16_xpart, c->r16_umax, c->r16_fsum,
+                                    c->r16_e, c->g.n});
+      }
       if (!mfma_desc_ok(c->g, 0, c->pl.fwd_tiles, c->pl.fwd_groups, m))
         return fail(EM_EDEVICE, "inconsistent forward descriptor");
       add_items(f.fitems, (int)f.fwdmf.size(), c->pl.fwd_tiles, c->pl.fwd_groups);
       f.fwdmf.push_back(m);
       fill_adjoint_mfma(c, &m, nullptr);
+      if (f.r16) apply_r16(c, &m, 1);
       if (!mfma_desc_ok(c->g, 1, c->pl.adj_tiles, 1, m) || m.fused != 1)
         return fail(EM_EDEVICE, "inconsistent adjoint descriptor");
       add_items(f.aitems, (int)f.adjmf.size(), c->pl.adj_tiles, 1);
@@ -325,6 +342,7 @@ int build_round(em_server* S) {
     if ((rc = upload(S, reinterpret_cast<void**>(&f.d_fitems), &f.cap_fitems, f.fitems))) return rc;
     if ((rc = upload(S, reinterpret_cast<void**>(&f.d_aitems), &f.cap_aitems, f.aitems))) return rc;
   }
+  if ((rc = upload(S, &S->d_r16jobs, &S->cap_r16jobs, S->r16jobs))) return rc;
   if (hipStreamSynchronize(S->stream) != hipSuccess) return fail(EM_EDEVICE, "upload sync");
   // capture one round
   if (S->graph_ok) (void)hipGraphExecDestroy(S->graph);
@@ -332,8 +350,11 @@ int build_round(em_server* S) {
   hipGraph_t gr = nullptr;
   if (hipStreamBeginCapture(S->stream, hipStreamCaptureModeThreadLocal) != hipSuccess)
     return fail(EM_EDEVICE, "graph capture");
-  hipError_t e = hipSuccess;
+  // the binary16 scales of every r16 job, from its current iterate
+  hipError_t e = launch_r16_scale_batched(static_cast<const R16Job*>(S->d_r16jobs),
+                                          (int)S->r16jobs.size(), S->stream);
   for (auto& f : S->fams) {
+    if (e != hipSuccess) break;
     const int n = (int)f.fitems.size();
     if (f.kind == 1 && f.sr == 2) {
       e = launch_mfma2_batched(f.precision, 0, f.fvar, static_cast<const MfmaLaunch*>(f.d_fdesc),
@@ -341,7 +362,7 @@ int build_round(em_server* S) {
     } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 0, f.fvar,
                               static_cast<const MfmaLaunch*>(f.d_fdesc), f.d_fitems, n,
-                              std::min(n, 512), S->stream, f.robust);
+                              std::min(n, 512), S->stream, f.robust, f.r16);
     } else {
       e = launch_forward_batched(f.sr, f.KT, static_cast<const FwdLaunch*>(f.d_fdesc),
                                  f.d_fitems, n, std::min(n, 1024), S->stream);
@@ -374,7 +395,7 @@ int build_round(em_server* S) {
     } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 1, f.avar,
                               static_cast<const MfmaLaunch*>(f.d_adesc), f.d_aitems, n,
-                              std::min(n, 512), S->stream);
+                              std::min(n, 512), S->stream, false, f.r16);
     } else {
       e = launch_adjoint_batched(f.sr, f.KT, static_cast<const AdjLaunch*>(f.d_adesc),
                                  f.d_aitems, n, std::min(n, 1024), S->stream);
@@ -418,13 +439,15 @@ int admit(em_server* S, Job* j) {
   j->dws = base + ows;
   j->ws_bytes = wsb;
   const size_t fb = (size_t)j->g.n * j->g.Nf * sizeof(float);
-  if (hipMemcpyAsync(j->dy, j->y.data(), fb, hipMemcpyHostToDevice, S->stream) != hipSuccess ||
-      hipMemcpyAsync(j->dv, j->v.data(), fb, hipMemcpyHostToDevice, S->stream) != hipSuccess ||
+  if (hipMemcpyAsync(j->dy, j->y.data(), fb, hipMemcpyHostToDevice, S->side) != hipSuccess ||
+      hipMemcpyAsync(j->dv, j->v.data(), fb, hipMemcpyHostToDevice, S->side) != hipSuccess ||
       hipMemcpyAsync(j->dpsf, j->psf.data(), j->psf.size() * sizeof(float),
-                     hipMemcpyHostToDevice, S->stream) != hipSuccess)
+                     hipMemcpyHostToDevice, S->side) != hipSuccess)
     return fail(EM_EDEVICE, "input upload");
+  // set-up on the side stream (synchronised inside); the job's rounds start
+  // on the round stream after this returns
   const int rc = init_ctx(&j->ctx, &j->prob, j->dy, j->dv, j->dpsf, nullptr, j->dx, j->dws,
-                          j->ws_bytes, S->stream, true);
+                          j->ws_bytes, S->side, true);
   std::vector<float>().swap(j->y);
   std::vector<float>().swap(j->v);
   return rc;
@@ -436,11 +459,54 @@ int finish(em_server* S, Job* j) {
   if (rc) return rc;
   j->x_out.resize((size_t)j->g.Nl);
   if (hipMemcpyAsync(j->x_out.data(), j->dx, (size_t)j->g.Nl * sizeof(float),
-                     hipMemcpyDeviceToHost, S->stream) != hipSuccess ||
-      hipStreamSynchronize(S->stream) != hipSuccess)
+                     hipMemcpyDeviceToHost, S->side) != hipSuccess ||
+      hipStreamSynchronize(S->side) != hipSuccess)
     return fail(EM_EDEVICE, "result copy");
   j->loglik = ll;
   return EM_OK;
+}
+
+// Admission in arrival order while a slot (counting `extra` jobs admitted but
+// not yet active) and arena space are free; called with the lock held, which
+// it releases around each job's upload and set-up.  Admitted jobs with work
+// to do are appended to `admitted`.
+void admit_queued(em_server* S, std::unique_lock<std::mutex>& lk, std::vector<Job*>& admitted) {
+  while (!S->queue.empty() && (int)(S->active.size() + admitted.size()) < S->max_slots) {
+    Job* j = S->queue.front();
+    size_t off;
+    if (!S->arena.alloc(j->bytes, &off)) break;
+    S->queue.pop_front();
+    j->off = off;
+    j->state = J_ACTIVE;
+    j->t_admit = now_s();
+    lk.unlock();
+    const double ta = now_s();
+    const int rc = admit(S, j);
+    S->sec_admit += now_s() - ta;
+    lk.lock();
+    if (rc != EM_OK) {
+      j->err = rc;
+      j->errmsg = em_last_error();
+      release_job_device(S, j);
+      j->state = J_FAILED;
+      j->t_done = now_s();
+      S->cv_done.notify_all();
+      continue;
+    }
+    if (j->n_iter == 0) {  // nothing to iterate: finish at once
+      lk.unlock();
+      const int frc = finish(S, j);
+      lk.lock();
+      j->err = frc;
+      if (frc) j->errmsg = em_last_error();
+      release_job_device(S, j);
+      j->state = frc ? J_FAILED : J_DONE;
+      j->t_done = now_s();
+      S->cv_done.notify_all();
+      continue;
+    }
+    admitted.push_back(j);
+  }
 }
 
 void worker_main(em_server* S) {
@@ -463,43 +529,14 @@ void worker_main(em_server* S) {
         ++i;
       }
     }
-    // --- admission (arrival order, while a slot and arena space are free)
-    while (!S->queue.empty() && (int)S->active.size() < S->max_slots) {
-      Job* j = S->queue.front();
-      size_t off;
-      if (!S->arena.alloc(j->bytes, &off)) break;
-      S->queue.pop_front();
-      j->off = off;
-      j->state = J_ACTIVE;
-      j->t_admit = now_s();
-      lk.unlock();
-      const double ta = now_s();
-      const int rc = admit(S, j);
-      S->sec_admit += now_s() - ta;
-      lk.lock();
-      if (rc != EM_OK) {
-        j->err = rc;
-        j->errmsg = em_last_error();
-        release_job_device(S, j);
-        j->state = J_FAILED;
-        j->t_done = now_s();
-        S->cv_done.notify_all();
-        continue;
-      }
-      if (j->n_iter == 0) {  // nothing to iterate: finish at once
-        lk.unlock();
-        const int frc = finish(S, j);
-        lk.lock();
-        j->err = frc;
-        if (frc) j->errmsg = em_last_error();
-        release_job_device(S, j);
-        j->state = frc ? J_FAILED : J_DONE;
-        j->t_done = now_s();
-        S->cv_done.notify_all();
-        continue;
-      }
-      S->active.push_back(j);
-      S->dirty = true;
+    // --- admission (arrival order, while a slot and arena space are free);
+    // with nothing running it goes first, else it overlaps the rounds below
+    std::vector<Job*> admitted;
+    if (S->active.empty()) {
+      admit_queued(S, lk, admitted);
+      for (Job* j : admitted) S->active.push_back(j);
+      if (!admitted.empty()) S->dirty = true;
+      admitted.clear();
     }
     if (S->active.empty()) continue;
     // --- rounds until the first job finishes (at most round_chunk)
@@ -513,12 +550,19 @@ void worker_main(em_server* S) {
     if (rc == EM_OK) {
       for (int i = 0; i < k && rc == EM_OK; ++i)
         if (hipGraphLaunch(S->graph, S->stream) != hipSuccess) rc = fail(EM_EDEVICE, "round launch");
-      if (rc == EM_OK && hipStreamSynchronize(S->stream) != hipSuccess)
-        rc = fail(EM_EDEVICE, "round sync: %s", hipGetErrorString(hipGetLastError()));
     }
     lk.lock();
+    // queued jobs are uploaded and set up on the side stream while the rounds run
+    if (rc == EM_OK) admit_queued(S, lk, admitted);
+    lk.unlock();
+    const double tw = now_s();
+    if (rc == EM_OK && hipStreamSynchronize(S->stream) != hipSuccess)
+      rc = fail(EM_EDEVICE, "round sync: %s", hipGetErrorString(hipGetLastError()));
+    lk.lock();
     S->sec_build += tr - tb;
-    S->sec_rounds += now_s() - tr;
+    S->sec_rounds += now_s() - tw;
+    for (Job* j : admitted) S->active.push_back(j);
+    if (!admitted.empty()) S->dirty = true;
     if (rc != EM_OK) {
       // a device failure ends every active job
       S->worker_error = em_last_error();
@@ -535,7 +579,8 @@ void worker_main(em_server* S) {
       continue;
     }
     S->rounds += k;
-    for (Job* j : S->active) j->done_iter += k;
+    for (Job* j : S->active)
+      if (std::find(admitted.begin(), admitted.end(), j) == admitted.end()) j->done_iter += k;
     for (size_t i = 0; i < S->active.size();) {
       Job* j = S->active[i];
       if (j->done_iter < j->n_iter) {
@@ -607,6 +652,12 @@ int em_server_create(em_server** out, size_t hbm_budget, int32_t max_slots, void
     delete S;
     return fail(EM_ENOMEM, "cannot allocate an HBM budget of %zu bytes", hbm_budget);
   }
+  if (hipStreamCreateWithFlags(&S->side, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipFree(S->arena_base);
+    if (S->own_stream) (void)hipStreamDestroy(S->stream);
+    delete S;
+    return fail(EM_EDEVICE, "stream creation failed");
+  }
   S->budget = hbm_budget;
   S->arena.reset(hbm_budget);
   S->max_slots = max_slots;
@@ -633,7 +684,10 @@ int em_server_destroy(em_server* S) {
     if (f.d_aitems) (void)hipFree(f.d_aitems);
   }
   (void)hipStreamSynchronize(S->stream);
+  if (S->d_r16jobs) (void)hipFree(S->d_r16jobs);
+  (void)hipStreamSynchronize(S->side);
   (void)hipFree(S->arena_base);
+  (void)hipStreamDestroy(S->side);
   if (S->own_stream) (void)hipStreamDestroy(S->stream);
   for (auto& kv : S->jobs) delete kv.second;
   delete S;

@@ -45,7 +45,8 @@ def _ops(em, sr, psf, x, r):
                                           (1, 7, 33, 40, 2), (1, 43, 5, 3, 1),
                                           (1, 43, 129, 257, 1), (2, 43, 75, 66, 2),
                                           (2, 15, 40, 70, 3), (2, 43, 3, 2, 1),
-                                          (2, 43, 130, 97, 2)])
+                                          (2, 43, 130, 97, 2), (2, 43, 70, 290, 2),
+                                          (1, 43, 70, 600, 1)])
 def test_fp16_operators_elementwise_bound(sr, K, hf, wf, n):
     em = _em()
     log(f"fp16 operators sr={sr} K={K} frame {hf}x{wf} n={n}")
@@ -140,14 +141,16 @@ def test_fp16_c4_recipe_sr2():
     assert err <= X_TOL and (xg >= 0).all()
 
 
-@pytest.mark.parametrize("sr", [1, 2])
-def test_fp16_every_variant_matches_oracle(sr):
+@pytest.mark.parametrize("sr,W", [(1, 200), (2, 600)])
+def test_fp16_every_variant_matches_oracle(sr, W):
+    """Every forward x adjoint variant; for sr = 2 on a latent grid 600 wide, so
+    that the 256-wide adjoint tiles have inner seams and a ragged last tile."""
     import torch
     em = _em()
-    p = synth.make_problem("c3" if sr == 1 else "c4", H=260, W=200, n=3, seed=4403)
+    p = synth.make_problem("c3" if sr == 1 else "c4", H=260, W=W, n=3, seed=4403)
     x0 = synth.positive_start(p.latent_shape, 2.0, seed=14)
     xo = oracle.run(p.y, p.v, p.psf, x0, 3, sr=sr)
-    prob = em.Problem.make(3, 260 // sr, 200 // sr, 43, sr=sr, precision=em.FP16_SPLIT)
+    prob = em.Problem.make(3, 260 // sr, W // sr, 43, sr=sr, precision=em.FP16_SPLIT)
     nv = em._lib.em_variant_count()
     outs = []
     for fv in range(nv):
