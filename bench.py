@@ -168,7 +168,7 @@ def cpu_baseline(prob, crop: int, iters: int, frames: int = 0):
     }
 
 
-def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
+def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0, job_iters=0):
     """Time one precision form on resident inputs; returns a dict of figures.
 
     After the autotuner and `warmup` iterations (which also capture the traced
@@ -198,7 +198,7 @@ def time_form(em, prob, tensors, prec_name, steps, warmup, stream, nu=0.0):
     ctx.iterate(max(warmup, 1))
     ctx.iterate(1, trace=True)
     torch.cuda.synchronize()
-    job_iters = max(prob.n_iter, steps)
+    job_iters = max(job_iters if job_iters > 0 else prob.n_iter, steps)
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
     x.copy_(x_start)
     torch.cuda.synchronize()
@@ -478,6 +478,9 @@ def main() -> int:
                     help="c3 only: further workloads timed after c3 and reported in config "
                          "(comma list of c4, c5; '' for none)")
     ap.add_argument("--leg-jobs", type=int, default=80, help="jobs of the c5 leg of a c3 run")
+    ap.add_argument("--job-iters", type=int, default=0,
+                    help="iterations of each timed job (0 = the workload's count; shorter "
+                         "jobs for profiler runs)")
     ap.add_argument("--slots", type=int, default=16, help="c5: server slots")
     ap.add_argument("--serve-budget-gib", type=float, default=64.0, help="c5: HBM budget")
     ap.add_argument("--serve-precision", default="fp16split", choices=["fp16split", "bf16split"],
@@ -564,7 +567,8 @@ def main() -> int:
     res = {}
     for fm in forms:
         log(f"timing {fm}")
-        res[fm] = time_form(em, prob, tensors, fm, args.steps, args.warmup, stream, nu)
+        res[fm] = time_form(em, prob, tensors, fm, args.steps, args.warmup, stream, nu,
+                            args.job_iters)
     head = res[forms[0]]
     n, hf, wf = tensors[0].shape
     cfg = {
@@ -600,7 +604,8 @@ def main() -> int:
         r4 = {}
         for fm in forms:
             log(f"timing c4 {fm}")
-            r4[fm] = time_form(em, p4, t4, fm, args.steps, args.warmup, stream)
+            r4[fm] = time_form(em, p4, t4, fm, args.steps, args.warmup, stream,
+                               job_iters=args.job_iters)
         del t4
         torch.cuda.synchronize()
         torch.cuda.empty_cache()

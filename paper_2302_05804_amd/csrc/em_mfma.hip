@@ -63,6 +63,13 @@ struct MfCfg {
   static constexpr int NTF = MMAX * 2 * NB;     // Toeplitz fragments of one class
   static constexpr int RFULL = KT - 16 * (MMAX - 1);     // classes with MMAX members
   static constexpr int RLAST = (MMAX == 1) ? KT : 16;    // number of classes
+  // FP16 split, K = 43: the lo part of the PSF enters only on the 21 kernel rows
+  // within 10 of the centre (rows 11..31: member 1 of the three-member classes
+  // r <= 10, both members of the classes r >= 11), where a PSF keeps its core;
+  // elsewhere the binary16 hi part alone carries each tap (relative error
+  // 2^-11, the image operand's own).  Bit m of lo_mask(NM): member m takes lo.
+  static constexpr bool BAND = PREC_ == EM_FP16_SPLIT && KT_ == 43;
+  static constexpr int lo_mask(int nm) { return !BAND ? 7 : (nm == 3 ? 2 : 3); }
 };
 
 // LDS staging buffers of the Toeplitz fragments (PFT = 2): two classes, NTF
@@ -112,6 +119,7 @@ __device__ inline void mfma_class(int r, const unsigned short (*sh)[C::ROWS * C:
                                   int col_base, f32x4 (&acc)[C::BR][C::BC]) {
   const int i = threadIdx.x & 15;
   constexpr int NRHO = C::BR + NM - 1;
+  constexpr int LOM = C::lo_mask(NM);
   typename C::frag A[C::PFA ? 2 : 1][C::BC + 2][C::NA];
   if (C::PFA) load_A<C>(A[0], sh, row_base + r + i, col_base);
 #pragma unroll
@@ -131,6 +139,7 @@ __device__ inline void mfma_class(int r, const unsigned short (*sh)[C::ROWS * C:
         for (int m = 0; m < NM; ++m) {
           const int beta = rho - m;
           if (beta < 0 || beta >= C::BR) continue;
+          if (C::P::pb(s) == 1 && !((LOM >> m) & 1)) continue;   // no lo term on this row
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int gam = kap - 2 * h;

@@ -8,9 +8,12 @@ products accumulate in FP32 and the epilogue removes both scales exactly.
 Error model of one output o = sum_k g_k v_k: rounding each v_k to 11
 significant bits moves it by at most 2^-11 |v_k| (values down to 2^-29 of the
 tile maximum are normal binary16 numbers); the hi + lo PSF is exact to about
-2^-22; products of binary16 numbers are exact in FP32 and the FP32 sums add a
-few 2^-24.  The operator tests therefore bound |o_gpu - o| by
-6e-4 * sum_k |g_k||v_k| element by element (the oracle on absolute values).
+2^-22 on the kernel rows that take the lo part (sr = 1, K = 43: the 21 rows
+within 10 of the centre; every row otherwise), and the hi part alone is within
+2^-11 |g_k| on the others; products of binary16 numbers are exact in FP32 and
+the FP32 sums add a few 2^-24.  The operator tests therefore bound
+|o_gpu - o| by 1e-3 * sum_k |g_k||v_k| element by element (the oracle on
+absolute values; 2^-11 + 2^-11 < 1e-3).
 Whole EM runs must stay within rel L2 1e-3 of the oracle's iterate, the bar of
 the mixed-precision forms.
 """
@@ -23,7 +26,7 @@ from tests.gpu_common import gpu_run, log, rel_l2, to_dev
 
 pytestmark = pytest.mark.gpu
 
-OP16_EPS = 6e-4
+OP16_EPS = 1e-3
 X_TOL = 1e-3
 
 
