@@ -77,7 +77,14 @@ struct M2F {
   static constexpr int ROWS = 2 * TH + M2_KC - 2;                   // latent rows staged
   static constexpr int COLS = 2 * TW + 64;                          // latent cols staged
   static constexpr int PITCH = mf_pitch(COLS, 2);   // fragment rows are 2 apart
+  // FP16 split: the lo part of the PSF on the 22 rows a = 11..32 of the 44-row
+  // box-extended kernel only (the core; the hi part alone elsewhere)
+  static constexpr bool BAND = PREC_ == EM_FP16_SPLIT;
 };
+
+// kernel rows of the 44 x 44 box-extended kernel that take the PSF's lo part
+// in the FP16 split form
+__host__ __device__ constexpr bool m2_lo_row(int a) { return a >= 11 && a <= 32; }
 
 template <class C>
 __device__ inline void m2f_load_T(typename C::frag (&T)[2][M2_FCH][C::NB],
@@ -92,8 +99,9 @@ __device__ inline void m2f_load_T(typename C::frag (&T)[2][M2_FCH][C::NB],
         T[m][h][s] = tab_t[(((r + 32 * m) * M2_FCH + h) * 2 + s) * 64 + lane];
 }
 
-// one tap class a = r + 32 m (m < NM)
-template <class C, int NM>
+// one tap class a = r + 32 m (m < NM); member m takes the PSF's lo part when
+// bit m of LOM is set
+template <class C, int NM, int LOM = 3>
 __device__ inline void m2f_class(int r, const unsigned short (*sh)[C::ROWS * C::PITCH],
                                  const typename C::frag (&T)[2][M2_FCH][C::NB], int row_base,
                                  int col_base, f32x4 (&acc)[C::BR][C::BC]) {
@@ -120,6 +128,7 @@ __device__ inline void m2f_class(int r, const unsigned short (*sh)[C::ROWS * C::
         for (int m = 0; m < NM; ++m) {
           const int beta = rho - m;
           if (beta < 0 || beta >= C::BR) continue;
+          if (C::P::pb(s) == 1 && !((LOM >> m) & 1)) continue;   // no lo term on this row
 #pragma unroll
           for (int h = 0; h < M2_FCH; ++h) {
             const int gam = kap - h;
@@ -176,7 +185,26 @@ __device__ inline void m2f_frame_lds(const unsigned short (*sh)[C::ROWS * C::PIT
           for (int q = 0; q < C::NB; ++q)
             if (m < nm) Tc[m][h][q] = tl[cur][(m * M2_FCH + h) * C::NB + q][lane];
     };
-    if (r < M2_KC - 32) {
+    if constexpr (C::BAND) {
+      // rows r and r + 32 against the lo band 11..32: r = 0 -> (no, yes);
+      // 1..10 -> (no, no); 11 -> (yes, no); 12..31 -> (yes)
+      static_assert(!m2_lo_row(0) && m2_lo_row(32) && !m2_lo_row(10) && !m2_lo_row(42) &&
+                        m2_lo_row(11) && !m2_lo_row(43) && m2_lo_row(12) && m2_lo_row(31),
+                    "class segments follow the lo band");
+      if (r == 0) {
+        read_T(2);
+        m2f_class<C, 2, 2>(r, sh, Tc, row_base, col_base, acc);
+      } else if (r < 11) {
+        read_T(2);
+        m2f_class<C, 2, 0>(r, sh, Tc, row_base, col_base, acc);
+      } else if (r == 11) {
+        read_T(2);
+        m2f_class<C, 2, 1>(r, sh, Tc, row_base, col_base, acc);
+      } else {
+        read_T(1);
+        m2f_class<C, 1, 1>(r, sh, Tc, row_base, col_base, acc);
+      }
+    } else if (r < M2_KC - 32) {
       read_T(2);
       m2f_class<C, 2>(r, sh, Tc, row_base, col_base, acc);
     } else {
@@ -278,6 +306,7 @@ struct M2A {
   static constexpr int ROWS = THL / 2 + 32;
   static constexpr int COLS = TWL / 2 + 24;                         // frame cols staged
   static constexpr int PITCH = mf_pitch(COLS);
+  static constexpr bool BAND = PREC_ == EM_FP16_SPLIT;   // as for M2F
 };
 
 // Toeplitz fragments of adjoint class r: T[q][m] for alpha = r - q + 16 m.
@@ -339,6 +368,8 @@ __device__ inline void m2a_class(const unsigned short (*sh)[C::ROWS * C::PITCH],
             if (beta < 0 || beta >= C::BR) continue;
             const int al = R - q + 16 * m;
             if (al < 0 || al >= 22) continue;
+            // kernel row 2 alpha + q: the PSF's lo part only inside the band
+            if (C::BAND && C::P::pb(s) == 1 && !m2_lo_row(2 * al + q)) continue;
             acc[q][beta][gam] =
                 C::P::mma(A[gam][C::P::pa(s)], T[q][m][C::P::pb(s)], acc[q][beta][gam]);
           }
