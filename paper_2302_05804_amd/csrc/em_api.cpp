@@ -289,6 +289,7 @@ static int adjoint_sum(em_ctx* c, const float* in, float* out) {
     m.fpg = c->pl.adj_fpg;
     m.ntiles = c->pl.adj_tiles;
     m.fused = 0;
+    m.lo_band = c->pl.lo_band;
     EM_HIP(launch_mfma(c->g, 1, c->pl.adj_variant, c->pl.adj_tiles, c->pl.adj_groups, m,
                        c->stream));
   } else {
@@ -327,6 +328,7 @@ void fill_forward_mfma(const em_ctx* c, MfmaLaunch* m, bool write_r, bool loglik
   m->W = c->g.Wf;
   m->fpg = c->pl.fwd_fpg;
   m->ntiles = c->pl.fwd_tiles;
+  m->lo_band = c->pl.lo_band;
 }
 
 void fill_forward_fp32(const em_ctx* c, FwdLaunch* f, bool write_r, bool loglik) {
@@ -361,6 +363,7 @@ void fill_adjoint_mfma(const em_ctx* c, MfmaLaunch* m, double* part_rc) {
   m->B = c->B;
   m->part = fused ? part_rc : nullptr;
   m->plane = c->planes;
+  m->lo_band = c->pl.lo_band;
 }
 
 void fill_adjoint_fp32(const em_ctx* c, AdjLaunch* a, double* part_rc) {
@@ -629,6 +632,18 @@ static int setup_job(em_ctx* c, const em_problem* p, const float* y, const float
   if (uses_r16(g) && (e = launch_r16_setup(g, c->u, psf, c->r16, c->r16_umax, c->r16_fsum,
                                            c->stream)) != hipSuccess)
     return fail(EM_EDEVICE, "r16 planes: %s", hipGetErrorString(e));
+  // BF16 split (sr = 1, K = 43, not served): the lo band when every frame's PSF
+  // keeps at most 1/16 of its mass outside it
+  c->pl.lo_band = 0;
+  if (!serving && g.precision == EM_BF16_SPLIT && g.sr == 1 && g.KT == KT_LARGE) {
+    int over = 1;
+    if ((e = launch_lo_band_check(g, psf, c->counters + 7, c->stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(&over, c->counters + 7, sizeof(int), hipMemcpyDeviceToHost,
+                            c->stream)) != hipSuccess ||
+        (e = hipStreamSynchronize(c->stream)) != hipSuccess)
+      return fail(EM_EDEVICE, "band check: %s", hipGetErrorString(e));
+    c->pl.lo_band = over == 0 ? 1 : 0;
+  }
   if ((rc = adjoint_sum(c, c->r, c->B))) return rc;
   if ((e = launch_finalize_prep(c->part_prep, pl.prep_blocks, c->scalars, g.sr, c->stream)) !=
       hipSuccess)

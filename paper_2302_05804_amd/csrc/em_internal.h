@@ -65,6 +65,7 @@ struct Plan {
   int adj_fpg;
   int adj_fused;       // 1 => update fused into the adjoint (one frame group and
                        // the weights on the frame grid); else partial planes
+  int lo_band;         // BF16 split: PSF lo part on the central kernel rows only
   // reductions
   int prep_blocks;     // blocks of the per-pixel prep kernel
   int upd_blocks;      // blocks of the separate update kernel
@@ -142,7 +143,13 @@ struct MfmaLaunch {
   const int* e16;
   int p16;
   int64_t s16;
+  // BF16 split, K = 43: the PSF's lo part on the central kernel rows only (the
+  // job's PSFs passed the band check at set-up)
+  int lo_band;
 };
+// BF16 split, sr = 1, K = 43: counts in *flag the frames whose PSF keeps more
+// than 1/16 of its mass outside the kernel rows that take the lo part
+hipError_t launch_lo_band_check(const Geometry& g, const float* psf, int* flag, hipStream_t s);
 // binary16 r plane geometry: every adjoint window of 128 x 128 outputs (rows
 // k0 - c .. k0 + 127 + c, columns l0 - c .. l0 + 175 - c) lies inside the plane
 // and starts on a 16-byte boundary.

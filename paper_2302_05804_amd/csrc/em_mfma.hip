@@ -42,7 +42,7 @@ constexpr int MF_TILE = 128;   // every sr = 1 variant covers 128 x 128 outputs
 
 // Tile configuration: each wave owns BR x BC blocks of 16 x 16 outputs, the
 // workgroup WR x WC waves.
-template <int KT_, int PREC_, int BR_, int BC_, int WR_, int WC_, int PFA_, int PFT_>
+template <int KT_, int PREC_, int BR_, int BC_, int WR_, int WC_, int PFA_, int PFT_, int LB_ = -1>
 struct MfCfg {
   using P = Prec<PREC_>;
   using frag = typename P::frag;
@@ -63,12 +63,15 @@ struct MfCfg {
   static constexpr int NTF = MMAX * 2 * NB;     // Toeplitz fragments of one class
   static constexpr int RFULL = KT - 16 * (MMAX - 1);     // classes with MMAX members
   static constexpr int RLAST = (MMAX == 1) ? KT : 16;    // number of classes
-  // FP16 split, K = 43: the lo part of the PSF enters only on the 21 kernel rows
-  // within 10 of the centre (rows 11..31: member 1 of the three-member classes
-  // r <= 10, both members of the classes r >= 11), where a PSF keeps its core;
-  // elsewhere the binary16 hi part alone carries each tap (relative error
-  // 2^-11, the image operand's own).  Bit m of lo_mask(NM): member m takes lo.
-  static constexpr bool BAND = PREC_ == EM_FP16_SPLIT && KT_ == 43;
+  // K = 43, FP16 split (always) or BF16 split (LB_ = 1, for jobs whose PSFs keep
+  // at most 1/16 of their mass outside the band): the lo part of the PSF enters
+  // only on the 21 kernel rows within 10 of the centre (rows 11..31: member 1 of
+  // the three-member classes r <= 10, both members of the classes r >= 11),
+  // where a PSF keeps its core; elsewhere the hi part alone carries each tap
+  // (relative error 2^-11 in binary16, 2^-9 in bf16).  Bit m of lo_mask(NM):
+  // member m takes lo.
+  static constexpr bool BAND =
+      KT_ == 43 && (LB_ < 0 ? PREC_ == EM_FP16_SPLIT : (LB_ == 1 && PREC_ != EM_BF16));
   static constexpr int lo_mask(int nm) { return !BAND ? 7 : (nm == 3 ? 2 : 3); }
 };
 
@@ -806,6 +809,24 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
   } else {
     if (a.r16 != nullptr) return hipErrorInvalidValue;
   }
+  if constexpr (PREC == EM_BF16_SPLIT && KT == 43) {
+    // the BF16 split iteration of a job whose PSFs pass the band check
+    if (a.lo_band && a.out_y == nullptr) {
+      using B0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, PFT, 1>;
+      using B1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, PFT, 1>;
+      using B2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, PFT, 1>;
+      if (dir == 0) {
+        if (variant == 1) hipLaunchKernelGGL(mfma_fwd_kernel<B1>, grid, dim3(B1::NT), 0, s, a);
+        else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_kernel<B2>, grid, dim3(B2::NT), 0, s, a);
+        else hipLaunchKernelGGL(mfma_fwd_kernel<B0>, grid, dim3(B0::NT), 0, s, a);
+      } else {
+        if (variant == 1) hipLaunchKernelGGL(mfma_adj_kernel<B1>, grid, dim3(B1::NT), 0, s, a);
+        else if (variant == 2) hipLaunchKernelGGL(mfma_adj_kernel<B2>, grid, dim3(B2::NT), 0, s, a);
+        else hipLaunchKernelGGL(mfma_adj_kernel<B0>, grid, dim3(B0::NT), 0, s, a);
+      }
+      return hipGetLastError();
+    }
+  }
   if (dir == 0 && a.out_y != nullptr) {
     if (variant == 1) hipLaunchKernelGGL(mfma_fwd_t_kernel<C1>, grid, dim3(C1::NT), 0, s, a);
     else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_t_kernel<C2>, grid, dim3(C2::NT), 0, s, a);
@@ -900,6 +921,41 @@ bool mfma_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaL
 
 int r16_pitch(const Geometry& g) { return MF_TILE * ((g.Wl + MF_TILE - 1) / MF_TILE) + 48; }
 int r16_rows(const Geometry& g) { return MF_TILE * ((g.Hl + MF_TILE - 1) / MF_TILE) + g.KT - 1; }
+
+// Per frame (one block each): counts in *flag the frames whose PSF keeps more
+// than 1/16 of its mass on the kernel rows outside the lo band (rows farther
+// than 10 from the centre of the K-row stamp padded to 43).
+__global__ __launch_bounds__(256) void lo_band_check_kernel(const float* psf, int K, int* flag) {
+  __shared__ double red[2][4];
+  const int t = blockIdx.x, off = (43 - K) / 2;
+  const float* f = psf + (int64_t)t * K * K;
+  double all = 0.0, outside = 0.0;
+  for (int i = threadIdx.x; i < K * K; i += 256) {
+    const double v = (double)f[i];
+    const int a = i / K + off;
+    all += v;
+    if (a < 11 || a > 31) outside += v;
+  }
+  for (int o = 32; o > 0; o >>= 1) {
+    all += __shfl_xor(all, o, 64);
+    outside += __shfl_xor(outside, o, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = all;
+    red[1][threadIdx.x >> 6] = outside;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double A = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    const double O = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    if (!(16.0 * O <= A)) atomicAdd(flag, 1);
+  }
+}
+
+hipError_t launch_lo_band_check(const Geometry& g, const float* psf, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(lo_band_check_kernel, dim3(g.n), dim3(256), 0, s, psf, g.K, flag);
+  return hipGetLastError();
+}
 
 // Zero the r16 planes (16 bytes per thread).
 __global__ __launch_bounds__(256) void r16_clear_kernel(uint4* p, int64_t count) {

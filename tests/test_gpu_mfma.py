@@ -232,3 +232,40 @@ def test_sr2_autotune_then_iterate_matches_oracle():
     log(f"sr2 autotuned (fwd {f}, adj {a}): rel L2 {err:.2e}")
     assert err <= SPLIT_X_TOL
     ctx.close()
+
+
+def test_split_iteration_keeps_full_lo_for_broad_psf():
+    """The BF16 split iteration drops the PSF's lo part outside the 21 central
+    kernel rows only for jobs whose every PSF keeps at most 1/16 of its mass
+    outside them.  Here frame 2 is flat over the 43 x 43 stamp (51% of its mass
+    outside) and every tap's lo part is 0.99 * 2^-8 of its hi part, so dropping
+    it would move B by 6e-4 to 8e-4 relative (frame 2 carries a third of B);
+    with the full lo part (and all operands positive) each element of B stays
+    within 1e-4 of the oracle's and each of Dn within 2e-4 (two operator
+    passes)."""
+    import torch
+    em = _em()
+    n, h, w, K = 3, 150, 141, 43
+    rng = np.random.default_rng(44)
+    a = np.arange(K) - K // 2
+    g = np.exp(-(a[:, None] ** 2 + a[None, :] ** 2) / 8.0)
+    psf = np.empty((n, K, K), np.float32)
+    psf[0] = g / g.sum()
+    psf[1] = np.roll(g, (1, -2), (0, 1)) / g.sum()
+    psf[2] = np.float32(2.0 ** -11 * (1.0 + 0.99 * 2.0 ** -8))
+    y = rng.uniform(10.0, 100.0, (n, h, w)).astype(np.float32)
+    v = rng.uniform(1.0, 2.0, (n, h, w)).astype(np.float32)
+    x0 = rng.uniform(5.0, 50.0, (h, w)).astype(np.float32)
+    prob = em.Problem.make(n, h, w, K, precision=em.BF16_SPLIT)
+    x = torch.empty((h, w), dtype=torch.float32, device="cuda")
+    ctx = em.Context(prob, to_dev(y), to_dev(v), to_dev(psf), x, x0=to_dev(x0))
+    B, Dn = ctx.terms()
+    ctx.sync()
+    B, Dn = B.cpu().numpy(), Dn.cpu().numpy()
+    ctx.close()
+    Bo = oracle.numerator(y, v, psf)
+    Dno = oracle.denominator(y, v, psf, x0)
+    eb = float(np.max(np.abs(B - Bo) / Bo))
+    ed = float(np.max(np.abs(Dn - Dno) / Dno))
+    log(f"broad PSF bf16-split terms: max rel err B {eb:.2e}, Dn {ed:.2e}")
+    assert eb <= 1e-4 and ed <= 2e-4
