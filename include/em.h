@@ -69,12 +69,24 @@ extern "C" {
  * log-likelihood and convergence sums always FP64) */
 #define EM_FP32        0    /* FP32 products, FP32 accumulation               */
 #define EM_BF16_SPLIT  1    /* BF16 MFMA, image and PSF split into hi+lo,
-                               three products, FP32 accumulation             */
-#define EM_FP16_SPLIT  2    /* FP16 MFMA: image in binary16 with a power-of-two
-                               scale per staged tile, PSF split into binary16
-                               hi+lo with a power-of-two scale per frame, two
-                               products, FP32 accumulation, scales removed
-                               exactly in the epilogue                       */
+                               three products (hi hi, hi lo, lo hi), FP32
+                               accumulation.  K = 43, sr = 1, not served: when
+                               every frame's PSF keeps at most 1/16 of its
+                               mass outside the 21 kernel rows nearest the
+                               centre (checked at set-up), the taps on the
+                               other rows take the hi hi product alone       */
+#define EM_FP16_SPLIT  2    /* FP16 MFMA: image operand in binary16 with a
+                               power-of-two scale (per staged tile of x; for
+                               the adjoint of an sr = 1 iteration, r written by
+                               the forward in binary16 with a per-frame scale
+                               fixed from a bound on u_t F_t x), PSF split into
+                               binary16 hi+lo with a power-of-two scale per
+                               frame, FP32 accumulation, scales removed exactly
+                               in the epilogue.  Two products (hi, lo) on the
+                               kernel rows near the centre (K = 43: the 21
+                               rows within 10 of it; sr = 2: rows 11..32 of the
+                               44-row stride-2 kernel), the hi part alone on
+                               the others                                    */
 #define EM_BF16        3    /* plain BF16 MFMA (ablation; below 1e-3 accuracy) */
 
 /* placement of the inverse-variance weights, and the noise model */

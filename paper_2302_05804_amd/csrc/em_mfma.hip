@@ -64,12 +64,12 @@ struct MfCfg {
   static constexpr int RFULL = KT - 16 * (MMAX - 1);     // classes with MMAX members
   static constexpr int RLAST = (MMAX == 1) ? KT : 16;    // number of classes
   // K = 43, FP16 split (always) or BF16 split (LB_ = 1, for jobs whose PSFs keep
-  // at most 1/16 of their mass outside the band): the lo part of the PSF enters
-  // only on the 21 kernel rows within 10 of the centre (rows 11..31: member 1 of
-  // the three-member classes r <= 10, both members of the classes r >= 11),
-  // where a PSF keeps its core; elsewhere the hi part alone carries each tap
-  // (relative error 2^-11 in binary16, 2^-9 in bf16).  Bit m of lo_mask(NM):
-  // member m takes lo.
+  // at most 1/16 of their mass outside the band): the lo parts enter only on the
+  // 21 kernel rows within 10 of the centre (rows 11..31: member 1 of the
+  // three-member classes r <= 10, both members of the classes r >= 11), where a
+  // PSF keeps its core; elsewhere each tap is the product of the hi parts alone
+  // (the PSF's relative error 2^-11 in binary16; in bf16 2^-9 for the PSF and
+  // for the image operand each).  Bit m of lo_mask(NM): member m takes lo.
   static constexpr bool BAND =
       KT_ == 43 && (LB_ < 0 ? PREC_ == EM_FP16_SPLIT : (LB_ == 1 && PREC_ != EM_BF16));
   static constexpr int lo_mask(int nm) { return !BAND ? 7 : (nm == 3 ? 2 : 3); }
@@ -142,7 +142,8 @@ __device__ inline void mfma_class(int r, const unsigned short (*sh)[C::ROWS * C:
         for (int m = 0; m < NM; ++m) {
           const int beta = rho - m;
           if (beta < 0 || beta >= C::BR) continue;
-          if (C::P::pb(s) == 1 && !((LOM >> m) & 1)) continue;   // no lo term on this row
+          // outside the band: the hi x hi product alone
+          if ((C::P::pa(s) == 1 || C::P::pb(s) == 1) && !((LOM >> m) & 1)) continue;
 #pragma unroll
           for (int h = 0; h < 2; ++h) {
             const int gam = kap - 2 * h;

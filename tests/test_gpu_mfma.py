@@ -235,9 +235,9 @@ def test_sr2_autotune_then_iterate_matches_oracle():
 
 
 def test_split_iteration_keeps_full_lo_for_broad_psf():
-    """The BF16 split iteration drops the PSF's lo part outside the 21 central
-    kernel rows only for jobs whose every PSF keeps at most 1/16 of its mass
-    outside them.  Here frame 2 is flat over the 43 x 43 stamp (51% of its mass
+    """The BF16 split iteration keeps only the hi x hi product outside the 21
+    central kernel rows, and only for jobs whose every PSF keeps at most 1/16 of
+    its mass outside them.  Here frame 2 is flat over the 43 x 43 stamp (51% of its mass
     outside) and every tap's lo part is 0.99 * 2^-8 of its hi part, so dropping
     it would move B by 6e-4 to 8e-4 relative (frame 2 carries a third of B);
     with the full lo part (and all operands positive) each element of B stays
