@@ -812,11 +812,15 @@ hipError_t launch_dir(int dir, int variant, dim3 grid, const MfmaLaunch& a, hipS
   }
   if constexpr (PREC == EM_BF16_SPLIT && KT == 43) {
     // the BF16 split iteration of a job whose PSFs pass the band check
-    if (a.lo_band && a.out_y == nullptr) {
+    if (a.lo_band) {
       using B0 = MfCfg<KT, PREC, 4, 4, 2, 2, 1, PFT, 1>;
       using B1 = MfCfg<KT, PREC, 4, 2, 2, 4, 0, PFT, 1>;
       using B2 = MfCfg<KT, PREC, 2, 4, 4, 2, 0, PFT, 1>;
-      if (dir == 0) {
+      if (dir == 0 && a.out_y != nullptr) {
+        if (variant == 1) hipLaunchKernelGGL(mfma_fwd_t_kernel<B1>, grid, dim3(B1::NT), 0, s, a);
+        else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_t_kernel<B2>, grid, dim3(B2::NT), 0, s, a);
+        else hipLaunchKernelGGL(mfma_fwd_t_kernel<B0>, grid, dim3(B0::NT), 0, s, a);
+      } else if (dir == 0) {
         if (variant == 1) hipLaunchKernelGGL(mfma_fwd_kernel<B1>, grid, dim3(B1::NT), 0, s, a);
         else if (variant == 2) hipLaunchKernelGGL(mfma_fwd_kernel<B2>, grid, dim3(B2::NT), 0, s, a);
         else hipLaunchKernelGGL(mfma_fwd_kernel<B0>, grid, dim3(B0::NT), 0, s, a);

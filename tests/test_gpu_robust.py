@@ -117,10 +117,12 @@ def test_terms_and_loglik(sr):
 
 
 @pytest.mark.parametrize("sr", [1, 2])
-@pytest.mark.parametrize("prec_name", ["FP32", "FP16_SPLIT"])
+@pytest.mark.parametrize("prec_name", ["FP32", "BF16_SPLIT", "FP16_SPLIT"])
 def test_gaussian_limit_is_bitwise(sr, prec_name):
     """nu = 1e30: every weight is exactly 1 in binary32, so the Student-t
-    iteration reproduces the Gaussian one bit for bit."""
+    iteration reproduces the Gaussian one bit for bit (also the operators: for
+    the BF16 split form at sr = 1 these PSFs pass the band check, and both
+    iterations must take the banded products in the forward and the adjoint)."""
     em = _em()
     p, y, _ = _problem(sr, 7300 + sr, H=64, W=64, n=3)
     x0 = synth.positive_start(p.latent_shape, max(oracle.flat_x0(y, p.v, sr), 0.25), seed=7303)
@@ -190,7 +192,7 @@ def c3_trails():
     return p, y
 
 
-@pytest.mark.parametrize("prec_name", ["FP32", "FP16_SPLIT"])
+@pytest.mark.parametrize("prec_name", ["FP32", "BF16_SPLIT", "FP16_SPLIT"])
 def test_full_size_sampled(prec_name, c3_trails):
     """One Student-t iteration on the c3 workload with trails (33 x 4096^2), in
     the launch configuration the bench uses, at 12 sampled pixels."""
