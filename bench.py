@@ -384,6 +384,7 @@ def serving_bench(args):
         tms = [srv.times(i) for i in ids]
         st = srv.stats()
         ph = srv.phase_seconds()
+        ph["staging"] = srv.staging()
         srv.close()
         lat = np.array([t[2] - t[0] for t in tms])
         return t_end - t_start, lat, st, ph
@@ -437,7 +438,8 @@ def serving_bench(args):
             "capacity_jobs_per_s": round(capacity, 3),
             "saturated_frame_mpix_per_s": round(total_fpix / mk / 1e6, 1),
             "saturated_makespan_s": round(mk, 3),
-            "saturated_worker_seconds": {k: round(v, 3) for k, v in ph.items()},
+            "saturated_worker_seconds": {k: round(v, 3) for k, v in ph.items() if k != "staging"},
+            "saturated_input_staging": ph["staging"],
             "arrival_rate_jobs_per_s": round(rate, 3),
             "p50_latency_ms": round(float(p50) * 1e3, 1),
             "p99_latency_ms": round(float(p99) * 1e3, 1),

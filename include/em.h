@@ -425,6 +425,14 @@ int em_server_stats(em_server* server, int64_t* stats);
  * finishing jobs (final log-likelihood, result copy to the host). */
 int em_server_phase_seconds(em_server* server, double* sec);
 
+/* Host staging of submitted inputs.  The server holds a pinned host area of
+ * a quarter of hbm_budget (at most 2 GiB; none if pinned memory cannot be
+ * allocated); em_submit copies a job's y and v there when it has room, so
+ * that their upload at admission is an asynchronous DMA, else into pageable
+ * memory.  A job's range is freed once its upload has completed.  out[3]:
+ * staging bytes, jobs staged there, jobs staged in pageable memory. */
+int em_server_staging(em_server* server, int64_t* out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,7 +1,10 @@
 // em_server.cpp -- serving loop of libem.so: continuous batching of
 // deconvolution jobs (each one EM run of Eq. (2), arXiv:2302.05804, Sec. 2).
 //
-//  * em_submit copies a job's host inputs and queues it (non-blocking).
+//  * em_submit copies a job's host inputs and queues it (non-blocking): into
+//    the server's pinned host staging area when it has room (the upload at
+//    admission is then a DMA that does not hold up the worker), else into
+//    pageable host memory.
 //  * A worker thread admits queued jobs in arrival order while a slot and
 //    enough of the HBM budget are free.  The budget is one device arena
 //    allocated at em_server_create; every job's inputs, iterate and workspace
@@ -52,7 +55,10 @@ struct Job {
   em_problem prob{};
   Geometry g{};
   int n_iter = 0, done_iter = 0;
-  std::vector<float> y, v, psf;   // host copies until admission
+  std::vector<float> y, v, psf;   // host copies until admission (y and v
+                                  // only when not staged in pinned memory)
+  float *hy = nullptr, *hv = nullptr;   // y and v in the pinned staging area
+  size_t pin_off = 0, pin_len = 0;      // its range there (pin_len 0: none)
   std::vector<float> x_out;       // result
   double loglik = 0.0;
   JobState state = J_QUEUED;
@@ -168,6 +174,12 @@ struct em_server {
   char* arena_base = nullptr;
   size_t budget = 0;
   Arena arena;
+  // pinned host staging of queued jobs' y and v (a quarter of the budget, at
+  // most 2 GiB; none if the allocation fails)
+  char* pin_base = nullptr;
+  size_t pin_bytes = 0;
+  Arena pin_arena;
+  int64_t staged_pinned = 0, staged_pageable = 0;
   int max_slots = 1;
   int round_chunk = 8;
   std::mutex mu;
@@ -415,6 +427,15 @@ int build_round(em_server* S) {
   return EM_OK;
 }
 
+// The job's pinned staging range back to the staging area (lock held).
+void release_job_pinned(em_server* S, Job* j) {
+  if (j->pin_len) {
+    S->pin_arena.release(j->pin_off, j->pin_len);
+    j->pin_len = 0;
+    j->hy = j->hv = nullptr;
+  }
+}
+
 void release_job_device(em_server* S, Job* j) {
   if (j->ctx) {
     em_destroy(j->ctx);
@@ -439,15 +460,23 @@ int admit(em_server* S, Job* j) {
   j->dws = base + ows;
   j->ws_bytes = wsb;
   const size_t fb = (size_t)j->g.n * j->g.Nf * sizeof(float);
-  if (hipMemcpyAsync(j->dy, j->y.data(), fb, hipMemcpyHostToDevice, S->side) != hipSuccess ||
-      hipMemcpyAsync(j->dv, j->v.data(), fb, hipMemcpyHostToDevice, S->side) != hipSuccess ||
+  const float* hy = j->pin_len ? j->hy : j->y.data();
+  const float* hv = j->pin_len ? j->hv : j->v.data();
+  if (hipMemcpyAsync(j->dy, hy, fb, hipMemcpyHostToDevice, S->side) != hipSuccess ||
+      hipMemcpyAsync(j->dv, hv, fb, hipMemcpyHostToDevice, S->side) != hipSuccess ||
       hipMemcpyAsync(j->dpsf, j->psf.data(), j->psf.size() * sizeof(float),
-                     hipMemcpyHostToDevice, S->side) != hipSuccess)
+                     hipMemcpyHostToDevice, S->side) != hipSuccess) {
+    (void)hipStreamSynchronize(S->side);
     return fail(EM_EDEVICE, "input upload");
+  }
   // set-up on the side stream (synchronised inside); the job's rounds start
   // on the round stream after this returns
   const int rc = init_ctx(&j->ctx, &j->prob, j->dy, j->dv, j->dpsf, nullptr, j->dx, j->dws,
                           j->ws_bytes, S->side, true);
+  // every copy from the host buffers has completed (also when the set-up
+  // stopped early) before they, or the job's arena range, are reused
+  if (hipStreamSynchronize(S->side) != hipSuccess && rc == EM_OK)
+    return fail(EM_EDEVICE, "input upload: %s", hipGetErrorString(hipGetLastError()));
   std::vector<float>().swap(j->y);
   std::vector<float>().swap(j->v);
   return rc;
@@ -484,6 +513,7 @@ void admit_queued(em_server* S, std::unique_lock<std::mutex>& lk, std::vector<Jo
     const int rc = admit(S, j);
     S->sec_admit += now_s() - ta;
     lk.lock();
+    release_job_pinned(S, j);
     if (rc != EM_OK) {
       j->err = rc;
       j->errmsg = em_last_error();
@@ -608,7 +638,10 @@ void worker_main(em_server* S) {
     j->state = J_CANCELED;
   }
   S->active.clear();
-  for (Job* j : S->queue) j->state = J_CANCELED;
+  for (Job* j : S->queue) {
+    release_job_pinned(S, j);
+    j->state = J_CANCELED;
+  }
   S->queue.clear();
   S->cv_done.notify_all();
 }
@@ -660,6 +693,14 @@ int em_server_create(em_server** out, size_t hbm_budget, int32_t max_slots, void
   }
   S->budget = hbm_budget;
   S->arena.reset(hbm_budget);
+  S->pin_bytes = std::min(hbm_budget / 4, (size_t)2 << 30) & ~(size_t)255;
+  if (hipHostMalloc(reinterpret_cast<void**>(&S->pin_base), S->pin_bytes,
+                    hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    S->pin_base = nullptr;
+    S->pin_bytes = 0;
+  }
+  S->pin_arena.reset(S->pin_bytes);
   S->max_slots = max_slots;
   S->round_chunk = 8;
   S->worker = std::thread(worker_main, S);
@@ -687,6 +728,7 @@ int em_server_destroy(em_server* S) {
   if (S->d_r16jobs) (void)hipFree(S->d_r16jobs);
   (void)hipStreamSynchronize(S->side);
   (void)hipFree(S->arena_base);
+  if (S->pin_base) (void)hipHostFree(S->pin_base);
   (void)hipStreamDestroy(S->side);
   if (S->own_stream) (void)hipStreamDestroy(S->stream);
   for (auto& kv : S->jobs) delete kv.second;
@@ -709,12 +751,35 @@ int em_submit(em_server* S, const em_problem* p, const float* y_host, const floa
     return fail(EM_ENOMEM, "job needs %zu bytes of HBM, the budget is %zu", total, S->budget);
   Job* j = new (std::nothrow) Job();
   if (!j) return fail(EM_ENOMEM, "host allocation failed");
+  const size_t nf = (size_t)g.n * g.Nf;
+  {
+    std::lock_guard<std::mutex> lk(S->mu);
+    size_t off;
+    if (S->pin_base && S->pin_arena.alloc(al256(2 * nf * sizeof(float)), &off)) {
+      j->pin_off = off;
+      j->pin_len = al256(2 * nf * sizeof(float));
+      S->staged_pinned++;
+    } else {
+      S->staged_pageable++;
+    }
+  }
   try {
-    const size_t nf = (size_t)g.n * g.Nf;
-    j->y.assign(y_host, y_host + nf);
-    j->v.assign(v_host, v_host + nf);
+    if (j->pin_len) {
+      // the range is this job's alone until it is queued below
+      j->hy = reinterpret_cast<float*>(S->pin_base + j->pin_off);
+      j->hv = j->hy + nf;
+      std::memcpy(j->hy, y_host, nf * sizeof(float));
+      std::memcpy(j->hv, v_host, nf * sizeof(float));
+    } else {
+      j->y.assign(y_host, y_host + nf);
+      j->v.assign(v_host, v_host + nf);
+    }
     j->psf.assign(psf_host, psf_host + (size_t)g.n * g.K * g.K);
   } catch (...) {
+    {
+      std::lock_guard<std::mutex> lk(S->mu);
+      release_job_pinned(S, j);
+    }
     delete j;
     return fail(EM_ENOMEM, "host copy of the inputs failed");
   }
@@ -767,6 +832,7 @@ int em_cancel(em_server* S, em_job_id id) {
   Job* j = it->second;
   if (j->state == J_QUEUED) {
     S->queue.erase(std::find(S->queue.begin(), S->queue.end(), j));
+    release_job_pinned(S, j);
     j->state = J_CANCELED;
     j->t_done = now_s();
     S->cv_done.notify_all();
@@ -831,6 +897,15 @@ int em_server_phase_seconds(em_server* S, double* sec) {
   sec[1] = S->sec_build;
   sec[2] = S->sec_rounds;
   sec[3] = S->sec_finish;
+  return EM_OK;
+}
+
+int em_server_staging(em_server* S, int64_t* out) {
+  if (!S || !out) return fail(EM_EINVAL, "NULL argument");
+  std::lock_guard<std::mutex> lk(S->mu);
+  out[0] = (int64_t)S->pin_bytes;
+  out[1] = S->staged_pinned;
+  out[2] = S->staged_pageable;
   return EM_OK;
 }
 

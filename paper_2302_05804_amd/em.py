@@ -99,6 +99,7 @@ _sig = {
                                     ctypes.POINTER(ctypes.c_double)]),
     "em_server_stats": (ctypes.c_int, [_P, _P]),
     "em_server_phase_seconds": (ctypes.c_int, [_P, _P]),
+    "em_server_staging": (ctypes.c_int, [_P, _P]),
     "em_variant_count": (ctypes.c_int, []),
     "em_check_plan": (ctypes.c_int, [ctypes.POINTER(Problem)]),
     "em_set_variants": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32]),
@@ -461,6 +462,13 @@ class Server:
         _check(_lib.em_server_phase_seconds(self._h, sec.ctypes.data_as(_P)),
                "em_server_phase_seconds")
         return dict(zip(["admit", "rebuild", "rounds", "finish"], sec.tolist()))
+
+    def staging(self):
+        """Pinned host staging: its bytes, jobs staged there, jobs staged in
+        pageable memory."""
+        out = np.zeros(3, np.int64)
+        _check(_lib.em_server_staging(self._h, out.ctypes.data_as(_P)), "em_server_staging")
+        return dict(zip(["pinned_bytes", "pinned_jobs", "pageable_jobs"], out.tolist()))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -192,3 +192,45 @@ def test_concurrent_clients_match_one_client_bitwise():
     for k, ((xa, la), res) in enumerate(zip(ref, out)):
         assert res is not None, k
         assert np.array_equal(xa, res[0]) and la == res[1], k
+
+
+
+def test_pinned_and_pageable_staging_bitwise():
+    """A job's inputs go through the server's pinned staging area (a quarter of
+    the budget) when it has room, else through pageable memory; the result is
+    bitwise the same.  Here job A runs (one slot), job B waits behind it holding
+    most of the staging area, so job C is staged in pageable memory; C alone on
+    a fresh server is staged in pinned memory."""
+    import time
+    em = _em()
+    al = lambda b: (b + 255) // 256 * 256
+    pa = synth.make_problem("c1", H=64, W=64, n=4, seed=7)
+    prob_a = em.Problem.make(4, 64, 64, pa.K, precision=em.FP32)
+    pb = synth.make_problem("c2", H=256, W=256, n=12, seed=8)
+    prob_b = em.Problem.make(12, 256, 256, pb.K, precision=em.FP32)
+    for k in (1, 2, 6, 8):            # FP32, BF16 sr = 2, FP16, FP16 Student-t
+        pc, prob_c, it = _jobs()[k]
+        staged = al(pb.y.nbytes + pb.v.nbytes) + al(pc.y.nbytes + pc.v.nbytes)
+        budget = 4 * staged - 1024
+        assert max(em.job_bytes(q) for q in (prob_a, prob_b, prob_c)) <= budget
+        srv = em.Server(budget, max_slots=1)
+        ja = srv.submit(prob_a, pa.y, pa.v, pa.psf, 3000)
+        t0 = time.time()
+        while srv.stats()["active"] == 0:
+            assert time.time() - t0 < 60
+            time.sleep(0.001)
+        srv.submit(prob_b, pb.y, pb.v, pb.psf, 2)
+        jc = srv.submit(prob_c, pc.y, pc.v, pc.psf, it)
+        st_mix = srv.staging()
+        xc, llc = srv.wait(jc)
+        srv.wait(ja)
+        srv.close()
+        srv = em.Server(512 << 20, max_slots=1)
+        xs, lls = srv.wait(srv.submit(prob_c, pc.y, pc.v, pc.psf, it))
+        st_alone = srv.staging()
+        srv.close()
+        log(f"job {pc.name} {pc.latent_shape} sr={pc.sr}: staging in the mix {st_mix}, "
+            f"alone {st_alone}")
+        assert st_mix["pinned_jobs"] == 2 and st_mix["pageable_jobs"] == 1
+        assert st_alone["pinned_jobs"] == 1 and st_alone["pageable_jobs"] == 0
+        assert np.array_equal(xc, xs) and llc == lls
