@@ -82,7 +82,7 @@ KERNEL_FILES = {
     (prec, 1): ["em_mfma.hip", "em_mfma_common.h", "em_device.h"]
     for prec in ("fp16split", "bf16split", "bf16")
 }
-KERNEL_FILES.update({(prec, 2): ["em_mfma2.hip", "em_mfma_common.h", "em_device.h"]
+KERNEL_FILES.update({(prec, 2): ["em_mfma2.hip", "em_mfma2n.hip", "em_mfma_common.h", "em_device.h"]
                      for prec in ("fp16split", "bf16split", "bf16")})
 KERNEL_FILES[("fp32", 1)] = KERNEL_FILES[("fp32", 2)] = ["em_fp32.hip", "em_device.h"]
 

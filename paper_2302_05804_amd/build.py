@@ -19,7 +19,7 @@ LIB = os.path.join(HERE, "libem.so")
 ROOT = os.path.dirname(HERE)
 
 SOURCES = ["em_api.cpp", "em_server.cpp", "em_fp32.hip", "em_elem.hip", "em_mfma.hip", "em_mfma2.hip",
-           "em_psf.hip"]
+           "em_mfma2n.hip", "em_psf.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

@@ -94,7 +94,9 @@ Plan make_plan(const Geometry& g) {
   const int target = uses_mfma(g) ? 512 : 1024;
   pl.fwd_variant = 0;
   const bool mf = uses_mfma(g);
-  if (mf && g.sr == 2)
+  if (uses_m2n(g))
+    pl.fwd_tiles = (int)(cdiv(g.Wf, M2N_TW) * cdiv(g.Hf, M2N_TH));
+  else if (mf && g.sr == 2)
     pl.fwd_tiles = (int)(cdiv(g.Wf, mfma2_fwd_tile_w(g.precision)) *
                          cdiv(g.Hf, mfma2_fwd_tile_h(g.precision)));
   else if (mf)
@@ -104,6 +106,7 @@ Plan make_plan(const Geometry& g) {
   int fg = (int)std::min<int64_t>(g.n, cdiv(target, pl.fwd_tiles));
   fg = std::max(fg, 1);
   pl.fwd_fpg = (int)cdiv(g.n, fg);
+  if (uses_m2n(g)) pl.fwd_fpg = M2N_FPG;   // the frames are the products' N dimension
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.adj_variant = 0;
   if (mf && g.sr == 2)
@@ -148,7 +151,7 @@ Plan make_serving_plan(const Geometry& g) {
   pl.adj_groups = 1;
   pl.adj_fpg = g.n;
   pl.adj_fused = 1;
-  pl.fwd_fpg = std::min(g.n, 4);
+  if (!uses_m2n(g)) pl.fwd_fpg = std::min(g.n, 4);
   pl.fwd_groups = (int)cdiv(g.n, pl.fwd_fpg);
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
   if (uses_mfma(g)) {

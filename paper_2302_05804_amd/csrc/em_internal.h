@@ -186,10 +186,24 @@ hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int 
                         const MfmaLaunch& a, hipStream_t s);
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
                                 const int4* items, int n_items, int grid, hipStream_t s,
-                                bool robust = false);
+                                bool robust = false, bool m2n = false);
 hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                                hipStream_t s);
 size_t mfma2_table_bytes(int n, int dir);
+// sr = 2 FP16 split forward with the frames in the N dimension of the products
+// (em_mfma2n.hip): 16 x 64 frame pixels and 16 frames per workgroup, jobs of at
+// least M2N_MIN_FRAMES frames
+constexpr int M2N_TH = 16, M2N_TW = 64, M2N_FPG = 16, M2N_MIN_FRAMES = 8;
+inline bool uses_m2n(const Geometry& g) {
+  return g.sr == 2 && g.precision == EM_FP16_SPLIT && g.n >= M2N_MIN_FRAMES;
+}
+size_t mfma2n_table_bytes(int n);
+hipError_t launch_mfma2n_table(const Geometry& g, const float* psf, void* tab, hipStream_t s);
+hipError_t launch_mfma2n(const Geometry& g, int variant, int tiles, int groups,
+                         const MfmaLaunch& a, hipStream_t s);
+hipError_t launch_mfma2n_batched(int variant, const MfmaLaunch* descs, const int4* items,
+                                 int n_items, int grid, hipStream_t s, bool robust);
+bool mfma2n_desc_ok(const Geometry& g, int tiles, int groups, const MfmaLaunch& a);
 int mfma2_fwd_tile_h(int precision);
 int mfma2_fwd_tile_w(int precision);
 int mfma2_adj_tile_h(int precision);

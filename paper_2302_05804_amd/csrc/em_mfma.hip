@@ -774,7 +774,7 @@ int mfma_tile_h() { return MF_TILE; }
 int mfma_tile_w() { return MF_TILE; }
 
 size_t mfma_table_bytes(const Geometry& g, int dir) {
-  if (g.sr == 2) return mfma2_table_bytes(g.n, dir);
+  if (g.sr == 2) return dir == 0 && uses_m2n(g) ? mfma2n_table_bytes(g.n) : mfma2_table_bytes(g.n, dir);
   // fragments, then one scale exponent per frame
   return (size_t)g.n * mfma_table_rows(g.KT) * 4 * 64 * 8 * sizeof(uint16_t) +
          (size_t)g.n * sizeof(int);

@@ -664,8 +664,13 @@ hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fw
                                hipStream_t s) {
   auto ker = g.precision == EM_FP16_SPLIT ? m2_table_kernel<EM_FP16_SPLIT>
                                           : m2_table_kernel<EM_BF16_SPLIT>;
-  hipLaunchKernelGGL(ker, dim3(g.n, M2_FROWS), dim3(384), 0, s, psf, g.n, g.K, 0,
-                     static_cast<unsigned short*>(tab_fwd));
+  if (uses_m2n(g)) {
+    const hipError_t e = launch_mfma2n_table(g, psf, tab_fwd, s);
+    if (e != hipSuccess) return e;
+  } else {
+    hipLaunchKernelGGL(ker, dim3(g.n, M2_FROWS), dim3(384), 0, s, psf, g.n, g.K, 0,
+                       static_cast<unsigned short*>(tab_fwd));
+  }
   hipLaunchKernelGGL(ker, dim3(g.n, 2 * M2_AROWS), dim3(384), 0, s, psf, g.n, g.K, 1,
                      static_cast<unsigned short*>(tab_adj));
   return hipGetLastError();
@@ -736,6 +741,7 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
 
 // forward descriptors carry the frame grid, adjoint descriptors the latent grid
 bool mfma2_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
+  if (dir == 0 && uses_m2n(g)) return mfma2n_desc_ok(g, tiles, groups, a);
   return dir == 0
       ? (a.H == g.Hf && a.W == g.Wf &&
          launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W,
@@ -748,6 +754,7 @@ bool mfma2_desc_ok(const Geometry& g, int dir, int tiles, int groups, const Mfma
 hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int groups,
                         const MfmaLaunch& a, hipStream_t s) {
   if (!mfma2_desc_ok(g, dir, tiles, groups, a)) return hipErrorInvalidValue;
+  if (dir == 0 && uses_m2n(g)) return launch_mfma2n(g, variant, tiles, groups, a, s);
   dim3 grid(tiles, groups);
   switch (g.precision) {
     case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, grid, false, a, nullptr, nullptr, 0, s);
@@ -759,8 +766,12 @@ hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int 
 
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
                                 const int4* items, int n_items, int grid, hipStream_t s,
-                                bool robust) {
+                                bool robust, bool m2n) {
   if (n_items <= 0) return hipSuccess;
+  if (m2n) {
+    if (precision != EM_FP16_SPLIT || dir != 0) return hipErrorInvalidValue;
+    return launch_mfma2n_batched(variant, descs, items, n_items, grid, s, robust);
+  }
   MfmaLaunch dummy{};
   switch (precision) {
     case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);

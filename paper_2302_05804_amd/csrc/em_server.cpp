@@ -127,6 +127,7 @@ struct Family {
   int sr = 1, KT = 43, precision = EM_FP32, fvar = 0, avar = 0;
   bool robust = false;  // Student-t noise: E-step weights in the forward, numerator adjoint
   bool r16 = false;     // FP16 split, sr = 1, Gaussian: r through binary16 planes
+  bool m2n = false;     // FP16 split, sr = 2: forward with the frames in the N dimension
   std::vector<FwdLaunch> fwd32;
   std::vector<AdjLaunch> adj32, adjB32;
   std::vector<MfmaLaunch> fwdmf, adjmf, adjBmf;
@@ -239,15 +240,17 @@ int build_round(em_server* S) {
     const int kind = uses_mfma(c->g) ? 1 : 0;
     const bool robust = c->g.weight_mode == EM_W_STUDENT_T;
     const bool r16 = uses_r16(c->g);
+    const bool m2n = uses_m2n(c->g);
     for (auto& f : S->fams)
       if (f.kind == kind && f.sr == c->g.sr && f.KT == c->g.KT && f.precision == c->g.precision &&
           f.fvar == c->pl.fwd_variant && f.avar == c->pl.adj_variant && f.robust == robust &&
-          f.r16 == r16)
+          f.r16 == r16 && f.m2n == m2n)
         return f;
     Family f;
     f.kind = kind;
     f.robust = robust;
     f.r16 = r16;
+    f.m2n = m2n;
     f.sr = c->g.sr;
     f.KT = c->g.KT;
     f.precision = c->g.precision;
@@ -370,7 +373,7 @@ int build_round(em_server* S) {
     const int n = (int)f.fitems.size();
     if (f.kind == 1 && f.sr == 2) {
       e = launch_mfma2_batched(f.precision, 0, f.fvar, static_cast<const MfmaLaunch*>(f.d_fdesc),
-                               f.d_fitems, n, std::min(n, 512), S->stream, f.robust);
+                               f.d_fitems, n, std::min(n, 512), S->stream, f.robust, f.m2n);
     } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 0, f.fvar,
                               static_cast<const MfmaLaunch*>(f.d_fdesc), f.d_fitems, n,

@@ -63,7 +63,7 @@ def test_launch_plans_match_their_grids():
     import itertools
     sizes = [(1, 1), (3, 2), (17, 130), (64, 64), (65, 129), (128, 128), (257, 1023),
              (1024, 1024), (2048, 2048), (4096, 4096)]
-    for (h, w), n, k, sr, prec in itertools.product(sizes, (1, 3, 33), (1, 15, 43), (1, 2),
+    for (h, w), n, k, sr, prec in itertools.product(sizes, (1, 3, 8, 16, 33), (1, 15, 43), (1, 2),
                                                      (em.FP32, em.BF16_SPLIT, em.FP16_SPLIT, em.BF16)):
         em.check_plan(em.Problem.make(n, h, w, k, sr=sr, precision=prec))
     # the typeset weighting (sr = 1): one frame per adjoint group, never fused

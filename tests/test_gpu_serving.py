@@ -36,6 +36,8 @@ def _jobs():
         ("c2", 112, 96, 3, 1, em.FP16_SPLIT, 6, 4.0),     # Student-t jobs, with trails
         ("c4", 96, 112, 2, 2, em.FP32, 5, 3.0),
         ("c3", 96, 80, 2, 1, em.BF16_SPLIT, 4, 2.5),
+        ("c4", 96, 144, 12, 2, em.FP16_SPLIT, 5, 0.0),    # sr = 2, frames in N
+        ("c4", 64, 96, 9, 2, em.FP16_SPLIT, 4, 3.0),
     ]
     out = []
     for k, (rec, H, W, n, sr, prec, it, nu) in enumerate(specs):
