@@ -144,6 +144,9 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
         if (need) Gn[f] = m2n_ldB(tab, p + 1, f);
       }
     }
+    // keep these loads ahead of this step's products (the scheduler would
+    // otherwise sink them next to their first use, exposing their latency)
+    __builtin_amdgcn_sched_barrier(0);
     // products of pair p; consecutive products write different accumulators
 #pragma unroll
     for (int kind = 0; kind < 6; ++kind) {
@@ -321,11 +324,11 @@ __global__ __launch_bounds__(384) void m2n_table_kernel(const float* psf, int n,
 }
 
 // variants: 0: 8 waves (2 x 4) of 8 rows x 1 block; 1: 8 waves (4 x 2) of 4 rows
-// x 2 blocks; 2: 16 waves (4 x 4) of 4 rows x 1 block.  Every variant covers
+// x 2 blocks; 2: 8 waves (8 x 1) of 2 rows x 4 blocks.  Every variant covers
 // 16 x 64 frame pixels.
 using N0 = M2N<8, 1, 2, 4>;
 using N1 = M2N<4, 2, 4, 2>;
-using N2 = M2N<4, 1, 4, 4>;
+using N2 = M2N<2, 4, 8, 1>;
 static_assert(N0::TH == M2N_TH && N0::TW == M2N_TW && N1::TH == M2N_TH && N1::TW == M2N_TW &&
                   N2::TH == M2N_TH && N2::TW == M2N_TW,
               "tile");
