@@ -189,6 +189,12 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
   float* oyt = ROB ? a.out_y + (int64_t)tc * N : nullptr;
   const bool want_ll = a.part != nullptr;
   const float nu = a.nu, nu1 = a.nu + 1.f;
+  // four consecutive pixels per lane and block: 16-byte accesses when rows and
+  // bases allow (frame width a multiple of 4, 16-byte aligned planes)
+  const bool al =
+      (a.W & 3) == 0 &&
+      ((reinterpret_cast<uintptr_t>(ut) | reinterpret_cast<uintptr_t>(yt) |
+        reinterpret_cast<uintptr_t>(ot) | reinterpret_cast<uintptr_t>(oyt)) & 15) == 0;
   double llp = 0.0;
 #pragma unroll
   for (int b = 0; b < C::BR; ++b) {
@@ -196,43 +202,65 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
 #pragma unroll
     for (int c = 0; c < C::BC; ++c) {
       const int Jb = J0 + 16 * (wc * C::BC + c) + 4 * gq;
+      const bool vec = al && Jb + 3 < a.W;
       float uu[4], yy[4];
       const int Ic = min(I, a.H - 1);
+      if (vec) {
+        const int64_t o = (int64_t)Ic * a.W + Jb;
+        const float4 u4 = ut ? *reinterpret_cast<const float4*>(ut + o) : make_float4(1.f, 1.f, 1.f, 1.f);
+        const float4 y4 = (ROB || want_ll) ? *reinterpret_cast<const float4*>(yt + o)
+                                           : make_float4(0.f, 0.f, 0.f, 0.f);
+        uu[0] = u4.x; uu[1] = u4.y; uu[2] = u4.z; uu[3] = u4.w;
+        yy[0] = y4.x; yy[1] = y4.y; yy[2] = y4.z; yy[3] = y4.w;
+      } else {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t o = (int64_t)Ic * a.W + min(Jb + v, a.W - 1);
-        uu[v] = ut ? ut[o] : 1.f;
-        yy[v] = (ROB || want_ll) ? yt[o] : 0.f;
+        for (int v = 0; v < 4; ++v) {
+          const int64_t o = (int64_t)Ic * a.W + min(Jb + v, a.W - 1);
+          uu[v] = ut ? ut[o] : 1.f;
+          yy[v] = (ROB || want_ll) ? yt[o] : 0.f;
+        }
       }
       if (!tv || I >= a.H) continue;
+      float ro[4], ryo[4];
 #pragma unroll
       for (int v = 0; v < 4; ++v) {
-        const int J = Jb + v;
-        if (J >= a.W) continue;
         const float m = ldexpf(acc[b][c][v], unscale);
         const float u = uu[v];
-        const int64_t o = (int64_t)I * a.W + J;
+        const bool in = Jb + v < a.W;
         if constexpr (ROB) {
-          float ro = 0.f, ryo = 0.f;
+          ro[v] = 0.f;
+          ryo[v] = 0.f;
           if (u > 0.f) {
             const float y = yy[v];
             const float d = y - m;
             const float wgt = nu1 / (nu + u * d * d);
-            ro = (u * wgt) * m;
-            ryo = (u * wgt) * y;
-            if (want_ll) {
+            ro[v] = (u * wgt) * m;
+            ryo[v] = (u * wgt) * y;
+            if (want_ll && in) {
               const double dd = (double)y - (double)m;
               llp += ((double)nu + 1.0) * log1p((double)u * dd * dd / (double)nu) - a.lcst;
             }
           }
-          ot[o] = ro;
-          oyt[o] = ryo;
         } else {
-          if (ot) ot[o] = ut ? u * m : m;
-          if (want_ll && u > 0.f) {
+          ro[v] = ut ? u * m : m;
+          ryo[v] = 0.f;
+          if (want_ll && in && u > 0.f) {
             const double d = (double)yy[v] - (double)m;
             llp += (double)u * d * d;
           }
+        }
+      }
+      const int64_t o = (int64_t)I * a.W + Jb;
+      if (vec) {
+        if (ot) *reinterpret_cast<float4*>(ot + o) = make_float4(ro[0], ro[1], ro[2], ro[3]);
+        if constexpr (ROB)
+          *reinterpret_cast<float4*>(oyt + o) = make_float4(ryo[0], ryo[1], ryo[2], ryo[3]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          if (Jb + v >= a.W) continue;
+          if (ot) ot[o + v] = ro[v];
+          if constexpr (ROB) oyt[o + v] = ryo[v];
         }
       }
     }
