@@ -7,9 +7,10 @@ weighting, adjoint correlation, sum over frames and the multiplicative update.
 Inputs are synthetic, seeded, and resident in HBM before timing starts.
 
 Default: the HSC-shaped workload (33 frames of 4096^2, 43x43 PSFs) timed in
-the FP16 split matrix-core form (binary16 image with a power-of-two tile scale
-times a binary16 hi+lo PSF; the reported value), in the BF16 hi+lo split form
-and in plain FP32 on the same data.  Each form runs the whole 100-iteration
+the FP16 split matrix-core form (binary16 image operand with power-of-two
+scales times a binary16 hi+lo PSF whose lo part enters on the kernel rows
+near the centre; the reported value), in the BF16 hi+lo split form and in
+plain FP32 on the same data.  Each form runs the whole 100-iteration
 job from the flat start; the reported value is its last --steps iterations,
 and the whole job, untraced and with the FP64 log-likelihood traced every
 iteration, is reported beside it.  The default run then times two more legs
