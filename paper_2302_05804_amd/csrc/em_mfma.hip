@@ -228,16 +228,19 @@ __device__ inline void issue_T(const typename C::frag* __restrict__ tab_t, int r
 }
 
 template <class C>
-__device__ inline void issue_u(const UPre& u, int r) {
+__device__ inline int issue_u(const UPre& u, int r) {
   static_assert(C::RLAST >= 14, "the copy needs tap classes 1..13");
-  issue_u_tile<C::TH, C::TW, C::NW>(u, r);
+  return issue_u_tile<C::TH, C::TW, C::NW>(u, r);
 }
 
 // One tap class with the Toeplitz fragments staged in LDS: start the copy of
 // the next class (the first class of tab_next after the last one, if any) into
 // the other buffer, read this class's fragments from LDS, issue its products,
-// then wait for this wave's copies and meet the other waves at a barrier, after
-// which the next buffer is complete and this one free.
+// then wait for this wave's fragment copies and meet the other waves at a
+// barrier, after which the next buffer is complete and this one free.  The
+// weight copies issued after the fragment copies may stay in flight into the
+// next class (a wave's loads complete in issue order); the classes without a
+// weight copy wait for everything, so the copies have landed by the epilogue.
 template <class C, int NM>
 __device__ inline void mfma_class_lds(int r, const unsigned short (*sh)[C::ROWS * C::PITCH],
                                       const typename C::frag* __restrict__ tab_t,
@@ -248,7 +251,7 @@ __device__ inline void mfma_class_lds(int r, const unsigned short (*sh)[C::ROWS 
   const int cur = step & 1;
   if (r + 1 < C::RLAST) issue_T<C>(tab_t, r + 1, (void*)&tl[cur ^ 1][0][0]);
   else if (tab_next != nullptr) issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
-  issue_u<C>(up, r);
+  const int nu = __builtin_amdgcn_readfirstlane(issue_u<C>(up, r));   // wave-uniform
   typename C::frag Tc[C::MMAX][2][C::NB];
 #pragma unroll
   for (int m = 0; m < C::MMAX; ++m)
@@ -257,7 +260,14 @@ __device__ inline void mfma_class_lds(int r, const unsigned short (*sh)[C::ROWS 
 #pragma unroll
       for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = tl[cur][(m * 2 + h) * C::NB + q][lane];
   mfma_class<C, NM>(r, sh, Tc, row_base, col_base, acc);
-  frags_landed();
+  // s_waitcnt vmcnt(nu) lgkmcnt(0)
+  if (nu == 0) __builtin_amdgcn_s_waitcnt(0x0070);
+  else if (nu == 1) __builtin_amdgcn_s_waitcnt(0x0071);
+  else __builtin_amdgcn_s_waitcnt(0x0072);
+  // a bare barrier (a fence here would make the compiler wait for every copy),
+  // and no compiler motion of memory accesses across it
+  __builtin_amdgcn_s_barrier();
+  __asm__ volatile("" ::: "memory");
   ++step;
 }
 

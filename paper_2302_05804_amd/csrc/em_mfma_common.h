@@ -343,21 +343,26 @@ struct UPre {
   float* ub;         // LDS destination
   int k0, l0, H, W;
 };
+// Returns the number of copies this wave issued (at most 2).
 template <int TH, int TW, int NW>
-__device__ inline void issue_u_tile(const UPre& u, int r) {
+__device__ inline int issue_u_tile(const UPre& u, int r) {
   static_assert(256 % TW == 0, "a 1 KB chunk holds whole tile rows");
   constexpr int NCH = TH * TW / 256;         // 1 KB chunks of the tile
   constexpr int CPC = (NCH + 12) / 13;       // chunks per class, classes 1..13
+  static_assert(CPC <= 2 * NW, "at most two copies per wave and class");
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (u.ut == nullptr || r < 1 || r > 13) return;
+  if (u.ut == nullptr || r < 1 || r > 13) return 0;
   const int end = min(r * CPC, NCH);
+  int issued = 0;
   for (int ch = (r - 1) * CPC + w; ch < end; ch += NW) {
     const int e = ch * 256 + 4 * lane;
     const int gy = min(u.k0 + e / TW, u.H - 1), gx = min(u.l0 + e % TW, u.W - 4);
     __builtin_amdgcn_global_load_lds(
         (__attribute__((address_space(1))) void*)(u.ut + (int64_t)gy * u.W + gx),
         (__attribute__((address_space(3))) void*)(u.ub + ch * 256), 16, 0, 0);
+    ++issued;
   }
+  return issued;
 }
 
 // Forward epilogue with u already in LDS (ub: the tile's TH x TW weights, row-major
