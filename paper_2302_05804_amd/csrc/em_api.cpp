@@ -852,10 +852,19 @@ int em_check_plan(const em_problem* p) {
           apply_r16(&c, &a16, 1);
           if (!mfma_desc_ok(g, 1, pl.adj_tiles, pl.adj_groups, a16))
             return fail(EM_EINVAL, "%s: r16 adjoint descriptor does not match", what);
-          // every window of every tile inside its plane
-          const int64_t last_row = (int64_t)((g.Hl + 127) / 128 - 1) * 128 + 127 + g.KT - 1;
-          const int64_t last_col = (int64_t)((g.Wl + 127) / 128 - 1) * 128 + 175;
+          // every window of every tile, and every pixel the forward writes,
+          // inside its plane
+          int64_t last_row, last_col;
+          if (g.sr == 2) {
+            const int th = mfma2_adj_tile_h(EM_FP16_SPLIT), tw = mfma2_adj_tile_w(EM_FP16_SPLIT);
+            last_row = (int64_t)((g.Hl + th - 1) / th - 1) * (th / 2) + th / 2 + 31;
+            last_col = (int64_t)((g.Wl + tw - 1) / tw - 1) * (tw / 2) + tw / 2 + 47;
+          } else {
+            last_row = (int64_t)((g.Hl + 127) / 128 - 1) * 128 + 127 + g.KT - 1;
+            last_col = (int64_t)((g.Wl + 127) / 128 - 1) * 128 + 175;
+          }
           if (last_row >= r16_rows(g) || last_col >= r16_pitch(g) || r16_pitch(g) % 8 != 0 ||
+              g.Hf - 1 + r16_off(g) >= r16_rows(g) || g.Wf - 1 + r16_off(g) >= r16_pitch(g) ||
               c.lay.r16stat - c.lay.r16 < (size_t)g.n * r16_rows(g) * r16_pitch(g) * 2)
             return fail(EM_EINVAL, "%s: r16 planes smaller than the windows", what);
         }

@@ -150,14 +150,27 @@ struct MfmaLaunch {
 // BF16 split, sr = 1, K = 43: counts in *flag the frames whose PSF keeps more
 // than 1/16 of its mass outside the kernel rows that take the lo part
 hipError_t launch_lo_band_check(const Geometry& g, const float* psf, int* flag, hipStream_t s);
-// binary16 r plane geometry: every adjoint window of 128 x 128 outputs (rows
-// k0 - c .. k0 + 127 + c, columns l0 - c .. l0 + 175 - c) lies inside the plane
-// and starts on a 16-byte boundary.
-int r16_pitch(const Geometry& g);   // 128 * ceil(W / 128) + 48
-int r16_rows(const Geometry& g);    // 128 * ceil(H / 128) + KT - 1
-// the FP16 split sr = 1 iteration with Gaussian weights runs on binary16 r planes
+// sr = 2 FP16 split forward with the frames in the N dimension of the products
+// (em_mfma2n.hip): 16 x 64 frame pixels and 16 frames per workgroup, jobs of at
+// least M2N_MIN_FRAMES frames
+constexpr int M2N_TH = 16, M2N_TW = 64, M2N_FPG = 16, M2N_MIN_FRAMES = 8;
+inline bool uses_m2n(const Geometry& g) {
+  return g.sr == 2 && g.precision == EM_FP16_SPLIT && g.n >= M2N_MIN_FRAMES;
+}
+// binary16 r plane geometry.  sr = 1: frame pixel (k, l) at plane (k + c, l + c),
+// c = (KT - 1) / 2, so every adjoint window of 128 x 128 outputs (rows k0 - c ..
+// k0 + 127 + c, columns l0 - c .. l0 + 175 - c) lies inside the plane and starts
+// on a 16-byte boundary.  sr = 2: frame pixel (I, J) at plane (I + 11, J + 11),
+// so the window of a 128 x 256 latent tile (96 frame rows of 176 from frame
+// (K0/2 - 11, L0/2 - 11)) starts at plane (K0/2, L0/2).
+int r16_pitch(const Geometry& g);   // sr = 1: 128 ceil(W / 128) + 48; sr = 2: 128 ceil(Wl / 256) + 48
+int r16_rows(const Geometry& g);    // sr = 1: 128 ceil(H / 128) + KT - 1; sr = 2: 64 ceil(Hl / 128) + 32
+int r16_off(const Geometry& g);     // c (sr = 1) or 11 (sr = 2)
+// Gaussian FP16 split iterations run on binary16 r planes: every sr = 1 job, and
+// sr = 2 jobs whose forward has the frames in N
 inline bool uses_r16(const Geometry& g) {
-  return g.precision == EM_FP16_SPLIT && g.sr == 1 && g.weight_mode == EM_W_ADJOINT;
+  return g.precision == EM_FP16_SPLIT && g.weight_mode == EM_W_ADJOINT &&
+         (g.sr == 1 || uses_m2n(g));
 }
 // set-up of the binary16 r planes: zero planes, per-frame max u and sum of the PSF
 hipError_t launch_r16_setup(const Geometry& g, const float* u, const float* psf,
@@ -186,17 +199,10 @@ hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int 
                         const MfmaLaunch& a, hipStream_t s);
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
                                 const int4* items, int n_items, int grid, hipStream_t s,
-                                bool robust = false, bool m2n = false);
+                                bool robust = false, bool m2n = false, bool r16 = false);
 hipError_t launch_mfma2_tables(const Geometry& g, const float* psf, void* tab_fwd, void* tab_adj,
                                hipStream_t s);
 size_t mfma2_table_bytes(int n, int dir);
-// sr = 2 FP16 split forward with the frames in the N dimension of the products
-// (em_mfma2n.hip): 16 x 64 frame pixels and 16 frames per workgroup, jobs of at
-// least M2N_MIN_FRAMES frames
-constexpr int M2N_TH = 16, M2N_TW = 64, M2N_FPG = 16, M2N_MIN_FRAMES = 8;
-inline bool uses_m2n(const Geometry& g) {
-  return g.sr == 2 && g.precision == EM_FP16_SPLIT && g.n >= M2N_MIN_FRAMES;
-}
 size_t mfma2n_table_bytes(int n);
 hipError_t launch_mfma2n_table(const Geometry& g, const float* psf, void* tab, hipStream_t s);
 hipError_t launch_mfma2n(const Geometry& g, int variant, int tiles, int groups,

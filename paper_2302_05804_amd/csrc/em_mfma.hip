@@ -923,19 +923,34 @@ hipError_t launch_mfma_batched(int KT, int precision, int dir, int variant, cons
 }
 
 bool mfma_desc_ok(const Geometry& g, int dir, int tiles, int groups, const MfmaLaunch& a) {
-  if (g.sr == 2) return a.r16 == nullptr && mfma2_desc_ok(g, dir, tiles, groups, a);
   // r16 planes: the plane geometry the set-up laid out, and the stride between frames
   if (a.r16 != nullptr &&
       (!uses_r16(g) || a.e16 == nullptr || a.p16 != r16_pitch(g) ||
        a.s16 != (int64_t)r16_rows(g) * r16_pitch(g) || a.out_y != nullptr || a.out != nullptr ||
        (dir == 1 && a.in != nullptr)))
     return false;
+  if (g.sr == 2) return mfma2_desc_ok(g, dir, tiles, groups, a);
   return a.H == g.Hl && a.W == g.Wl &&
          launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, MF_TILE, MF_TILE);
 }
 
-int r16_pitch(const Geometry& g) { return MF_TILE * ((g.Wl + MF_TILE - 1) / MF_TILE) + 48; }
-int r16_rows(const Geometry& g) { return MF_TILE * ((g.Hl + MF_TILE - 1) / MF_TILE) + g.KT - 1; }
+int r16_pitch(const Geometry& g) {
+  if (g.sr == 2) {
+    // the FP16 split sr = 2 adjoint's windows: 176 halves from frame column L0/2
+    const int tw = mfma2_adj_tile_w(EM_FP16_SPLIT);
+    return tw / 2 * ((g.Wl + tw - 1) / tw) + 48;
+  }
+  return MF_TILE * ((g.Wl + MF_TILE - 1) / MF_TILE) + 48;
+}
+int r16_rows(const Geometry& g) {
+  if (g.sr == 2) {
+    // 96 frame rows from frame row K0/2
+    const int th = mfma2_adj_tile_h(EM_FP16_SPLIT);
+    return th / 2 * ((g.Hl + th - 1) / th) + 32;
+  }
+  return MF_TILE * ((g.Hl + MF_TILE - 1) / MF_TILE) + g.KT - 1;
+}
+int r16_off(const Geometry& g) { return g.sr == 2 ? 11 : (g.KT - 1) / 2; }
 
 // Per frame (one block each): counts in *flag the frames whose PSF keeps more
 // than 1/16 of its mass on the kernel rows outside the lo band (rows farther
@@ -979,10 +994,13 @@ __global__ __launch_bounds__(256) void r16_clear_kernel(uint4* p, int64_t count)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
-// Per frame (one block each): the largest weight u_t and the sum of f_t.
+// Per frame (one block each): the largest weight u_t and the sum of the absolute
+// taps the forward applies (f_t, or for sr = 2 the 2x2 box-extended kernel,
+// whose sum is fscale = 4 times that of f_t).
 __global__ __launch_bounds__(1024) void r16_frame_stats_kernel(const float* u, int64_t Nf,
                                                                const float* psf, int K,
-                                                               float* umax, float* fsum) {
+                                                               float fscale, float* umax,
+                                                               float* fsum) {
   __shared__ float redm[16];
   __shared__ double reds[16];
   const int t = blockIdx.x;
@@ -990,7 +1008,7 @@ __global__ __launch_bounds__(1024) void r16_frame_stats_kernel(const float* u, i
   float m = 0.f;
   for (int64_t i = threadIdx.x; i < Nf; i += 1024) m = fmaxf(m, ut[i]);
   double sf = 0.0;
-  for (int i = threadIdx.x; i < K * K; i += 1024) sf += (double)psf[(int64_t)t * K * K + i];
+  for (int i = threadIdx.x; i < K * K; i += 1024) sf += fabs((double)psf[(int64_t)t * K * K + i]);
   m = wave_max(m);
   for (int off = 32; off > 0; off >>= 1) sf += __shfl_xor(sf, off, 64);
   if ((threadIdx.x & 63) == 0) {
@@ -1006,7 +1024,7 @@ __global__ __launch_bounds__(1024) void r16_frame_stats_kernel(const float* u, i
       ss += reds[i];
     }
     umax[t] = mm;
-    fsum[t] = (float)ss;
+    fsum[t] = (float)(ss * fscale);
   }
 }
 
@@ -1015,16 +1033,16 @@ __global__ __launch_bounds__(256) void r16_xmax_kernel(const float* x, int64_t N
   __shared__ float red[4];
   float m = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < Nl; i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, x[i]);
+    m = fmaxf(m, fabsf(x[i]));
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
   if (threadIdx.x == 0) part[blockIdx.x] = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
 }
 
-// e16[t]: the power of two that maps the bound 2 max u_t (sum f_t) max x of
-// |u_t F_t x| into [2^14, 2^15) (x >= 0 and f_t >= 0, so 0 <= F_t x <= sum f_t
-// max x; the factor 2 covers the rounding of the matrix-core products), so no
+// e16[t]: the power of two that maps the bound 2 max u_t (sum |f_t|) max |x| of
+// |u_t F_t x| into [2^14, 2^15) (|F_t x| <= sum |f_t| max |x|; the factor 2
+// covers the rounding of the matrix-core products), so no
 // scaled value overflows binary16 and values down to 2^-29 of the bound keep
 // 11 significant bits.
 __global__ __launch_bounds__(256) void r16_scale_kernel(const float* part, int nb,
@@ -1047,7 +1065,7 @@ __global__ __launch_bounds__(256) void r16_xmax_batched_kernel(const R16Job* job
   float m = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < j.Nl;
        i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, j.x[i]);
+    m = fmaxf(m, fabsf(j.x[i]));
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -1081,7 +1099,7 @@ hipError_t launch_r16_setup(const Geometry& g, const float* u, const float* psf,
   hipLaunchKernelGGL(r16_clear_kernel, dim3(std::max(blocks, 1)), dim3(256), 0, s,
                      reinterpret_cast<uint4*>(r16), n16);
   hipLaunchKernelGGL(r16_frame_stats_kernel, dim3(g.n), dim3(1024), 0, s, u, g.Nf, psf, g.K,
-                     umax, fsum);
+                     g.sr == 2 ? 4.f : 1.f, umax, fsum);
   return hipGetLastError();
 }
 

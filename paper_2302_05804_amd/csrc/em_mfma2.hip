@@ -533,6 +533,167 @@ __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int g
 }
 
 // ---------------------------------------------------------------------------
+// adjoint, sr = 2, FP16 split, on binary16 r planes
+// ---------------------------------------------------------------------------
+// The forward with the frames in N writes 2^e16[t] r_t as binary16 into frame
+// t's plane at plane pixel (I + 11, J + 11), zero elsewhere, so the window of a
+// latent tile (ROWS frame rows of PITCH halves from frame (K0/2 - 11, L0/2 - 11),
+// the layout the staged tile has in LDS) is ROWS runs of 2 PITCH bytes starting
+// at plane (K0/2, L0/2) on 16-byte boundaries.  As in the sr = 1 adjoint, the
+// window is copied straight into LDS, the next frame's into the second buffer
+// during the first classes of the current frame, one copy per wave and class;
+// a copy may stay in flight for one more class, since a wave's loads complete in
+// issue order and each class waits only until its newest copy is the one left.
+template <class C>
+struct M2Win {
+  static constexpr int HALVES = C::ROWS * C::PITCH;
+  static constexpr int BYTES = 2 * HALVES;
+  static constexpr int ROW_BYTES = 2 * C::PITCH;
+  static constexpr int NCH = (BYTES + 1023) / 1024;       // 1 KB copies per window
+  static constexpr int CCL = (NCH + C::NW - 1) / C::NW;   // classes that carry copies
+  static_assert(ROW_BYTES % 16 == 0, "16-byte pieces never straddle window rows");
+  static_assert(CCL < 16, "the last class of a frame carries no copy, so its wait completes the window");
+};
+
+template <class C>
+__device__ inline void m2_copy_window_chunk(const unsigned short* __restrict__ plane, int p16,
+                                            int k0, int l0, int ch, unsigned short* dst) {
+  using Wn = M2Win<C>;
+  const int o = ch * 1024 + 16 * (threadIdx.x & 63);
+  if (o < Wn::BYTES) {
+    const int row = o / Wn::ROW_BYTES, cb = o - row * Wn::ROW_BYTES;
+    const char* src =
+        reinterpret_cast<const char*>(plane + (int64_t)(k0 + row) * p16 + l0) + cb;
+    __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src),
+                                     (__attribute__((address_space(3))) void*)(
+                                         reinterpret_cast<char*>(dst) + ch * 1024),
+                                     16, 0, 0);
+  }
+}
+
+// Classes R .. 15 of one frame: this class's fragments are read from LDS before
+// the next class's fragment copy and the window copy are issued (so no wait for
+// those copies lands before the products).
+template <class C, int R>
+__device__ inline void m2a16_classes(const unsigned short (*sh)[C::ROWS * C::PITCH],
+                                     const typename C::frag* __restrict__ tab_t,
+                                     const typename C::frag* __restrict__ tab_next,
+                                     M2TBuf<C>& tl, int& step, int row_base, int col_base,
+                                     f32x4 (&acc)[2][C::BR][C::BC],
+                                     const unsigned short* __restrict__ next_plane, int p16,
+                                     int k0, int l0, unsigned short* next_buf) {
+  if constexpr (R < 16) {
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int cur = step & 1;
+    typename C::frag Tc[2][2][C::NB];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int m = 0; m < 2; ++m)
+#pragma unroll
+        for (int s = 0; s < C::NB; ++s) Tc[q][m][s] = tl[cur][(q * 2 + m) * C::NB + s][lane];
+    if constexpr (R + 1 < 16) m2a_issue_T<C>(tab_t, R + 1, (void*)&tl[cur ^ 1][0][0]);
+    else if (tab_next != nullptr) m2a_issue_T<C>(tab_next, 0, (void*)&tl[cur ^ 1][0][0]);
+    const int ch = R * C::NW + w;
+    const bool copied = next_plane != nullptr && R < M2Win<C>::CCL && ch < M2Win<C>::NCH;
+    if (copied) m2_copy_window_chunk<C>(next_plane, p16, k0, l0, ch, next_buf);
+    m2a_class<C, R>(sh, Tc, row_base, col_base, acc);
+    // s_waitcnt vmcnt(1 or 0) lgkmcnt(0): this class's fragment copies have landed
+    if (copied) __builtin_amdgcn_s_waitcnt(0x0071);
+    else __builtin_amdgcn_s_waitcnt(0x0070);
+    __builtin_amdgcn_s_barrier();
+    ++step;
+    m2a16_classes<C, R + 1>(sh, tab_t, tab_next, tl, step, row_base, col_base, acc, next_plane,
+                            p16, k0, l0, next_buf);
+  }
+}
+
+template <class C>
+__device__ inline void m2a16_body(const MfmaLaunch& a, const int tile, const int group) {
+  static_assert(C::PREC == EM_FP16_SPLIT && C::PFT == 2, "r16 planes feed the FP16 split form");
+  static_assert(C::ROWS == C::THL / 2 + 32 && C::PITCH == C::TWL / 2 + 48,
+                "the window geometry the planes are laid out for (r16_rows, r16_pitch)");
+  using Wn = M2Win<C>;
+  __shared__ __align__(16) unsigned short rb[2][Wn::HALVES];
+  __shared__ double red[2 * C::NW];
+  __shared__ __align__(16) M2TBufDecl<C> tl;
+  const int w = threadIdx.x >> 6;
+  const int wr = w / C::WC, wc = w % C::WC;
+  const int tiles_x = (a.W + C::TWL - 1) / C::TWL;
+  const int tx = tile % tiles_x, ty = tile / tiles_x;
+  const int K0 = ty * C::THL, L0 = tx * C::TWL;     // both even
+  const int64_t Nl = (int64_t)a.H * a.W;
+  const int row_base = wr * 16 * C::BR;             // frame rows (relative to K0/2 - 11)
+  const int col_base = wc * 8 * C::BC;              // frame cols (relative to L0/2 - 11)
+
+  f32x4 acc[2][C::BR][C::BC];
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+#pragma unroll
+    for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+      for (int c2 = 0; c2 < C::BC; ++c2) acc[q][b][c2] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+  const int t0 = group * a.fpg;
+  const int t1 = min(a.n, t0 + a.fpg);
+  const typename C::frag* tab = reinterpret_cast<const typename C::frag*>(a.tab);
+  constexpr int64_t TSTRIDE = (int64_t)2 * M2_AROWS * 2 * 64;   // fragments per frame
+  const int* e_tab = m2_table_exponents(a, M2_ADJ_FRAME_BYTES);
+  int step = 0;
+  // first frame: its window and its first class's fragments, all waves
+  m2a_issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
+  for (int ch = w; ch < Wn::NCH; ch += C::NW)
+    m2_copy_window_chunk<C>(a.r16 + (int64_t)t0 * a.s16, a.p16, K0 / 2, L0 / 2, ch, &rb[0][0]);
+  __builtin_amdgcn_s_waitcnt(0x0070);
+  __builtin_amdgcn_s_barrier();
+  for (int t = t0; t < t1; ++t) {
+    const int buf = (t - t0) & 1;
+    const unsigned short(*sh)[C::ROWS * C::PITCH] =
+        reinterpret_cast<const unsigned short(*)[C::ROWS * C::PITCH]>(&rb[buf][0]);
+    const bool more = t + 1 < t1;
+    const unsigned short* next_plane = more ? a.r16 + (int64_t)(t + 1) * a.s16 : nullptr;
+    const typename C::frag* tab_t = tab + t * TSTRIDE;
+    const typename C::frag* tab_next = more ? tab_t + TSTRIDE : nullptr;
+    f32x4 accf[2][C::BR][C::BC];
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+        for (int c2 = 0; c2 < C::BC; ++c2) accf[q][b][c2] = f32x4{0.f, 0.f, 0.f, 0.f};
+    m2a16_classes<C, 0>(sh, tab_t, tab_next, tl, step, row_base, col_base, accf, next_plane,
+                        a.p16, K0 / 2, L0 / 2, &rb[buf ^ 1][0]);
+    // each frame has its own scales: add it to the total unscaled (exact)
+    const int unscale = -(a.e16[t] + e_tab[t]);
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int b = 0; b < C::BR; ++b)
+#pragma unroll
+        for (int c2 = 0; c2 < C::BC; ++c2)
+#pragma unroll
+          for (int v = 0; v < 4; ++v) acc[q][b][c2][v] += ldexpf(accf[q][b][c2][v], unscale);
+  }
+
+  double dsq = 0.0, xsq = 0.0;
+  float* pl = a.fused ? nullptr : a.plane + (int64_t)group * Nl;
+#pragma unroll
+  for (int q = 0; q < 2; ++q)
+    adjoint_epilogue<C::BR, C::BC>(acc[q],
+                                   BlockPos{K0 + 2 * wr * 16 * C::BR + q, L0 + wc * 16 * C::BC, 2},
+                                   a.H, a.W, a.fused, a.x, a.B, pl, dsq, xsq);
+  if (a.fused && a.part != nullptr) {
+    const double s1 = block_sum<C::NT>(dsq, red);
+    __syncthreads();
+    const double s2 = block_sum<C::NT>(xsq, red + C::NW);
+    if (threadIdx.x == 0) {
+      a.part[2 * tile] = s1;
+      a.part[2 * tile + 1] = s2;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // entry points
 // ---------------------------------------------------------------------------
 template <class C>
@@ -579,6 +740,23 @@ __global__ __launch_bounds__(C::NT) void m2a_batched(const MfmaLaunch* __restric
   for (int it = blockIdx.x; it < n; it += gridDim.x) {
     const int4 w = items[it];
     m2a_item<C>(descs[w.x], w.y, w.z);
+    __syncthreads();
+  }
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void m2a16_kernel(MfmaLaunch a) {
+  m2a16_body<C>(a, blockIdx.x, blockIdx.y);
+}
+template <class C>
+__device__ __attribute__((noinline)) void m2a16_item(const MfmaLaunch d, int tile, int group) {
+  m2a16_body<C>(d, tile, group);
+}
+template <class C>
+__global__ __launch_bounds__(C::NT) void m2a16_batched(const MfmaLaunch* __restrict__ descs,
+                                                       const int4* __restrict__ items, int n) {
+  for (int it = blockIdx.x; it < n; it += gridDim.x) {
+    const int4 w = items[it];
+    m2a16_item<C>(descs[w.x], w.y, w.z);
     __syncthreads();
   }
 }
@@ -694,7 +872,8 @@ namespace {
 // of 4x2; 2: 4 waves of 2x4.
 template <int PREC>
 hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaunch& a,
-                   const MfmaLaunch* d, const int4* it, int n, hipStream_t s, bool robust = false) {
+                   const MfmaLaunch* d, const int4* it, int n, hipStream_t s, bool robust = false,
+                   bool r16 = false) {
   // Toeplitz fragments staged in LDS for the one-plane binary16 image
   constexpr int PFT = PREC == EM_FP16_SPLIT ? 2 : 1;
   constexpr bool H16 = PREC == EM_FP16_SPLIT;
@@ -717,6 +896,17 @@ hipError_t launch2(int dir, int variant, dim3 grid, bool batched, const MfmaLaun
     else                                                                                \
       hipLaunchKernelGGL(KER##_kernel<CFG>, grid, dim3(CFG::NT), 0, s, a);              \
   } while (0)
+  // the adjoint on binary16 r planes (FP16 split)
+  if (dir == 1 && (batched ? r16 : a.r16 != nullptr)) {
+    if constexpr (PREC == EM_FP16_SPLIT) {
+      if (variant == 1) EM_M2_LAUNCH(m2a16, A1);
+      else if (variant == 2) EM_M2_LAUNCH(m2a16, A2);
+      else EM_M2_LAUNCH(m2a16, A0);
+      return hipGetLastError();
+    } else {
+      return hipErrorInvalidValue;
+    }
+  }
   if (dir == 0 && batched && robust) {
     if (variant == 1) hipLaunchKernelGGL(m2f_t_batched<F1>, grid, dim3(F1::NT), 0, s, d, it, n);
     else if (variant == 2) hipLaunchKernelGGL(m2f_t_batched<F2>, grid, dim3(F2::NT), 0, s, d, it, n);
@@ -766,7 +956,7 @@ hipError_t launch_mfma2(const Geometry& g, int dir, int variant, int tiles, int 
 
 hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaLaunch* descs,
                                 const int4* items, int n_items, int grid, hipStream_t s,
-                                bool robust, bool m2n) {
+                                bool robust, bool m2n, bool r16) {
   if (n_items <= 0) return hipSuccess;
   if (m2n) {
     if (precision != EM_FP16_SPLIT || dir != 0) return hipErrorInvalidValue;
@@ -775,7 +965,7 @@ hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaL
   MfmaLaunch dummy{};
   switch (precision) {
     case EM_BF16_SPLIT: return launch2<EM_BF16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);
-    case EM_FP16_SPLIT: return launch2<EM_FP16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);
+    case EM_FP16_SPLIT: return launch2<EM_FP16_SPLIT>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust, r16);
     case EM_BF16: return launch2<EM_BF16>(dir, variant, dim3(grid), true, dummy, descs, items, n_items, s, robust);
     default: return hipErrorInvalidValue;
   }

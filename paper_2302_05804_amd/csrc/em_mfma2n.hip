@@ -30,6 +30,8 @@
 #include "em_internal.h"
 #include "em_mfma_common.h"
 
+#include <type_traits>
+
 namespace em {
 
 namespace {
@@ -60,6 +62,16 @@ struct M2N {
   static constexpr int ROWS = 2 * TH + 42;                 // latent rows staged
   static constexpr int COLS = 2 * TW + 46;                 // latent columns staged
   static constexpr int PITCH = m2n_pitch(COLS);
+  // binary16 r planes: the workgroup's outputs of all 16 frames go through an LDS
+  // staging tile so that most stores are 16-byte runs.  A plane holds output
+  // column J at plane column J + 11, so the runs that start on 16-byte
+  // boundaries begin at output columns J0 + LEAD + 8 j.
+  static constexpr int LEAD = (8 - 11 % 8) % 8;
+  static constexpr int S0 = (8 - LEAD) % 8;        // staging column of output column J0
+  static constexpr int NRUN = (TW - LEAD) / 8;
+  static constexpr int TAIL = TW - LEAD - 8 * NRUN;
+  static constexpr int SP = (S0 + TW + 7) / 8 * 8;  // staging row pitch (halves)
+  static constexpr int FS = TH * SP + 8;            // staging frame stride (halves)
 };
 
 // Eight binary16 values of one latent row of the staged tile, starting at an
@@ -83,6 +95,8 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
   __shared__ __align__(16) unsigned short sh[1][C::ROWS * C::PITCH];
   __shared__ double red[C::NW];
   __shared__ float redf[C::NW];
+  __shared__ __align__(16) std::conditional_t<ROB, unsigned short[8],
+                                              unsigned short[M2N_FPG * C::FS]> stg;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w / C::WC, wc = w % C::WC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;     // a.H, a.W: frame grid
@@ -187,6 +201,10 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
   const float* yt = a.y ? a.y + (int64_t)tc * N : nullptr;
   float* ot = a.out ? a.out + (int64_t)tc * N : nullptr;
   float* oyt = ROB ? a.out_y + (int64_t)tc * N : nullptr;
+  // binary16 r planes (the Gaussian iteration): 2^e16[t] u m at plane pixel
+  // (I + 11, J + 11) instead of r, through the staging tile
+  const bool to16 = !ROB && a.r16 != nullptr;     // uniform over the workgroup
+  const int e16 = to16 ? a.e16[tc] : 0;
   const bool want_ll = a.part != nullptr;
   const float nu = a.nu, nu1 = a.nu + 1.f;
   // four consecutive pixels per lane and block: 16-byte accesses when rows and
@@ -251,6 +269,15 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
         }
       }
       const int64_t o = (int64_t)I * a.W + Jb;
+      if constexpr (!ROB) {
+        if (to16) {
+          unsigned short* srow =
+              &stg[(lane & 15) * C::FS + (I - I0) * C::SP + C::S0 + (Jb - J0)];
+#pragma unroll
+          for (int v = 0; v < 4; ++v) srow[v] = f16_bits((_Float16)ldexpf(ro[v], e16));
+          continue;
+        }
+      }
       if (vec) {
         if (ot) *reinterpret_cast<float4*>(ot + o) = make_float4(ro[0], ro[1], ro[2], ro[3]);
         if constexpr (ROB)
@@ -261,6 +288,40 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
           if (Jb + v >= a.W) continue;
           if (ot) ot[o + v] = ro[v];
           if constexpr (ROB) oyt[o + v] = ryo[v];
+        }
+      }
+    }
+  }
+  if constexpr (!ROB) {
+    if (to16) {
+      __syncthreads();
+      constexpr int SLOTS = C::NRUN + 1;   // per frame row: the runs, then lead and tail
+      for (int e = threadIdx.x; e < M2N_FPG * C::TH * SLOTS; e += C::NT) {
+        const int f = e / (C::TH * SLOTS), rem = e - f * (C::TH * SLOTS);
+        const int rr = rem / SLOTS, j = rem - rr * SLOTS;
+        const int tf = t0 + f, I = I0 + rr;
+        if (tf >= a.n || I >= a.H) continue;
+        unsigned short* prow = a.r16 + (int64_t)tf * a.s16 + (int64_t)(I + 11) * a.p16 + 11;
+        const unsigned short* srow = &stg[f * C::FS + rr * C::SP + C::S0];
+        if (j < C::NRUN) {
+          const int lc = J0 + C::LEAD + 8 * j;
+          if (lc + 7 < a.W) {
+            *reinterpret_cast<uint4*>(prow + lc) =
+                *reinterpret_cast<const uint4*>(srow + C::LEAD + 8 * j);
+          } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i)
+              if (lc + i < a.W) prow[lc + i] = srow[C::LEAD + 8 * j + i];
+          }
+        } else {
+#pragma unroll
+          for (int i = 0; i < C::LEAD; ++i)
+            if (J0 + i < a.W) prow[J0 + i] = srow[i];
+#pragma unroll
+          for (int i = 0; i < C::TAIL; ++i) {
+            const int lc = J0 + C::LEAD + 8 * C::NRUN + i;
+            if (lc < a.W) prow[lc] = srow[C::LEAD + 8 * C::NRUN + i];
+          }
         }
       }
     }
@@ -375,6 +436,7 @@ hipError_t launch_mfma2n_table(const Geometry& g, const float* psf, void* tab, h
 
 bool mfma2n_desc_ok(const Geometry& g, int tiles, int groups, const MfmaLaunch& a) {
   return uses_m2n(g) && a.H == g.Hf && a.W == g.Wf && a.fpg == M2N_FPG &&
+         (a.r16 == nullptr || (a.out == nullptr && a.out_y == nullptr)) &&
          launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2N_TH, M2N_TW);
 }
 

@@ -126,7 +126,7 @@ struct Family {
   int kind = 0;       // 0 = FP32 direct, 1 = matrix core
   int sr = 1, KT = 43, precision = EM_FP32, fvar = 0, avar = 0;
   bool robust = false;  // Student-t noise: E-step weights in the forward, numerator adjoint
-  bool r16 = false;     // FP16 split, sr = 1, Gaussian: r through binary16 planes
+  bool r16 = false;     // FP16 split, Gaussian (sr = 1, or sr = 2 with frames in N): binary16 r planes
   bool m2n = false;     // FP16 split, sr = 2: forward with the frames in the N dimension
   std::vector<FwdLaunch> fwd32;
   std::vector<AdjLaunch> adj32, adjB32;
@@ -406,7 +406,7 @@ int build_round(em_server* S) {
     const int n = (int)f.aitems.size();
     if (f.kind == 1 && f.sr == 2) {
       e = launch_mfma2_batched(f.precision, 1, f.avar, static_cast<const MfmaLaunch*>(f.d_adesc),
-                               f.d_aitems, n, std::min(n, 1024), S->stream);
+                               f.d_aitems, n, std::min(n, 1024), S->stream, false, false, f.r16);
     } else if (f.kind == 1) {
       e = launch_mfma_batched(f.KT, f.precision, 1, f.avar,
                               static_cast<const MfmaLaunch*>(f.d_adesc), f.d_aitems, n,
