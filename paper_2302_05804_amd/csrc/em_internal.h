@@ -150,12 +150,17 @@ struct MfmaLaunch {
 // BF16 split, sr = 1, K = 43: counts in *flag the frames whose PSF keeps more
 // than 1/16 of its mass outside the kernel rows that take the lo part
 hipError_t launch_lo_band_check(const Geometry& g, const float* psf, int* flag, hipStream_t s);
-// sr = 2 FP16 split forward with the frames in the N dimension of the products
-// (em_mfma2n.hip): 16 x 64 frame pixels and 16 frames per workgroup, jobs of at
-// least M2N_MIN_FRAMES frames
-constexpr int M2N_TH = 16, M2N_TW = 64, M2N_FPG = 16, M2N_MIN_FRAMES = 8;
+// sr = 2 split-form forward with the frames in the N dimension of the products
+// (em_mfma2n.hip): 16 x m2n_tile_w frame pixels and 16 frames per workgroup,
+// jobs of at least M2N_MIN_FRAMES frames
+constexpr int M2N_TH = 16, M2N_FPG = 16, M2N_MIN_FRAMES = 8;
+// FP16 split 64; BF16 split 32 (its two image planes double the register window)
+__host__ __device__ constexpr int m2n_tile_w(int precision) {
+  return precision == EM_BF16_SPLIT ? 32 : 64;
+}
 inline bool uses_m2n(const Geometry& g) {
-  return g.sr == 2 && g.precision == EM_FP16_SPLIT && g.n >= M2N_MIN_FRAMES;
+  return g.sr == 2 && (g.precision == EM_FP16_SPLIT || g.precision == EM_BF16_SPLIT) &&
+         g.n >= M2N_MIN_FRAMES;
 }
 // binary16 r plane geometry.  sr = 1: frame pixel (k, l) at plane (k + c, l + c),
 // c = (KT - 1) / 2, so every adjoint window of 128 x 128 outputs (rows k0 - c ..
@@ -207,8 +212,9 @@ size_t mfma2n_table_bytes(int n);
 hipError_t launch_mfma2n_table(const Geometry& g, const float* psf, void* tab, hipStream_t s);
 hipError_t launch_mfma2n(const Geometry& g, int variant, int tiles, int groups,
                          const MfmaLaunch& a, hipStream_t s);
-hipError_t launch_mfma2n_batched(int variant, const MfmaLaunch* descs, const int4* items,
-                                 int n_items, int grid, hipStream_t s, bool robust);
+hipError_t launch_mfma2n_batched(int precision, int variant, const MfmaLaunch* descs,
+                                 const int4* items, int n_items, int grid, hipStream_t s,
+                                 bool robust);
 bool mfma2n_desc_ok(const Geometry& g, int tiles, int groups, const MfmaLaunch& a);
 int mfma2_fwd_tile_h(int precision);
 int mfma2_fwd_tile_w(int precision);

@@ -959,8 +959,8 @@ hipError_t launch_mfma2_batched(int precision, int dir, int variant, const MfmaL
                                 bool robust, bool m2n, bool r16) {
   if (n_items <= 0) return hipSuccess;
   if (m2n) {
-    if (precision != EM_FP16_SPLIT || dir != 0) return hipErrorInvalidValue;
-    return launch_mfma2n_batched(variant, descs, items, n_items, grid, s, robust);
+    if (dir != 0) return hipErrorInvalidValue;
+    return launch_mfma2n_batched(precision, variant, descs, items, n_items, grid, s, robust);
   }
   MfmaLaunch dummy{};
   switch (precision) {

@@ -1,7 +1,7 @@
 // em_mfma2n.hip -- forward convolution of the super-resolution iteration
 // (arXiv:2302.05804, Sec. 2, Eq. (3) inside Eq. (2)) on the matrix cores with
-// the frames in the N dimension of the products: FP16 split form, jobs of at
-// least M2N_MIN_FRAMES frames.
+// the frames in the N dimension of the products: FP16 split and BF16 split
+// forms, jobs of at least M2N_MIN_FRAMES frames.
 //
 // With g_t the flipped 44 x 44 box-extended kernel of frame t (as in
 // em_mfma2.hip),
@@ -22,10 +22,14 @@
 // registers and reads one new pair from LDS per step (each A fragment serves BR
 // output rows).  The B fragments of a pair (hi and lo parts of the three chunks,
 // one binary16 scale per frame) come from a per-group table in global memory,
-// which stays in L2, and each serves BR x BC products.  The staged x tile is
-// binary16 with a power-of-two scale; the epilogue removes both scales exactly.
-// The PSF's lo part enters on kernel rows 11..32 only, as in the other FP16
-// split sr = 2 forward.
+// which stays in L2, and each serves BR x BC products.
+// FP16 split: the staged x tile is binary16 with a power-of-two scale, the PSF
+// parts carry one per frame, and the epilogue removes both scales exactly; the
+// PSF's lo part enters on kernel rows 11..32 only, as in the other FP16 split
+// sr = 2 forward.  BF16 split: the staged tile holds the hi and lo bf16 planes
+// of x, and every kernel row takes x_hi g_hi + x_lo g_hi + x_hi g_lo, as the
+// sr = 2 adjoint of that form does; the two image planes double the register
+// window, so its workgroups cover 16 x 32 frame pixels.
 #include "em_device.h"
 #include "em_internal.h"
 #include "em_mfma_common.h"
@@ -42,7 +46,10 @@ constexpr int64_t M2N_GROUP_FRAGS = (int64_t)M2N_PAIRS * M2N_NF * 64;   // 16-by
 constexpr size_t M2N_GROUP_BYTES = (size_t)M2N_GROUP_FRAGS * 16;
 
 // kernel rows of the 44 x 44 box-extended kernel that take the PSF's lo part
-__host__ __device__ constexpr bool m2n_lo_row(int a) { return a >= 11 && a <= 32; }
+template <int PREC>
+__host__ __device__ constexpr bool m2n_lo_row(int a) {
+  return PREC != EM_FP16_SPLIT || (a >= 11 && a <= 32);
+}
 
 // LDS row pitch (halves): at least `cols`, even, and half of it (the distance
 // in dwords between consecutive latent rows) 20..44 mod 64, so that the two
@@ -54,9 +61,13 @@ __host__ __device__ constexpr int m2n_pitch(int cols) {
 }
 
 // BR output rows x BC blocks of 16 output columns per wave, WR x WC waves.
-template <int BR_, int BC_, int WR_, int WC_>
+template <int BR_, int BC_, int WR_, int WC_, int PREC_ = EM_FP16_SPLIT>
 struct M2N {
-  static constexpr int BR = BR_, BC = BC_, WR = WR_, WC = WC_;
+  static constexpr int BR = BR_, BC = BC_, WR = WR_, WC = WC_, PREC = PREC_;
+  using P = Prec<PREC_>;
+  using frag = typename P::frag;
+  static constexpr int NA = P::NA;                  // image planes
+  static constexpr bool R16 = PREC_ == EM_FP16_SPLIT;   // may write binary16 r planes
   static constexpr int NW = WR * WC, NT = 64 * NW;
   static constexpr int TH = BR * WR, TW = 16 * BC * WC;   // frame pixels per workgroup
   static constexpr int ROWS = 2 * TH + 42;                 // latent rows staged
@@ -74,41 +85,46 @@ struct M2N {
   static constexpr int FS = TH * SP + 8;            // staging frame stride (halves)
 };
 
-// Eight binary16 values of one latent row of the staged tile, starting at an
+// Eight 16-bit values of one latent row of a staged plane, starting at an
 // even column (dword reads: the start is 4-byte aligned only).
-__device__ inline f16x8 m2n_ld8(const unsigned short* __restrict__ sh, int off) {
+template <class F>
+__device__ inline F m2n_ld8(const unsigned short* __restrict__ sh, int off) {
   const uint32_t* p = reinterpret_cast<const uint32_t*>(sh + off);
   uint4 v;
   v.x = p[0];
   v.y = p[1];
   v.z = p[2];
   v.w = p[3];
-  return __builtin_bit_cast(f16x8, v);
+  return __builtin_bit_cast(F, v);
 }
 
-__device__ inline f16x8 m2n_ldB(const f16x8* __restrict__ tab, int p, int f) {
+template <class F>
+__device__ inline F m2n_ldB(const F* __restrict__ tab, int p, int f) {
   return tab[(p * M2N_NF + f) * 64];
 }
 
 template <class C, bool ROB>
 __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int group) {
-  __shared__ __align__(16) unsigned short sh[1][C::ROWS * C::PITCH];
+  using F = typename C::frag;
+  constexpr bool STG = !ROB && C::R16;   // binary16 r planes possible
+  __shared__ __align__(16) unsigned short sh[C::NA][C::ROWS * C::PITCH];
   __shared__ double red[C::NW];
   __shared__ float redf[C::NW];
-  __shared__ __align__(16) std::conditional_t<ROB, unsigned short[8],
-                                              unsigned short[M2N_FPG * C::FS]> stg;
+  __shared__ __align__(16) std::conditional_t<STG, unsigned short[M2N_FPG * C::FS],
+                                              unsigned short[8]> stg;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wr = w / C::WC, wc = w % C::WC;
   const int tiles_x = (a.W + C::TW - 1) / C::TW;     // a.H, a.W: frame grid
   const int tx = tile % tiles_x, ty = tile / tiles_x;
   const int I0 = ty * C::TH, J0 = tx * C::TW;
   const int t0 = group * M2N_FPG;
-  const int sx = stage_tile<EM_FP16_SPLIT, C::ROWS, C::COLS, C::PITCH, C::NT>(
+  const int sx = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
       a.in, 2 * a.H, 2 * a.W, 2 * I0 - 21, 2 * J0 - 21, sh, redf);
   __syncthreads();
 
   const int i = lane & 15, gq = lane >> 4;
   const unsigned short* base = &sh[0][0];
+  constexpr int PLANE = C::ROWS * C::PITCH;
   // tile row of latent row 2 (I0 + wr BR) - 21 (pair 0 of the wave's row 0) and
   // tile column of this lane's output column in block 0, times 2
   const int row0 = 2 * wr * C::BR;
@@ -117,10 +133,10 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
   const int off_f0 = row0 * C::PITCH + col0 + 8 * gq;
   const int off_f1 = off_f0 + C::PITCH;
   const int off_t = (row0 + (gq >> 1)) * C::PITCH + col0 + 32 + 8 * (gq & 1);
-  const f16x8* tab = reinterpret_cast<const f16x8*>(a.tab) + (int64_t)group * M2N_GROUP_FRAGS + lane;
+  const F* tab = reinterpret_cast<const F*>(a.tab) + (int64_t)group * M2N_GROUP_FRAGS + lane;
 
   constexpr int NS = C::BR + 1;   // window slots
-  f16x8 F0[NS][C::BC], F1[NS][C::BC], FT[NS][C::BC];
+  F F0[NS][C::BC][C::NA], F1[NS][C::BC][C::NA], FT[NS][C::BC][C::NA];
   f32x4 acc[C::BR][C::BC];
 #pragma unroll
   for (int b = 0; b < C::BR; ++b)
@@ -129,54 +145,62 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
 #pragma unroll
   for (int q = 0; q < C::BR; ++q)
 #pragma unroll
-    for (int c = 0; c < C::BC; ++c) {
-      F0[q][c] = m2n_ld8(base, off_f0 + 2 * q * C::PITCH + 32 * c);
-      F1[q][c] = m2n_ld8(base, off_f1 + 2 * q * C::PITCH + 32 * c);
-      FT[q][c] = m2n_ld8(base, off_t + 2 * q * C::PITCH + 32 * c);
-    }
-  f16x8 G[M2N_NF], Gn[M2N_NF];
+    for (int c = 0; c < C::BC; ++c)
 #pragma unroll
-  for (int f = 0; f < M2N_NF; ++f) G[f] = m2n_ldB(tab, 0, f);
+      for (int pa = 0; pa < C::NA; ++pa) {
+        F0[q][c][pa] = m2n_ld8<F>(base + pa * PLANE, off_f0 + 2 * q * C::PITCH + 32 * c);
+        F1[q][c][pa] = m2n_ld8<F>(base + pa * PLANE, off_f1 + 2 * q * C::PITCH + 32 * c);
+        FT[q][c][pa] = m2n_ld8<F>(base + pa * PLANE, off_t + 2 * q * C::PITCH + 32 * c);
+      }
+  F G[M2N_NF], Gn[M2N_NF];
+#pragma unroll
+  for (int f = 0; f < M2N_NF; ++f) G[f] = m2n_ldB<F>(tab, 0, f);
 
 #pragma unroll
   for (int p = 0; p < M2N_PAIRS; ++p) {
-    const bool lo0 = m2n_lo_row(2 * p), lo1 = m2n_lo_row(2 * p + 1);
+    const bool lo0 = m2n_lo_row<C::PREC>(2 * p), lo1 = m2n_lo_row<C::PREC>(2 * p + 1);
     if (p + 1 < M2N_PAIRS) {
       // the window's next pair (used from step p + 1 on) and the next B fragments
       const int q = p + C::BR, s = q % NS;
 #pragma unroll
-      for (int c = 0; c < C::BC; ++c) {
-        F0[s][c] = m2n_ld8(base, off_f0 + 2 * q * C::PITCH + 32 * c);
-        F1[s][c] = m2n_ld8(base, off_f1 + 2 * q * C::PITCH + 32 * c);
-        FT[s][c] = m2n_ld8(base, off_t + 2 * q * C::PITCH + 32 * c);
-      }
-      const bool nlo0 = m2n_lo_row(2 * p + 2), nlo1 = m2n_lo_row(2 * p + 3);
+      for (int c = 0; c < C::BC; ++c)
+#pragma unroll
+        for (int pa = 0; pa < C::NA; ++pa) {
+          F0[s][c][pa] = m2n_ld8<F>(base + pa * PLANE, off_f0 + 2 * q * C::PITCH + 32 * c);
+          F1[s][c][pa] = m2n_ld8<F>(base + pa * PLANE, off_f1 + 2 * q * C::PITCH + 32 * c);
+          FT[s][c][pa] = m2n_ld8<F>(base + pa * PLANE, off_t + 2 * q * C::PITCH + 32 * c);
+        }
+      const bool nlo0 = m2n_lo_row<C::PREC>(2 * p + 2), nlo1 = m2n_lo_row<C::PREC>(2 * p + 3);
 #pragma unroll
       for (int f = 0; f < M2N_NF; ++f) {
         const bool need = (f & 1) == 0 || (f == 1 && nlo0) || (f == 3 && nlo1) ||
                           (f == 5 && (nlo0 || nlo1));
-        if (need) Gn[f] = m2n_ldB(tab, p + 1, f);
+        if (need) Gn[f] = m2n_ldB<F>(tab, p + 1, f);
       }
     }
     // keep these loads ahead of this step's products (the scheduler would
     // otherwise sink them next to their first use, exposing their latency)
     __builtin_amdgcn_sched_barrier(0);
-    // products of pair p; consecutive products write different accumulators
+    // products of pair p; consecutive products write different accumulators.
+    // kind % 3 is the chunk (row 2p, row 2p + 1, tail); FP16 split: kinds 0-2
+    // x g_hi, 3-5 x g_lo; BF16 split: 0-2 x_hi g_hi, 3-5 x_lo g_hi, 6-8 x_hi g_lo
+    constexpr int NKIND = C::NA == 2 ? 9 : 6;
 #pragma unroll
-    for (int kind = 0; kind < 6; ++kind) {
-      // 0, 1, 2: hi part of the chunks (row 2p, row 2p + 1, tail); 3, 4, 5: lo parts
-      if (kind == 3 && !lo0) continue;
-      if (kind == 4 && !lo1) continue;
-      if (kind == 5 && !(lo0 || lo1)) continue;
+    for (int kind = 0; kind < NKIND; ++kind) {
       const int ch = kind % 3;
-      const int f = 2 * ch + (kind >= 3 ? 1 : 0);
+      const bool glo = kind >= (C::NA == 2 ? 6 : 3);
+      const int pa = (C::NA == 2 && kind >= 3 && kind < 6) ? 1 : 0;
+      if (glo && ch == 0 && !lo0) continue;
+      if (glo && ch == 1 && !lo1) continue;
+      if (glo && ch == 2 && !(lo0 || lo1)) continue;
+      const int f = 2 * ch + (glo ? 1 : 0);
 #pragma unroll
       for (int b = 0; b < C::BR; ++b) {
         const int s = (b + p) % NS;
 #pragma unroll
         for (int c = 0; c < C::BC; ++c) {
-          const f16x8& A = ch == 0 ? F0[s][c] : (ch == 1 ? F1[s][c] : FT[s][c]);
-          acc[b][c] = __builtin_amdgcn_mfma_f32_16x16x32_f16(A, G[f], acc[b][c], 0, 0, 0);
+          const F& A = ch == 0 ? F0[s][c][pa] : (ch == 1 ? F1[s][c][pa] : FT[s][c][pa]);
+          acc[b][c] = C::P::mma(A, G[f], acc[b][c]);
         }
       }
     }
@@ -203,7 +227,7 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
   float* oyt = ROB ? a.out_y + (int64_t)tc * N : nullptr;
   // binary16 r planes (the Gaussian iteration): 2^e16[t] u m at plane pixel
   // (I + 11, J + 11) instead of r, through the staging tile
-  const bool to16 = !ROB && a.r16 != nullptr;     // uniform over the workgroup
+  const bool to16 = STG && a.r16 != nullptr;     // uniform over the workgroup
   const int e16 = to16 ? a.e16[tc] : 0;
   const bool want_ll = a.part != nullptr;
   const float nu = a.nu, nu1 = a.nu + 1.f;
@@ -269,7 +293,7 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
         }
       }
       const int64_t o = (int64_t)I * a.W + Jb;
-      if constexpr (!ROB) {
+      if constexpr (STG) {
         if (to16) {
           unsigned short* srow =
               &stg[(lane & 15) * C::FS + (I - I0) * C::SP + C::S0 + (Jb - J0)];
@@ -292,7 +316,7 @@ __device__ inline void m2n_body(const MfmaLaunch& a, const int tile, const int g
       }
     }
   }
-  if constexpr (!ROB) {
+  if constexpr (STG) {
     if (to16) {
       __syncthreads();
       constexpr int SLOTS = C::NRUN + 1;   // per frame row: the runs, then lead and tail
@@ -354,9 +378,11 @@ __global__ __launch_bounds__(C::NT) void m2n_batched(const MfmaLaunch* __restric
 // Table of one frame group (one block per group and pair): fragment
 // [group][p][f][lane], f = 2 ch + s for chunk ch (0: taps 0..31 of row 2p,
 // 1: of row 2p + 1, 2: taps 32..47 of rows 2p (k < 16) and 2p + 1 (k >= 16)) and
-// part s (0 hi, 1 lo; lo is zero on rows outside 11..32); lane j + 16 gq holds
-// B[8 gq + e][j] of frame 16 group + j (zero beyond n).  After all groups: the
-// n frames' scale exponents (f16_scale_exp of the largest |k_t|).
+// part s (0 hi, 1 lo; FP16 split: lo is zero on rows outside 11..32); lane
+// j + 16 gq holds B[8 gq + e][j] of frame 16 group + j (zero beyond n).  After
+// all groups: the n frames' scale exponents (FP16 split: f16_scale_exp of the
+// largest |k_t|; BF16 split: 0, no scale).
+template <int PREC>
 __global__ __launch_bounds__(384) void m2n_table_kernel(const float* psf, int n, int K,
                                                        unsigned short* tab) {
   __shared__ int sexp[M2N_FPG];
@@ -381,7 +407,7 @@ __global__ __launch_bounds__(384) void m2n_table_kernel(const float* psf, int n,
       for (int e = lane; e < 44 * 44; e += 64) mx = fmaxf(mx, fabsf(kk(t, e / 44, e % 44)));
     mx = wave_max(mx);
     if (lane == 0) {
-      sexp[j] = f16_scale_exp(mx);
+      sexp[j] = PREC == EM_FP16_SPLIT ? f16_scale_exp(mx) : 0;
       if (t < n && p == 0)
         reinterpret_cast<int*>(reinterpret_cast<char*>(tab) +
                                (size_t)((n + M2N_FPG - 1) / M2N_FPG) * M2N_GROUP_BYTES)[t] =
@@ -406,20 +432,29 @@ __global__ __launch_bounds__(384) void m2n_table_kernel(const float* psf, int n,
     }
     float gv = 0.f;
     if (t < n && b < 44) gv = kk(t, 43 - a, 43 - b);
-    unsigned short v = table_part<EM_FP16_SPLIT>(ldexpf(gv, sexp[j]), s);
-    if (s == 1 && !m2n_lo_row(a)) v = 0;
+    unsigned short v = table_part<PREC>(ldexpf(gv, sexp[j]), s);
+    if (s == 1 && !m2n_lo_row<PREC>(a)) v = 0;
     dst[e] = v;
   }
 }
 
-// variants: 0: 8 waves (2 x 4) of 8 rows x 1 block; 1: 8 waves (4 x 2) of 4 rows
-// x 2 blocks; 2: 8 waves (8 x 1) of 2 rows x 4 blocks.  Every variant covers
-// 16 x 64 frame pixels.
+// FP16 split variants: 0: 8 waves (2 x 4) of 8 rows x 1 block; 1: 8 waves
+// (4 x 2) of 4 rows x 2 blocks; 2: 8 waves (8 x 1) of 2 rows x 4 blocks, each
+// covering 16 x 64 frame pixels.  BF16 split (two image planes in the window):
+// 0 and 2: 8 waves (4 x 2) of 4 rows x 1 block; 1: 8 waves (8 x 1) of 2 rows x
+// 2 blocks, each covering 16 x 32 frame pixels (a third shape within the
+// register budget of 8-wave workgroups would leave one output row per wave).
 using N0 = M2N<8, 1, 2, 4>;
 using N1 = M2N<4, 2, 4, 2>;
 using N2 = M2N<2, 4, 8, 1>;
-static_assert(N0::TH == M2N_TH && N0::TW == M2N_TW && N1::TH == M2N_TH && N1::TW == M2N_TW &&
-                  N2::TH == M2N_TH && N2::TW == M2N_TW,
+using NB0 = M2N<4, 1, 4, 2, EM_BF16_SPLIT>;
+using NB1 = M2N<2, 2, 8, 1, EM_BF16_SPLIT>;
+template <class C>
+constexpr bool m2n_tile_ok() {
+  return C::TH == M2N_TH && C::TW == m2n_tile_w(C::PREC);
+}
+static_assert(m2n_tile_ok<N0>() && m2n_tile_ok<N1>() && m2n_tile_ok<N2>() &&
+                  m2n_tile_ok<NB0>() && m2n_tile_ok<NB1>(),
               "tile");
 
 }  // namespace
@@ -429,15 +464,23 @@ size_t mfma2n_table_bytes(int n) {
 }
 
 hipError_t launch_mfma2n_table(const Geometry& g, const float* psf, void* tab, hipStream_t s) {
-  hipLaunchKernelGGL(m2n_table_kernel, dim3((g.n + M2N_FPG - 1) / M2N_FPG, M2N_PAIRS),
-                     dim3(384), 0, s, psf, g.n, g.K, static_cast<unsigned short*>(tab));
+  const dim3 grid((g.n + M2N_FPG - 1) / M2N_FPG, M2N_PAIRS);
+  if (g.precision == EM_FP16_SPLIT)
+    hipLaunchKernelGGL(m2n_table_kernel<EM_FP16_SPLIT>, grid, dim3(384), 0, s, psf, g.n, g.K,
+                       static_cast<unsigned short*>(tab));
+  else if (g.precision == EM_BF16_SPLIT)
+    hipLaunchKernelGGL(m2n_table_kernel<EM_BF16_SPLIT>, grid, dim3(384), 0, s, psf, g.n, g.K,
+                       static_cast<unsigned short*>(tab));
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
 bool mfma2n_desc_ok(const Geometry& g, int tiles, int groups, const MfmaLaunch& a) {
   return uses_m2n(g) && a.H == g.Hf && a.W == g.Wf && a.fpg == M2N_FPG &&
          (a.r16 == nullptr || (a.out == nullptr && a.out_y == nullptr)) &&
-         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2N_TH, M2N_TW);
+         launch_grid_ok(tiles, groups, a.ntiles, a.n, a.fpg, a.H, a.W, M2N_TH,
+                        m2n_tile_w(g.precision));
 }
 
 hipError_t launch_mfma2n(const Geometry& g, int variant, int tiles, int groups,
@@ -445,6 +488,16 @@ hipError_t launch_mfma2n(const Geometry& g, int variant, int tiles, int groups,
   if (!mfma2n_desc_ok(g, tiles, groups, a)) return hipErrorInvalidValue;
   const dim3 grid(tiles, groups);
   const bool rob = a.out_y != nullptr;
+  if (g.precision == EM_BF16_SPLIT) {
+    if (variant == 1) {
+      if (rob) hipLaunchKernelGGL(m2n_t_kernel<NB1>, grid, dim3(NB1::NT), 0, s, a);
+      else hipLaunchKernelGGL(m2n_kernel<NB1>, grid, dim3(NB1::NT), 0, s, a);
+    } else {
+      if (rob) hipLaunchKernelGGL(m2n_t_kernel<NB0>, grid, dim3(NB0::NT), 0, s, a);
+      else hipLaunchKernelGGL(m2n_kernel<NB0>, grid, dim3(NB0::NT), 0, s, a);
+    }
+    return hipGetLastError();
+  }
   if (variant == 1) {
     if (rob) hipLaunchKernelGGL(m2n_t_kernel<N1>, grid, dim3(N1::NT), 0, s, a);
     else hipLaunchKernelGGL(m2n_kernel<N1>, grid, dim3(N1::NT), 0, s, a);
@@ -458,9 +511,21 @@ hipError_t launch_mfma2n(const Geometry& g, int variant, int tiles, int groups,
   return hipGetLastError();
 }
 
-hipError_t launch_mfma2n_batched(int variant, const MfmaLaunch* descs, const int4* items,
-                                 int n_items, int grid, hipStream_t s, bool robust) {
+hipError_t launch_mfma2n_batched(int precision, int variant, const MfmaLaunch* descs,
+                                 const int4* items, int n_items, int grid, hipStream_t s,
+                                 bool robust) {
   if (n_items <= 0) return hipSuccess;
+  if (precision == EM_BF16_SPLIT) {
+    if (variant == 1) {
+      if (robust) hipLaunchKernelGGL((m2n_batched<NB1, true>), dim3(grid), dim3(NB1::NT), 0, s, descs, items, n_items);
+      else hipLaunchKernelGGL((m2n_batched<NB1, false>), dim3(grid), dim3(NB1::NT), 0, s, descs, items, n_items);
+    } else {
+      if (robust) hipLaunchKernelGGL((m2n_batched<NB0, true>), dim3(grid), dim3(NB0::NT), 0, s, descs, items, n_items);
+      else hipLaunchKernelGGL((m2n_batched<NB0, false>), dim3(grid), dim3(NB0::NT), 0, s, descs, items, n_items);
+    }
+    return hipGetLastError();
+  }
+  if (precision != EM_FP16_SPLIT) return hipErrorInvalidValue;
   if (variant == 1) {
     if (robust) hipLaunchKernelGGL((m2n_batched<N1, true>), dim3(grid), dim3(N1::NT), 0, s, descs, items, n_items);
     else hipLaunchKernelGGL((m2n_batched<N1, false>), dim3(grid), dim3(N1::NT), 0, s, descs, items, n_items);

@@ -38,6 +38,7 @@ def _jobs():
         ("c3", 96, 80, 2, 1, em.BF16_SPLIT, 4, 2.5),
         ("c4", 96, 144, 12, 2, em.FP16_SPLIT, 5, 0.0),    # sr = 2, frames in N
         ("c4", 64, 96, 9, 2, em.FP16_SPLIT, 4, 3.0),
+        ("c4", 80, 112, 10, 2, em.BF16_SPLIT, 5, 0.0),    # BF16 split, frames in N
     ]
     out = []
     for k, (rec, H, W, n, sr, prec, it, nu) in enumerate(specs):
