@@ -334,6 +334,11 @@ __device__ inline void m2a_class(const unsigned short (*sh)[C::ROWS * C::PITCH],
                                  int col_base, f32x4 (&acc)[2][C::BR][C::BC]) {
   const int lane = threadIdx.x & 63;
   const int i = lane & 15, g = lane >> 4;
+  // two-plane forms with 4-wave workgroups: the wave issuing products runs at
+  // raised priority (c4 BF16 split adjoint 0.79 -> 0.73 ms; the 8-wave variant
+  // loses with it)
+  constexpr bool PRIO = C::NA == 2 && C::NW == 4;
+  if constexpr (PRIO) __builtin_amdgcn_s_setprio(1);
 #pragma unroll
   for (int rho = 0; rho < C::BR + 1; ++rho) {
     // skip fragment rows no (parity, tap) pair of this class uses
@@ -374,6 +379,7 @@ __device__ inline void m2a_class(const unsigned short (*sh)[C::ROWS * C::PITCH],
                 C::P::mma(A[gam][C::P::pa(s)], T[q][m][C::P::pb(s)], acc[q][beta][gam]);
           }
   }
+  if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 }
 
 // Classes R .. 15 with the next class's Toeplitz fragments fetched early.
