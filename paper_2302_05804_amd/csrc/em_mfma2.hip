@@ -479,7 +479,9 @@ __device__ inline void m2a_body(const MfmaLaunch& a, const int tile, const int g
   if constexpr (C::PFT == 2) m2a_issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
-    const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
+    // one pixel pair at a time: batched loads made two of the three BF16 split
+    // variants 45% slower here
+    const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT, 0>(
         a.in + (int64_t)t * Nf, Hf, Wf, K0 / 2 - 11, L0 / 2 - 11, sh, redf);
     if constexpr (C::PFT == 2) frags_landed();
     else __syncthreads();

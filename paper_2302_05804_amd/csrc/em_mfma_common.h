@@ -150,8 +150,10 @@ __device__ inline float wave_max(float v) {
 // outside [0,H) x [0,W)) into the LDS planes of encoding PREC, row pitch PITCH.
 // Returns the tile's scale exponent (0 for unscaled encodings); every thread of
 // the block gets the same value.  For scaled encodings the whole block must
-// call it (one barrier inside); `redf` holds NT/64 floats of LDS.
-template <int PREC, int ROWS, int COLS, int PITCH, int NT>
+// call it (one barrier inside); `redf` holds NT/64 floats of LDS.  Unscaled
+// encodings load SB pixel pairs per thread at a time (SB = 0: one pair, stored
+// before the next is loaded).
+template <int PREC, int ROWS, int COLS, int PITCH, int NT, int SB = 8>
 __device__ inline int stage_tile(const float* __restrict__ src, int H, int W, int r0, int q0,
                                  unsigned short (*sh)[ROWS * PITCH], float* redf) {
   constexpr int HALF = COLS / 2;
@@ -168,7 +170,7 @@ __device__ inline int stage_tile(const float* __restrict__ src, int H, int W, in
     }
     return row * PITCH + 2 * cp;
   };
-  if constexpr (!Prec<PREC>::SCALED) {
+  if constexpr (!Prec<PREC>::SCALED && SB == 0) {
     for (int e = threadIdx.x; e < NE; e += NT) {
       float v0, v1;
       const int o = load2(e, v0, v1);
@@ -178,6 +180,42 @@ __device__ inline int stage_tile(const float* __restrict__ src, int H, int W, in
       *reinterpret_cast<unsigned int*>(&sh[0][o]) = (unsigned int)h0 | ((unsigned int)h1 << 16);
       if constexpr (Prec<PREC>::NA == 2)
         *reinterpret_cast<unsigned int*>(&sh[1][o]) = (unsigned int)l0 | ((unsigned int)l1 << 16);
+    }
+    return 0;
+  } else if constexpr (!Prec<PREC>::SCALED) {
+    // batches of SB pixel pairs per thread: the batch's loads read clamped
+    // addresses inside the image (values outside it replaced by 0), so they
+    // carry no branches and are in flight together, one wait per batch
+    constexpr int NPT = (NE + NT - 1) / NT;
+#pragma unroll
+    for (int k0 = 0; k0 < NPT; k0 += SB) {
+      float v[SB][2];
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int e = threadIdx.x + (k0 + k) * NT;
+        const int row = e / HALF, cp = e - row * HALF;
+        const int gy = r0 + row, gx = q0 + 2 * cp;
+        const bool iny = e < NE && gy >= 0 && gy < H;
+        const float* rp = src + (int64_t)min(max(gy, 0), H - 1) * W;
+        const float a0 = rp[min(max(gx, 0), W - 1)];
+        const float a1 = rp[min(max(gx + 1, 0), W - 1)];
+        v[k][0] = (iny && gx >= 0 && gx < W) ? a0 : 0.f;
+        v[k][1] = (iny && gx + 1 >= 0 && gx + 1 < W) ? a1 : 0.f;
+      }
+#pragma unroll
+      for (int k = 0; k < SB; ++k) {
+        const int e = threadIdx.x + (k0 + k) * NT;
+        if (e < NE) {
+          const int row = e / HALF, cp = e - row * HALF;
+          const int o = row * PITCH + 2 * cp;
+          unsigned short h0, l0, h1, l1;
+          split_bf16(v[k][0], h0, l0);
+          split_bf16(v[k][1], h1, l1);
+          *reinterpret_cast<unsigned int*>(&sh[0][o]) = (unsigned int)h0 | ((unsigned int)h1 << 16);
+          if constexpr (Prec<PREC>::NA == 2)
+            *reinterpret_cast<unsigned int*>(&sh[1][o]) = (unsigned int)l0 | ((unsigned int)l1 << 16);
+        }
+      }
     }
     return 0;
   } else {
