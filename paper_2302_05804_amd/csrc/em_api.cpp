@@ -156,13 +156,14 @@ Plan make_serving_plan(const Geometry& g) {
   pl.max_partials = std::max(pl.fwd_tiles * pl.fwd_groups, std::max(pl.adj_tiles, pl.upd_blocks));
   if (uses_mfma(g)) {
     // the variants em_autotune picks on the large workloads (33 x 4096^2 sr = 1,
-    // 16 x 2048^2 sr = 2) for each encoding (the sr = 2 forward of jobs with its
-    // frames in the N dimension: 4 rows x 2 blocks per wave in the FP16 split
-    // form, 4 rows x 1 block in the BF16 split form); for the sr = 2 FP16 adjoint
-    // the 4x2-block variant, 3% slower alone but free of scratch reloads in its
-    // batched form
+    // 16 x 2048^2 sr = 2) for each encoding (the sr = 1 FP16 forward: 4x2 blocks
+    // per wave with the image fragments loaded ahead; the sr = 2 forward of jobs
+    // with its frames in the N dimension: 4 rows x 2 blocks per wave in the FP16
+    // split form, 4 rows x 1 block in the BF16 split form); for the sr = 2 FP16
+    // adjoint the 4x2-block variant, 3% slower alone but free of scratch reloads
+    // in its batched form
     const bool f16 = g.precision == EM_FP16_SPLIT;
-    pl.fwd_variant = g.sr == 1 ? (f16 ? 2 : 0) : (uses_m2n(g) ? (f16 ? 1 : 0) : (f16 ? 2 : 0));
+    pl.fwd_variant = g.sr == 1 ? (f16 ? 1 : 0) : (uses_m2n(g) ? (f16 ? 1 : 0) : (f16 ? 2 : 0));
     pl.adj_variant = g.sr == 1 ? 2 : (f16 ? 1 : 0);
   }
   return pl;
