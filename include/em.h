@@ -77,8 +77,9 @@ extern "C" {
                                other rows take the hi hi product alone       */
 #define EM_FP16_SPLIT  2    /* FP16 MFMA: image operand in binary16 with a
                                power-of-two scale (per staged tile of x; for
-                               the adjoint of an sr = 1 iteration, r written by
-                               the forward in binary16 with a per-frame scale
+                               the adjoint of a Gaussian iteration with sr = 1,
+                               or sr = 2 and 8 or more frames, r written by the
+                               forward in binary16 with a per-frame scale
                                fixed from a bound on u_t F_t x), PSF split into
                                binary16 hi+lo with a power-of-two scale per
                                frame, FP32 accumulation, scales removed exactly
