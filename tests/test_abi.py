@@ -70,3 +70,7 @@ def test_launch_plans_match_their_grids():
     for (h, w), n, prec in itertools.product(sizes[:7], (1, 3, 33),
                                              (em.FP32, em.BF16_SPLIT, em.FP16_SPLIT)):
         em.check_plan(em.Problem.make(n, h, w, 43, precision=prec, weight_mode=em.W_LITERAL))
+    # Student-t noise (its forward writes u w m and u w y, no binary16 r planes)
+    for (h, w), n, sr, prec in itertools.product(sizes[:8], (3, 16), (1, 2),
+                                                 (em.FP32, em.BF16_SPLIT, em.FP16_SPLIT)):
+        em.check_plan(em.Problem.make(n, h, w, 43, sr=sr, precision=prec, nu=4.0))
