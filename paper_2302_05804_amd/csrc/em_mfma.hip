@@ -162,12 +162,20 @@ __device__ inline void mfma_class(int r, const unsigned short (*sh)[C::ROWS * C:
   if constexpr (PRIO) __builtin_amdgcn_s_setprio(0);
 }
 
+// No prefetch of the next frame's tile (the default hook of mfma_frame).
+struct NoTilePf {
+  __device__ void issue() {}
+};
+
 // All kernel rows of one frame; the Toeplitz fragments of the next class are
-// fetched while the current class runs.
-template <class C>
-__device__ inline void mfma_frame(const unsigned short (*sh)[C::ROWS * C::PITCH],
-                                  const typename C::frag* __restrict__ tab_t, int row_base,
-                                  int col_base, f32x4 (&acc)[C::BR][C::BC]) {
+// fetched while the current class runs.  With use_pf, pf.issue() runs after
+// class 0's fragment loads and before class 1's, so class 0's products cover
+// the latency of its loads.
+template <class C, class PF>
+__device__ __attribute__((always_inline)) inline void mfma_frame(
+    const unsigned short (*sh)[C::ROWS * C::PITCH],
+    const typename C::frag* __restrict__ tab_t, int row_base, int col_base,
+    f32x4 (&acc)[C::BR][C::BC], PF& pf, bool use_pf) {
   // classes with MMAX members first, then MMAX-1 (KT = 43: r <= 10 -> 3, r >= 11 -> 2;
   // KT = 15: r <= 14 -> 1)
   constexpr int RFULL = C::KT - 16 * (C::MMAX - 1);
@@ -176,7 +184,9 @@ __device__ inline void mfma_frame(const unsigned short (*sh)[C::ROWS * C::PITCH]
   if (C::PFT) {
     typename C::frag Tn[C::MMAX][2][C::NB];
     load_T<C>(Tc, tab_t, 0);
+    if (use_pf) pf.issue();
     int r = 0;
+#pragma unroll 1
     for (; r < RFULL; ++r) {
       if (r + 1 < RLAST) load_T<C>(Tn, tab_t, r + 1);
       mfma_class<C, C::MMAX>(r, sh, Tc, row_base, col_base, acc);
@@ -188,6 +198,7 @@ __device__ inline void mfma_frame(const unsigned short (*sh)[C::ROWS * C::PITCH]
           for (int q = 0; q < C::NB; ++q) Tc[m][h][q] = Tn[m][h][q];
     }
     if constexpr (C::MMAX > 1) {
+#pragma unroll 1
       for (; r < RLAST; ++r) {
         if (r + 1 < RLAST) load_T<C>(Tn, tab_t, r + 1);
         mfma_class<C, C::MMAX - 1>(r, sh, Tc, row_base, col_base, acc);
@@ -346,6 +357,7 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
 
   const int64_t N = (int64_t)a.H * a.W;
   double llp = 0.0;
+  NoTilePf no_pf;
   for (int t = t0; t < t1; ++t) {
     // The staged tile does not change between frames; this fence keeps the
     // compiler from hoisting every fragment read of the tile out of the frame
@@ -362,7 +374,7 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
       mfma_frame_lds<C, R16>(sh, tab_t, t + 1 < t1 ? tab_t + TSTRIDE : nullptr, tl, step,
                              row_base, col_base, acc, up);
     else
-      mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
+      mfma_frame<C>(sh, tab_t, row_base, col_base, acc, no_pf, false);
     // exact removal of the image and PSF scales (scaled encodings)
     const int unscale = C::P::SCALED ? -(sx + table_exponents<C>(a)[t]) : 0;
     // epilogue: per-frame base pointers (wave-uniform) + 32-bit in-frame offsets
@@ -402,6 +414,65 @@ __device__ inline void mfma_fwd_body(const MfmaLaunch& a, const int tile, const 
 }
 
 
+// The next frame's r tile for the unscaled encodings (BF16 split, BF16) of the
+// adjoint with register-held Toeplitz fragments: the first NPF pixel pairs per
+// thread are loaded into registers during the current frame's first tap class;
+// once every wave is done with the current frame, the rest are loaded in one
+// batch and all are split and stored into the LDS planes.  Loads read clamped
+// addresses inside the image; values outside it are replaced by 0, as in
+// stage_tile.
+template <class C>
+struct TilePf {
+  static constexpr int HALF = C::COLS / 2, NE = C::ROWS * HALF;
+  static constexpr int NPT = (NE + C::NT - 1) / C::NT;   // pixel pairs per thread
+  static constexpr int NPF = NPT < 16 ? NPT : 16;        // pairs prefetched
+  const float* src;
+  int H, W, r0, q0;
+  float v[NPT][2];   // raw values (clamped reads), masked when stored
+  // tile position of pair k; the opaque copy keeps the compiler from hoisting
+  // every pair's address arithmetic out of the frame loop into registers
+  __device__ void pos(int k, int& e, int& gy, int& gx) const {
+    int kk = k * C::NT;
+    __asm__ volatile("" : "+v"(kk));
+    e = threadIdx.x + kk;
+    const int row = e / HALF, cp = e - row * HALF;
+    gy = r0 + row;
+    gx = q0 + 2 * cp;
+  }
+  __device__ void load(int k) {
+    int e, gy, gx;
+    pos(k, e, gy, gx);
+    const float* rp = src + (int64_t)min(max(gy, 0), H - 1) * W;
+    v[k][0] = rp[min(max(gx, 0), W - 1)];
+    v[k][1] = rp[min(max(gx + 1, 0), W - 1)];
+  }
+  __device__ void issue() {
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) load(k);
+  }
+  __device__ void store(unsigned short (*sh)[C::ROWS * C::PITCH]) {
+#pragma unroll
+    for (int k = NPF; k < NPT; ++k) load(k);
+#pragma unroll
+    for (int k = 0; k < NPT; ++k) {
+      int e, gy, gx;
+      pos(k, e, gy, gx);
+      if (e < NE) {
+        const bool iny = gy >= 0 && gy < H;
+        const float v0 = (iny && gx >= 0 && gx < W) ? v[k][0] : 0.f;
+        const float v1 = (iny && gx + 1 >= 0 && gx + 1 < W) ? v[k][1] : 0.f;
+        const int o = (e / HALF) * C::PITCH + 2 * (e - (e / HALF) * HALF);
+        unsigned short h0, l0, h1, l1;
+        split_bf16(v0, h0, l0);
+        split_bf16(v1, h1, l1);
+        *reinterpret_cast<unsigned int*>(&sh[0][o]) = (unsigned int)h0 | ((unsigned int)h1 << 16);
+        if constexpr (C::NA == 2)
+          *reinterpret_cast<unsigned int*>(&sh[1][o]) = (unsigned int)l0 | ((unsigned int)l1 << 16);
+      }
+    }
+  }
+};
+
 // Adjoint: sum over the frames of this group of F_t^T r_t; the r_t tile is
 // staged per frame.  Epilogue: partial plane, or the fused update of Eq. (2).
 template <class C>
@@ -429,11 +500,28 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
   constexpr int64_t TSTRIDE = (int64_t)C::KTP * 4 * 64;   // fragments per frame
   __shared__ __align__(16) TBufDecl<C> tl;
   int step = 0;
+  // unscaled encodings, register-held fragments, 8 waves: the next frame's tile
+  // is prefetched during the current frame's classes (the 4-wave variant would
+  // need twice the registers per thread)
+  constexpr bool PF = C::PFT == 1 && !C::P::SCALED && C::NW == 8;
+  std::conditional_t<PF, TilePf<C>, NoTilePf> pf;
+  NoTilePf no_pf;
+  if constexpr (PF) {
+    pf.src = nullptr;
+    pf.H = a.H;
+    pf.W = a.W;
+    pf.r0 = k0 - c;
+    pf.q0 = l0 - c;
+  }
   if constexpr (C::PFT == 2) issue_T<C>(tab + t0 * TSTRIDE, 0, (void*)&tl[0][0][0]);
   for (int t = t0; t < t1; ++t) {
     __syncthreads();
-    const int sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
-        a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh, redf);
+    int sr_t = 0;
+    if (!PF || t == t0)
+      sr_t = stage_tile<C::PREC, C::ROWS, C::COLS, C::PITCH, C::NT>(
+          a.in + (int64_t)t * N, a.H, a.W, k0 - c, l0 - c, sh, redf);
+    else if constexpr (PF)
+      pf.store(sh);
     if constexpr (C::PFT == 2) frags_landed();
     else __syncthreads();
     const typename C::frag* tab_t = tab + t * TSTRIDE;
@@ -449,7 +537,7 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
       if constexpr (C::PFT == 2)
         mfma_frame_lds<C>(sh, tab_t, tab_next, tl, step, row_base, col_base, accf);
       else
-        mfma_frame<C>(sh, tab_t, row_base, col_base, accf);
+        mfma_frame<C>(sh, tab_t, row_base, col_base, accf, no_pf, false);
       const int unscale = -(sr_t + table_exponents<C>(a)[t]);
 #pragma unroll
       for (int b = 0; b < C::BR; ++b)
@@ -459,10 +547,14 @@ __device__ inline void mfma_adj_body(const MfmaLaunch& a, const int tile, const 
           for (int v = 0; v < 4; ++v) acc[b][q][v] += ldexpf(accf[b][q][v], unscale);
     } else {
       (void)sr_t;
-      if constexpr (C::PFT == 2)
+      if constexpr (C::PFT == 2) {
         mfma_frame_lds<C>(sh, tab_t, tab_next, tl, step, row_base, col_base, acc);
-      else
-        mfma_frame<C>(sh, tab_t, row_base, col_base, acc);
+      } else if constexpr (PF) {
+        pf.src = a.in + (int64_t)(t + 1) * N;
+        mfma_frame<C>(sh, tab_t, row_base, col_base, acc, pf, t + 1 < t1);
+      } else {
+        mfma_frame<C>(sh, tab_t, row_base, col_base, acc, no_pf, false);
+      }
     }
   }
 
