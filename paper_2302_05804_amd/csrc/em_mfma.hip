@@ -1130,11 +1130,30 @@ __global__ __launch_bounds__(1024) void r16_frame_stats_kernel(const float* u, i
 }
 
 // Block maxima of x (R16_XBLOCKS blocks, grid-stride).
+// Largest |x[i]| over this thread's share of a grid-stride pass: 16-byte loads,
+// four in flight per thread, when x is 16-byte aligned.
+__device__ inline float abs_max_share(const float* __restrict__ x, int64_t Nl) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  float m = 0.f;
+  int64_t done = 0;
+  if ((reinterpret_cast<uintptr_t>(x) & 15) == 0) {
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const int64_t n4 = Nl >> 2;
+#pragma unroll 4
+    for (int64_t i = tid; i < n4; i += stride) {
+      const float4 v = x4[i];
+      m = fmaxf(m, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+    }
+    done = n4 << 2;
+  }
+  for (int64_t i = done + tid; i < Nl; i += stride) m = fmaxf(m, fabsf(x[i]));
+  return m;
+}
+
 __global__ __launch_bounds__(256) void r16_xmax_kernel(const float* x, int64_t Nl, float* part) {
   __shared__ float red[4];
-  float m = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < Nl; i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, fabsf(x[i]));
+  float m = abs_max_share(x, Nl);
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
@@ -1163,10 +1182,7 @@ __global__ __launch_bounds__(256) void r16_scale_kernel(const float* part, int n
 __global__ __launch_bounds__(256) void r16_xmax_batched_kernel(const R16Job* jobs) {
   __shared__ float red[4];
   const R16Job j = jobs[blockIdx.y];
-  float m = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < j.Nl;
-       i += (int64_t)gridDim.x * 256)
-    m = fmaxf(m, fabsf(j.x[i]));
+  float m = abs_max_share(j.x, j.Nl);
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
   __syncthreads();
